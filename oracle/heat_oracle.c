@@ -128,9 +128,12 @@ int orc_pcg(const orc_grid *g, const double *alpha, double dt, const double *dg,
     double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
     double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
     orc_apply_A(g, alpha, dt, x, q);
-    for (long long i = 0; i < n; ++i) r[i] = b[i] - q[i];
-    for (long long i = 0; i < n; ++i) z[i] = r[i] / dg[i];
-    for (long long i = 0; i < n; ++i) p[i] = z[i];
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < n; ++i) {
+        r[i] = b[i] - q[i];
+        z[i] = r[i] / dg[i];
+        p[i] = z[i];
+    }
     double rz = dot(n, r, z);
     double rr = dot(n, r, r);
     const double bnorm = sqrt(bb);
@@ -139,12 +142,16 @@ int orc_pcg(const orc_grid *g, const double *alpha, double dt, const double *dg,
         if (it == max_iter) { status = -1; break; }
         orc_apply_A(g, alpha, dt, p, q);
         double a = rz / dot(n, p, q);
-        for (long long i = 0; i < n; ++i) x[i] += a * p[i];
-        for (long long i = 0; i < n; ++i) r[i] -= a * q[i];
-        for (long long i = 0; i < n; ++i) z[i] = r[i] / dg[i];
+#pragma omp parallel for schedule(static)
+        for (long long i = 0; i < n; ++i) {
+            x[i] += a * p[i];
+            r[i] -= a * q[i];
+            z[i] = r[i] / dg[i];
+        }
         double rz_new = dot(n, r, z);
         double beta = rz_new / rz;
         rz = rz_new;
+#pragma omp parallel for schedule(static)
         for (long long i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         rr = dot(n, r, r);
         ++it;

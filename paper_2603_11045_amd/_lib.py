@@ -1,0 +1,109 @@
+"""ctypes binding of ``libnefty_heat.so`` (declared in ``include/nefty_heat.h``).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name. Importing this module loads the in-tree library and raises if
+it has not been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnefty_heat.so")
+
+NH_OK = 0
+NH_EINVAL = -1
+NH_ENOMEM = -2
+NH_ESTATE = -3
+NH_ENOCONV = -4
+NH_ENONFINITE = -5
+NH_EHIP = -6
+NH_ETIMEOUT = -7
+
+STATUS_NAMES = {0: "NH_OK", -1: "NH_EINVAL", -2: "NH_ENOMEM", -3: "NH_ESTATE", -4: "NH_ENOCONV",
+                -5: "NH_ENONFINITE", -6: "NH_EHIP", -7: "NH_ETIMEOUT"}
+
+EXPORTED = ["nh_create", "nh_set_grid", "nh_set_solver", "nh_forward", "nh_adjoint",
+            "nh_forward_f64", "nh_adjoint_f64", "nh_get_state", "nh_apply_A", "nh_set_launch",
+            "nh_set_barrier_timeout", "nh_get_stats", "nh_last_error", "nh_destroy", "nh_copy_f32"]
+
+
+class nh_stats(ctypes.Structure):
+    _fields_ = [
+        ("fwd_iters", ctypes.c_longlong),
+        ("adj_iters", ctypes.c_longlong),
+        ("recompute_iters", ctypes.c_longlong),
+        ("fwd_steps", ctypes.c_int),
+        ("adj_steps", ctypes.c_int),
+        ("recompute_steps", ctypes.c_int),
+        ("max_step_iters", ctypes.c_int),
+        ("worst_rel_res", ctypes.c_double),
+        ("bytes_alg_fwd", ctypes.c_double),
+        ("bytes_alg_adj", ctypes.c_double),
+        ("t_fwd_s", ctypes.c_double),
+        ("t_adj_s", ctypes.c_double),
+        ("t_kernel_fwd_s", ctypes.c_double),
+        ("t_kernel_adj_s", ctypes.c_double),
+        ("launches_fwd", ctypes.c_longlong),
+        ("launches_adj", ctypes.c_longlong),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("peak_workspace_bytes", ctypes.c_size_t),
+        ("team_blocks", ctypes.c_int),
+        ("block_threads", ctypes.c_int),
+        ("tile_x", ctypes.c_int),
+        ("tile_y", ctypes.c_int),
+        ("tile_z", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NHError(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__(f"{func}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load the library (once). Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2603_11045_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    st = ctypes.c_int
+    lib.nh_create.argtypes = [ctypes.POINTER(vp), ip, vp]
+    lib.nh_set_grid.argtypes = [vp, ip, ip, ip, dp, dp, dp]
+    lib.nh_set_solver.argtypes = [vp, dp, ip, ip]
+    lib.nh_forward.argtypes = [vp, vp, vp, ctypes.POINTER(dp), dp, ip, vp]
+    lib.nh_adjoint.argtypes = [vp, vp, vp]
+    lib.nh_forward_f64.argtypes = [vp, vp, vp, ctypes.POINTER(dp), dp, ip, vp]
+    lib.nh_adjoint_f64.argtypes = [vp, vp, vp]
+    lib.nh_get_state.argtypes = [vp, ip, vp]
+    lib.nh_apply_A.argtypes = [vp, vp, vp, vp, dp]
+    lib.nh_set_launch.argtypes = [vp, ip, ip, ip]
+    lib.nh_set_barrier_timeout.argtypes = [vp, dp]
+    lib.nh_get_stats.argtypes = [vp, ctypes.POINTER(nh_stats)]
+    lib.nh_last_error.argtypes = [vp]
+    lib.nh_last_error.restype = ctypes.c_char_p
+    lib.nh_destroy.argtypes = [vp]
+    lib.nh_destroy.restype = None
+    lib.nh_copy_f32.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    for name in EXPORTED:
+        f = getattr(lib, name)
+        if name not in ("nh_last_error", "nh_destroy"):
+            f.restype = st
+    _lib = lib
+    return lib
+
+
+def last_error(ctx) -> str:
+    return load().nh_last_error(ctx).decode(errors="replace")

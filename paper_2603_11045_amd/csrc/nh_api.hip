@@ -1,0 +1,774 @@
+// nh_api.hip -- host runtime and C ABI of the heat solver (include/nefty_heat.h).
+//
+// The runtime owns one HIP stream per context, the context's device
+// workspaces and the saved forward state, and drives the time loop: one
+// cooperative launch of nh::step_kernel per implicit-Euler step (Sec. 4.2),
+// forward in time for the state and backward in time for the adjoint
+// (Sec. 4.3). With checkpointing every k steps the adjoint recomputes each
+// k-step segment from its checkpoint before sweeping it backwards; the
+// recomputation runs the same kernel with the same launch shape, so it
+// reproduces the stored states bit for bit.
+#include "nefty_heat.h"
+#include "nh_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+using nh::Geom;
+using nh::kBlock;
+using nh::StepArgs;
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct nh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cu = 0;
+  long long wallclock_khz = 100000;
+  int occ_f32 = 0, occ_f64 = 0;              // co-resident step kernels per CU
+
+  bool grid_set = false;
+  int nx = 0, ny = 0, nz = 0;
+  double hx = 1, hy = 1, hz = 1;
+
+  double rtol = 1e-6;
+  int max_iter = 1000;
+  int ckpt_every = 0;
+
+  int team_max = 0, tile_z = 0, profile = 0;
+  double barrier_timeout_s = 20.0;
+
+  // saved forward
+  int saved_prec = 0;                        // 0 none, 4 fp32, 8 fp64
+  int saved_nsteps = 0;
+  double saved_dt = 0;
+  std::vector<double> saved_qt;
+
+  // workspaces
+  Buf alpha, qxy, z, p0, p1, mu, w0, w1, traj, seg, partials, bar, steps, flag;
+  size_t ws_bytes = 0, ws_peak = 0;
+
+  Geom geom{};
+  int team = 1;
+  nh_stats st{};
+  std::string err = "";
+  std::vector<hipEvent_t> ev;
+};
+
+namespace {
+
+nh_status fail(nh_ctx* c, nh_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define NH_HIP(ctx, call)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((ctx), NH_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define NH_TRY(expr)                   \
+  do {                                 \
+    nh_status s_ = (expr);             \
+    if (s_ != NH_OK) return s_;        \
+  } while (0)
+
+nh_status release(nh_ctx* c, Buf& b) {
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    c->ws_bytes -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return fail(c, NH_EHIP, std::string("hipFree: ") + hipGetErrorString(e));
+  }
+  return NH_OK;
+}
+
+// Make b hold at least `bytes` (contents are not preserved on growth).
+nh_status ensure(nh_ctx* c, Buf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return NH_OK;
+  NH_TRY(release(c, b));
+  if (bytes == 0) return NH_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, NH_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                  hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  c->ws_bytes += bytes;
+  if (c->ws_bytes > c->ws_peak) c->ws_peak = c->ws_bytes;
+  return NH_OK;
+}
+
+void drop_forward(nh_ctx* c) {
+  c->saved_prec = 0;
+  c->saved_nsteps = 0;
+  release(c, c->traj);
+  release(c, c->seg);
+  release(c, c->w0);
+  release(c, c->w1);
+}
+
+template <typename T>
+nh_status fill(nh_ctx* c, T* p, long long n, T v) {
+  if (n <= 0) return NH_OK;
+  int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(nh::fill_kernel<T>, dim3(blocks), dim3(256), 0, c->stream, p, n, v);
+  NH_HIP(c, hipGetLastError());
+  return NH_OK;
+}
+
+// Tile shape and team size for the current grid.
+void plan(nh_ctx* c, int occ) {
+  Geom g{};
+  g.nx = c->nx;
+  g.ny = c->ny;
+  g.nz = c->nz;
+  g.nxy = (long long)c->nx * c->ny;
+  g.ng = g.nxy * c->nz;
+  g.TX = c->nx > 32 ? 64 : (c->nx > 16 ? 32 : 16);
+  g.TY = kBlock / g.TX;
+  g.txs = g.TX == 64 ? 6 : (g.TX == 32 ? 5 : 4);
+  g.ntx = (g.nx + g.TX - 1) / g.TX;
+  g.nty = (g.ny + g.TY - 1) / g.TY;
+  const int maxteam_hw = std::max(1, occ * c->num_cu);
+  int maxteam = c->team_max > 0 ? std::min(c->team_max, maxteam_hw) : maxteam_hw;
+  const long long xy_tiles = (long long)g.ntx * g.nty;
+  int tz;
+  if (c->tile_z > 0) {
+    tz = std::min(c->tile_z, g.nz);
+  } else if (g.ng <= 65536) {
+    tz = g.nz;                                // small grids: few workgroups, cheap barriers
+  } else {
+    long long want_ntz = (maxteam + xy_tiles - 1) / xy_tiles;
+    if (want_ntz < 1) want_ntz = 1;
+    tz = (int)((g.nz + want_ntz - 1) / want_ntz);
+    if (tz < 4) tz = std::min(4, g.nz);
+  }
+  g.TZ = tz;
+  g.ntz = (g.nz + tz - 1) / tz;
+  g.ntiles = (int)(xy_tiles * g.ntz);
+  int team = std::min(g.ntiles, maxteam);
+  if (g.ng <= 65536 && c->team_max == 0) team = std::min(team, 1 + (int)(g.ng / 16384));
+  c->geom = g;
+  c->team = std::max(1, team);
+  c->st.team_blocks = c->team;
+  c->st.block_threads = kBlock;
+  c->st.tile_x = g.TX;
+  c->st.tile_y = g.TY;
+  c->st.tile_z = g.TZ;
+}
+
+template <typename R>
+int occupancy(nh_ctx* c) {
+  return sizeof(R) == 4 ? c->occ_f32 : c->occ_f64;
+}
+
+template <typename R>
+nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) {
+  void* args[] = {(void*)&S};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profile) {
+    e0 = c->ev[2 * slot_ev];
+    e1 = c->ev[2 * slot_ev + 1];
+    NH_HIP(c, hipEventRecord(e0, c->stream));
+  }
+  NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(kBlock),
+                                       args, 0, c->stream));
+  if (c->profile) NH_HIP(c, hipEventRecord(e1, c->stream));
+  (void)t_kernel;
+  return NH_OK;
+}
+
+// Events are recorded into a pool of kEvPairs pairs; when the pool is full
+// the elapsed times are collected (one stream sync) and the pool reused.
+constexpr int kEvPairs = 512;
+
+nh_status collect_events(nh_ctx* c, int used, double* acc) {
+  if (!c->profile || used == 0) return NH_OK;
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < used; ++i) {
+    float ms = 0;
+    NH_HIP(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    *acc += ms * 1e-3;
+  }
+  return NH_OK;
+}
+
+nh_status ensure_events(nh_ctx* c) {
+  if (!c->profile || !c->ev.empty()) return NH_OK;
+  c->ev.resize(2 * kEvPairs);
+  for (auto& e : c->ev) NH_HIP(c, hipEventCreate(&e));
+  return NH_OK;
+}
+
+template <typename R>
+void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
+  std::memset(&S, 0, sizeof(S));
+  S.g = c->geom;
+  S.sx = (R)(2.0 * dt / (c->hx * c->hx));
+  S.sy = (R)(2.0 * dt / (c->hy * c->hy));
+  S.sz = (R)(2.0 * dt / (c->hz * c->hz));
+  S.alpha = (const R*)c->alpha.p;
+  S.z = (R*)c->z.p;
+  S.p0 = (R*)c->p0.p;
+  S.p1 = (R*)c->p1.p;
+  S.partials = (double*)c->partials.p;
+  S.bar = (unsigned*)c->bar.p;
+  S.rtol2 = c->rtol * c->rtol;
+  S.max_iter = c->max_iter;
+  S.team = c->team;
+  S.xcd_order = 1;
+  S.err_flag = (int*)c->flag.p;
+  S.timeout_ticks = (long long)(c->barrier_timeout_s * (double)c->wallclock_khz * 1000.0);
+}
+
+// Per-step device outputs: [3][nsteps] iterations (forward, adjoint, recompute),
+// then relres and status in the same arrangement.
+struct StepOut {
+  int* iters;
+  double* relres;
+  int* status;
+};
+
+size_t relres_offset(int N) { return (sizeof(int) * 3 * (size_t)N + 63) / 64 * 64; }
+
+size_t step_out_bytes(int N) {
+  return relres_offset(N) + sizeof(double) * 3 * (size_t)N + sizeof(int) * 3 * (size_t)N;
+}
+
+StepOut step_out(nh_ctx* c, int region, int n) {
+  const int N = c->saved_nsteps;
+  char* base = (char*)c->steps.p;
+  int* iters = (int*)base;
+  double* relres = (double*)(base + relres_offset(N));
+  int* status = (int*)(relres + 3 * (size_t)N);
+  StepOut o{iters + region * N + n, relres + region * N + n, status + region * N + n};
+  return o;
+}
+
+nh_status check_flag(nh_ctx* c) {
+  int h = 0;
+  NH_HIP(c, hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  if (h & nh::kTimeout) {
+    // a workgroup left a barrier early: reset the barrier words and the flag
+    NH_HIP(c, hipMemsetAsync(c->bar.p, 0, c->bar.bytes, c->stream));
+    NH_HIP(c, hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
+    NH_HIP(c, hipStreamSynchronize(c->stream));
+    return fail(c, NH_ETIMEOUT, "a device-side team barrier exceeded its time limit");
+  }
+  return NH_OK;
+}
+
+// Sum the per-step outputs of `region` for steps [0, count).
+nh_status summarize(nh_ctx* c, int region, int count, long long* iters_sum, int* max_it,
+                    double* worst, int* any_status) {
+  const int N = c->saved_nsteps;
+  std::vector<int> it(count), stv(count);
+  std::vector<double> rel(count);
+  StepOut o = step_out(c, region, 0);
+  NH_HIP(c, hipMemcpyAsync(it.data(), o.iters, sizeof(int) * count, hipMemcpyDeviceToHost, c->stream));
+  NH_HIP(c, hipMemcpyAsync(rel.data(), o.relres, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  NH_HIP(c, hipMemcpyAsync(stv.data(), o.status, sizeof(int) * count, hipMemcpyDeviceToHost, c->stream));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  (void)N;
+  for (int i = 0; i < count; ++i) {
+    *iters_sum += it[i];
+    if (it[i] > *max_it) *max_it = it[i];
+    if (rel[i] > *worst || rel[i] != rel[i]) *worst = rel[i];
+    *any_status |= stv[i];
+  }
+  return NH_OK;
+}
+
+nh_status status_to_code(nh_ctx* c, int any) {
+  if (any & nh::kNonFinite) return fail(c, NH_ENONFINITE, "a CG reduction was not finite");
+  if (any & nh::kTimeout) return fail(c, NH_ETIMEOUT, "a device-side team barrier timed out");
+  if (any & nh::kNoConv) return fail(c, NH_ENOCONV, "a CG solve reached max_iter");
+  return NH_OK;
+}
+
+template <typename R>
+nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
+  NH_HIP(c, hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
+  int blocks = (int)std::min<long long>((n + 255) / 256, 2048);
+  if (positive)
+    hipLaunchKernelGGL(nh::validate_kernel<R>, dim3(blocks), dim3(256), 0, c->stream, a, n, (int*)c->flag.p);
+  else
+    hipLaunchKernelGGL(nh::finite_kernel<R>, dim3(blocks), dim3(256), 0, c->stream, a, n, (int*)c->flag.p);
+  NH_HIP(c, hipGetLastError());
+  int h = 0;
+  NH_HIP(c, hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  NH_HIP(c, hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
+  return h ? NH_EINVAL : NH_OK;
+}
+
+// Per-voxel algorithmic bytes of one step kernel (R = vector element size).
+double step_bytes(const Geom& g, int R, int mode, int iters, bool first_step, bool surf, bool ckpt) {
+  const double ng = (double)g.ng, nxy = (double)g.nxy;
+  double b = 0;
+  if (mode == nh::kForward) {
+    b += (first_step ? 3.0 : 4.0) * R * ng;        // read x0 (halo), alpha; write x, z
+    if (surf) b += 2.0 * R * nxy;
+    if (ckpt) b += 2.0 * R * ng;
+    b += R * nxy;                                 // top source map
+  } else {
+    b += 3.0 * R * ng + R * nxy;                  // read x, alpha, g^n; write z
+    b += (3.0 * R + 16.0) * ng;                   // gradient: read mu, T, alpha; G read+write
+  }
+  if (iters > 0) b += (10.0 * iters - 1.0) * R * ng;  // 4R+6R per iteration, no p_old on the first
+  return b;
+}
+
+template <typename R>
+nh_status ensure_common(nh_ctx* c, int nsteps) {
+  const size_t vb = sizeof(R) * (size_t)c->geom.ng;
+  NH_TRY(ensure(c, c->alpha, vb));
+  NH_TRY(ensure(c, c->z, vb));
+  NH_TRY(ensure(c, c->p0, vb));
+  NH_TRY(ensure(c, c->p1, vb));
+  NH_TRY(ensure(c, c->partials, sizeof(double) * 2 * (size_t)c->team * nh::kNumRed));
+  if (!c->bar.p) {
+    NH_TRY(ensure(c, c->bar, 256));
+    NH_HIP(c, hipMemsetAsync(c->bar.p, 0, 256, c->stream));
+  }
+  if (!c->flag.p) {
+    NH_TRY(ensure(c, c->flag, 64));
+    NH_HIP(c, hipMemsetAsync(c->flag.p, 0, 64, c->stream));
+  }
+  NH_TRY(ensure(c, c->steps, step_out_bytes(nsteps)));
+  return NH_OK;
+}
+
+// One forward step n (1-based) into x from xprev; region selects where its
+// iteration count goes (0 forward, 2 recompute).
+template <typename R>
+nh_status forward_step(nh_ctx* c, int n, const R* xprev, R* x, const R* q_xy, double dt, double qt,
+                       R* surf, R* ckpt, int region, int ev_slot) {
+  StepArgs<R> S;
+  base_args<R>(c, S, dt);
+  S.mode = nh::kForward;
+  S.x = x;
+  S.xprev = xprev;
+  S.top_src = q_xy;
+  S.top_scale = (R)(dt * qt);
+  S.surf_out = surf;
+  S.ckpt_out = ckpt;
+  StepOut o = step_out(c, region, n - 1);
+  S.out_iters = o.iters;
+  S.out_relres = o.relres;
+  S.out_status = o.status;
+  return launch_step<R>(c, S, ev_slot, nullptr);
+}
+
+template <typename R>
+nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t, double dt,
+                     int nsteps, R* T_surf) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!c) return NH_EINVAL;
+  if (!c->grid_set) return fail(c, NH_ESTATE, "nh_set_grid has not been called");
+  if (!alpha || !q_xy || !q_t || !T_surf) return fail(c, NH_EINVAL, "null pointer argument");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(c, NH_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 1) return fail(c, NH_EINVAL, "nsteps must be >= 1");
+  for (int i = 0; i < nsteps; ++i)
+    if (!std::isfinite(q_t[i])) return fail(c, NH_EINVAL, "q_t holds a non-finite value");
+
+  drop_forward(c);
+  plan(c, occupancy<R>(c));
+  NH_TRY(ensure_common<R>(c, nsteps));
+  NH_TRY(ensure_events(c));
+  const Geom& g = c->geom;
+  const size_t vb = sizeof(R) * (size_t)g.ng;
+
+  nh_status v = check_positive<R>(c, alpha, g.ng, true);
+  if (v == NH_EINVAL) return fail(c, NH_EINVAL, "alpha must be finite and > 0 everywhere");
+  NH_TRY(v);
+  v = check_positive<R>(c, q_xy, g.nxy, false);
+  if (v == NH_EINVAL) return fail(c, NH_EINVAL, "q_xy holds a non-finite value");
+  NH_TRY(v);
+  NH_HIP(c, hipMemcpyAsync(c->alpha.p, alpha, vb, hipMemcpyDeviceToDevice, c->stream));
+  NH_TRY(ensure(c, c->qxy, sizeof(R) * (size_t)g.nxy));
+  NH_HIP(c, hipMemcpyAsync(c->qxy.p, q_xy, sizeof(R) * (size_t)g.nxy, hipMemcpyDeviceToDevice, c->stream));
+  const R* qsrc = (const R*)c->qxy.p;
+
+  const int k = c->ckpt_every;
+  c->saved_nsteps = nsteps;
+  R* traj = nullptr;
+  if (k == 0) {
+    NH_TRY(ensure(c, c->traj, vb * (size_t)nsteps));
+    traj = (R*)c->traj.p;
+  } else {
+    const int nck = (nsteps - 1) / k;               // T^k, T^2k, ... below T^N
+    if (nck > 0) NH_TRY(ensure(c, c->traj, vb * (size_t)nck));
+    NH_TRY(ensure(c, c->w0, vb));
+    NH_TRY(ensure(c, c->w1, vb));
+  }
+
+  c->st.fwd_iters = 0;
+  c->st.fwd_steps = nsteps;
+  c->st.launches_fwd = 0;
+  c->st.t_kernel_fwd_s = 0;
+  double tk = 0;
+  int used = 0;
+  for (int n = 1; n <= nsteps; ++n) {
+    const R* xprev;
+    R* x;
+    R* ck = nullptr;
+    if (k == 0) {
+      xprev = n == 1 ? nullptr : traj + (size_t)(n - 2) * g.ng;
+      x = traj + (size_t)(n - 1) * g.ng;
+    } else {
+      R* w[2] = {(R*)c->w0.p, (R*)c->w1.p};
+      xprev = n == 1 ? nullptr : w[(n - 1) & 1];
+      x = w[n & 1];
+      if (n % k == 0 && n < nsteps) ck = (R*)c->traj.p + (size_t)(n / k - 1) * g.ng;
+    }
+    NH_TRY(forward_step<R>(c, n, xprev, x, qsrc, dt, q_t[n - 1], T_surf + (size_t)(n - 1) * g.nxy,
+                           ck, 0, used));
+    ++c->st.launches_fwd;
+    if (c->profile && ++used == kEvPairs) {
+      NH_TRY(collect_events(c, used, &tk));
+      used = 0;
+    }
+  }
+  NH_TRY(collect_events(c, used, &tk));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  c->st.t_kernel_fwd_s = tk;
+  NH_TRY(check_flag(c));
+
+  int max_it = 0, any = 0;
+  double worst = 0;
+  long long isum = 0;
+  NH_TRY(summarize(c, 0, nsteps, &isum, &max_it, &worst, &any));
+  c->st.fwd_iters = isum;
+  c->st.max_step_iters = max_it;
+  c->st.worst_rel_res = worst;
+  // algorithmic bytes from the per-step iteration counts
+  {
+    std::vector<int> it(nsteps);
+    NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 0, 0).iters, sizeof(int) * nsteps, hipMemcpyDeviceToHost, c->stream));
+    NH_HIP(c, hipStreamSynchronize(c->stream));
+    double bytes = 0;
+    for (int n = 1; n <= nsteps; ++n)
+      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1], n == 1, true,
+                          k > 0 && n % k == 0 && n < nsteps);
+    c->st.bytes_alg_fwd = bytes;
+  }
+  c->saved_prec = sizeof(R);
+  c->saved_dt = dt;
+  c->saved_qt.assign(q_t, q_t + nsteps);
+  c->st.workspace_bytes = c->ws_bytes;
+  c->st.peak_workspace_bytes = c->ws_peak;
+  c->st.t_fwd_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status_to_code(c, any);
+}
+
+template <typename R>
+nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!c) return NH_EINVAL;
+  if (!gsurf || !G) return fail(c, NH_EINVAL, "null pointer argument");
+  if (c->saved_prec != (int)sizeof(R))
+    return fail(c, NH_ESTATE, "no saved forward of this precision (call the matching nh_forward first)");
+  const Geom& g = c->geom;
+  const int N = c->saved_nsteps, k = c->ckpt_every;
+  const double dt = c->saved_dt;
+  const size_t vb = sizeof(R) * (size_t)g.ng;
+  NH_TRY(ensure(c, c->mu, vb));
+  NH_TRY(fill<R>(c, (R*)c->mu.p, g.ng, R(0)));
+  NH_TRY(fill<double>(c, G, g.ng, 0.0));
+  NH_TRY(ensure_events(c));
+
+  c->st.adj_steps = N;
+  c->st.recompute_steps = 0;
+  c->st.launches_adj = 0;
+  double tk = 0;
+  int used = 0;
+  double bytes = 0;
+  std::vector<int> it_rec;
+
+  auto adj_step = [&](int n, const R* Tn) -> nh_status {
+    StepArgs<R> S;
+    base_args<R>(c, S, dt);
+    S.mode = nh::kAdjoint;
+    S.x = (R*)c->mu.p;
+    S.xprev = nullptr;
+    S.top_src = gsurf + (size_t)(n - 1) * g.nxy;
+    S.top_scale = R(1);
+    S.T_grad = Tn;
+    S.G = G;
+    StepOut o = step_out(c, 1, n - 1);
+    S.out_iters = o.iters;
+    S.out_relres = o.relres;
+    S.out_status = o.status;
+    NH_TRY(launch_step<R>(c, S, used, nullptr));
+    ++c->st.launches_adj;
+    if (c->profile && ++used == kEvPairs) {
+      NH_TRY(collect_events(c, used, &tk));
+      used = 0;
+    }
+    return NH_OK;
+  };
+
+  if (k == 0) {
+    const R* traj = (const R*)c->traj.p;
+    for (int n = N; n >= 1; --n) NH_TRY(adj_step(n, traj + (size_t)(n - 1) * g.ng));
+  } else {
+    NH_TRY(ensure(c, c->seg, vb * (size_t)std::min(k, N)));
+    R* seg = (R*)c->seg.p;
+    const int nseg = (N + k - 1) / k;
+    const R* qxy = (const R*)c->qxy.p;
+    for (int s_idx = nseg - 1; s_idx >= 0; --s_idx) {
+      const int s = s_idx * k, e = std::min(s + k, N);
+      const R* start = s == 0 ? nullptr : (const R*)c->traj.p + (size_t)(s_idx - 1) * g.ng;
+      for (int n = s + 1; n <= e; ++n) {
+        const R* xprev = n == s + 1 ? start : seg + (size_t)(n - s - 2) * g.ng;
+        NH_TRY(forward_step<R>(c, n, xprev, seg + (size_t)(n - s - 1) * g.ng, qxy, dt,
+                               c->saved_qt[n - 1], nullptr, nullptr, 2, used));
+        ++c->st.launches_adj;
+        ++c->st.recompute_steps;
+        if (c->profile && ++used == kEvPairs) {
+          NH_TRY(collect_events(c, used, &tk));
+          used = 0;
+        }
+      }
+      for (int n = e; n >= s + 1; --n) NH_TRY(adj_step(n, seg + (size_t)(n - s - 1) * g.ng));
+    }
+  }
+  NH_TRY(collect_events(c, used, &tk));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  c->st.t_kernel_adj_s = tk;
+  NH_TRY(check_flag(c));
+
+  int max_it = 0, any = 0;
+  double worst = 0;
+  long long isum = 0;
+  NH_TRY(summarize(c, 1, N, &isum, &max_it, &worst, &any));
+  c->st.adj_iters = isum;
+  c->st.max_step_iters = max_it;
+  c->st.worst_rel_res = worst;
+  std::vector<int> it(N);
+  NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 1, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  for (int n = 1; n <= N; ++n) bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1], false, false, false);
+  c->st.recompute_iters = 0;
+  if (k > 0) {
+    long long rsum = 0;
+    int rmax = 0, rany = 0;
+    double rworst = 0;
+    NH_TRY(summarize(c, 2, N, &rsum, &rmax, &rworst, &rany));
+    c->st.recompute_iters = rsum;
+    any |= rany;
+    std::vector<int> ir(N);
+    NH_HIP(c, hipMemcpyAsync(ir.data(), step_out(c, 2, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
+    NH_HIP(c, hipStreamSynchronize(c->stream));
+    for (int n = 1; n <= N; ++n) bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1], n == 1, false, false);
+  }
+  c->st.bytes_alg_adj = bytes;
+  c->st.workspace_bytes = c->ws_bytes;
+  c->st.peak_workspace_bytes = c->ws_peak;
+  c->st.t_adj_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status_to_code(c, any);
+}
+
+}  // namespace
+
+extern "C" {
+
+nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
+  if (!out) return NH_EINVAL;
+  *out = nullptr;
+  nh_ctx* c = new (std::nothrow) nh_ctx();
+  if (!c) return NH_ENOMEM;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    delete c;
+    return NH_EINVAL;
+  }
+  c->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess) { delete c; return NH_EHIP; }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return NH_EHIP; }
+    c->own_stream = true;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return NH_EHIP; }
+  c->num_cu = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
+    c->wallclock_khz = khz;
+  int o32 = 0, o64 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, (const void*)nh::step_kernel<float>, kBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, (const void*)nh::step_kernel<double>, kBlock, 0) != hipSuccess) {
+    delete c;
+    return NH_EHIP;
+  }
+  c->occ_f32 = std::max(1, o32);
+  c->occ_f64 = std::max(1, o64);
+  *out = c;
+  return NH_OK;
+}
+
+nh_status nh_set_grid(nh_ctx* c, int nx, int ny, int nz, double hx, double hy, double hz) {
+  if (!c) return NH_EINVAL;
+  if (nx < 1 || ny < 1 || nz < 1) return fail(c, NH_EINVAL, "grid dimensions must be >= 1");
+  if ((long long)nx * ny * nz > (1LL << 40)) return fail(c, NH_EINVAL, "grid too large");
+  if (!(hx > 0) || !(hy > 0) || !(hz > 0) || !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz))
+    return fail(c, NH_EINVAL, "spacings must be finite and > 0");
+  drop_forward(c);
+  c->nx = nx; c->ny = ny; c->nz = nz;
+  c->hx = hx; c->hy = hy; c->hz = hz;
+  c->grid_set = true;
+  NH_TRY(release(c, c->alpha));
+  NH_TRY(release(c, c->z));
+  NH_TRY(release(c, c->p0));
+  NH_TRY(release(c, c->p1));
+  NH_TRY(release(c, c->mu));
+  plan(c, c->occ_f32);
+  return NH_OK;
+}
+
+nh_status nh_set_solver(nh_ctx* c, double rtol, int max_iter, int checkpoint_every) {
+  if (!c) return NH_EINVAL;
+  if (!(rtol > 0) || !(rtol < 1)) return fail(c, NH_EINVAL, "rtol must be in (0, 1)");
+  if (max_iter < 1) return fail(c, NH_EINVAL, "max_iter must be >= 1");
+  if (checkpoint_every < 0) return fail(c, NH_EINVAL, "checkpoint_every must be >= 0");
+  drop_forward(c);
+  c->rtol = rtol;
+  c->max_iter = max_iter;
+  c->ckpt_every = checkpoint_every;
+  return NH_OK;
+}
+
+nh_status nh_forward(nh_ctx* c, const float* alpha, const float* q_xy, const double* q_t, double dt,
+                     int nsteps, float* T_surf) {
+  return do_forward<float>(c, alpha, q_xy, q_t, dt, nsteps, T_surf);
+}
+
+nh_status nh_adjoint(nh_ctx* c, const float* dL_dTsurf, double* dL_dalpha) {
+  return do_adjoint<float>(c, dL_dTsurf, dL_dalpha);
+}
+
+nh_status nh_forward_f64(nh_ctx* c, const double* alpha, const double* q_xy, const double* q_t, double dt,
+                         int nsteps, double* T_surf) {
+  return do_forward<double>(c, alpha, q_xy, q_t, dt, nsteps, T_surf);
+}
+
+nh_status nh_adjoint_f64(nh_ctx* c, const double* dL_dTsurf, double* dL_dalpha) {
+  return do_adjoint<double>(c, dL_dTsurf, dL_dalpha);
+}
+
+nh_status nh_get_state(nh_ctx* c, int n, void* out) {
+  if (!c) return NH_EINVAL;
+  if (!out) return fail(c, NH_EINVAL, "null pointer argument");
+  if (!c->saved_prec) return fail(c, NH_ESTATE, "no saved forward");
+  if (n < 1 || n > c->saved_nsteps) return fail(c, NH_EINVAL, "step index out of range");
+  const size_t vb = (size_t)c->saved_prec * (size_t)c->geom.ng;
+  const void* src = nullptr;
+  if (c->ckpt_every == 0) {
+    src = (const char*)c->traj.p + (size_t)(n - 1) * vb;
+  } else if (n % c->ckpt_every == 0 && n < c->saved_nsteps) {
+    src = (const char*)c->traj.p + (size_t)(n / c->ckpt_every - 1) * vb;
+  } else if (n == c->saved_nsteps) {
+    src = (n & 1) ? c->w1.p : c->w0.p;
+  } else {
+    return fail(c, NH_ESTATE, "state not held (checkpointing keeps every k-th state and the last)");
+  }
+  NH_HIP(c, hipMemcpyAsync(out, src, vb, hipMemcpyDeviceToDevice, c->stream));
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  return NH_OK;
+}
+
+nh_status nh_apply_A(nh_ctx* c, const float* alpha, const float* x, float* y, double dt) {
+  if (!c) return NH_EINVAL;
+  if (!c->grid_set) return fail(c, NH_ESTATE, "nh_set_grid has not been called");
+  if (!alpha || !x || !y) return fail(c, NH_EINVAL, "null pointer argument");
+  if (x == y) return fail(c, NH_EINVAL, "y must not alias x");
+  if (!(dt >= 0) || !std::isfinite(dt)) return fail(c, NH_EINVAL, "dt must be finite and >= 0");
+  plan(c, c->occ_f32);
+  const Geom& g = c->geom;
+  const int blocks = std::min(g.ntiles, std::max(1, c->occ_f32 * c->num_cu));
+  hipLaunchKernelGGL(nh::apply_kernel<float>, dim3(blocks), dim3(kBlock), 0, c->stream, g, alpha, x, y,
+                     (float)(2.0 * dt / (c->hx * c->hx)), (float)(2.0 * dt / (c->hy * c->hy)),
+                     (float)(2.0 * dt / (c->hz * c->hz)));
+  NH_HIP(c, hipGetLastError());
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  return NH_OK;
+}
+
+nh_status nh_set_launch(nh_ctx* c, int team_blocks_max, int tile_z, int profile) {
+  if (!c) return NH_EINVAL;
+  if (team_blocks_max < 0 || tile_z < 0) return fail(c, NH_EINVAL, "negative launch setting");
+  drop_forward(c);
+  c->team_max = team_blocks_max;
+  c->tile_z = tile_z;
+  c->profile = profile != 0;
+  if (c->grid_set) plan(c, c->occ_f32);
+  return NH_OK;
+}
+
+nh_status nh_set_barrier_timeout(nh_ctx* c, double seconds) {
+  if (!c) return NH_EINVAL;
+  if (!(seconds >= 0) || !std::isfinite(seconds)) return fail(c, NH_EINVAL, "timeout must be finite and >= 0");
+  c->barrier_timeout_s = seconds;
+  return NH_OK;
+}
+
+nh_status nh_get_stats(const nh_ctx* c, nh_stats* out) {
+  if (!c || !out) return NH_EINVAL;
+  *out = c->st;
+  out->workspace_bytes = c->ws_bytes;
+  out->peak_workspace_bytes = c->ws_peak;
+  return NH_OK;
+}
+
+const char* nh_last_error(const nh_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+void nh_destroy(nh_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  Buf* bufs[] = {&c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->mu, &c->w0, &c->w1, &c->traj,
+                 &c->seg, &c->partials, &c->bar, &c->steps, &c->flag};
+  for (Buf* b : bufs) release(c, *b);
+  for (auto e : c->ev) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+nh_status nh_copy_f32(const float* src, float* dst, size_t n, void* hip_stream) {
+  if (!src || !dst) return NH_EINVAL;
+  if (n == 0) return NH_OK;
+  int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(nh::copy_kernel<float>, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream, src, dst,
+                     (long long)n);
+  return hipGetLastError() == hipSuccess ? NH_OK : NH_EHIP;
+}
+
+}  // extern "C"

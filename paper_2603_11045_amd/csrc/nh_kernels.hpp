@@ -1,0 +1,671 @@
+// nh_kernels.hpp -- gfx950 kernels of the implicit-Euler heat solver and its
+// discrete adjoint (the paper's Sec. 4.2-4.3, App. D.2-D.3).
+//
+// One cooperative launch performs one time step of one problem: the residual
+// set-up, every Jacobi-preconditioned CG iteration until convergence, and the
+// step's epilogue (surface frame and checkpoint in the forward sweep, the
+// gradient accumulation in the adjoint sweep). The workgroups of a launch form
+// a "team" that synchronises through a device-scope barrier; reductions are
+// FP64, per-workgroup partials summed in a fixed order by every workgroup, so
+// all of them take bit-identical decisions and a rerun is bit-identical.
+//
+// CG in the form used here (M = diag(A), the Jacobi preconditioner of
+// App. D.2, as a preconditioner instead of as the solver):
+//   set-up    r = b - A x,  z = r / D,  bb = |b|^2, rz = r.z, rr = |r|^2
+//   phase A   p = z + beta p  (beta = 0 first),  w = A p,  pw = p.w
+//   phase B   a = rz / pw,  x += a p,  z -= a (A p) / D,  rz = D z.z, rr = |D z|^2
+// until rr <= rtol^2 bb. Only z is stored (r = D z); A p is recomputed in
+// phase B instead of being stored, and D comes from alpha in-kernel, so an
+// iteration moves 40 bytes per voxel in FP32.
+//
+// The stencil is evaluated by marching a 2-D tile of (x, y) columns along z:
+// each z plane of the staged vectors and of alpha, with its one-cell halo in
+// x and y, goes through LDS with x-contiguous (coalesced) loads, while the
+// +-z neighbours of a column stay in registers. Cells outside the grid read
+// alpha = 0, which makes their harmonic-mean conductance 0: the zero-flux
+// boundary needs no special case.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nh {
+
+constexpr int kBlock = 512;                 // threads per workgroup (8 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxPlane = 660;              // max (TX+2)*(TY+2): TX=64,TY=8 -> 66*10
+constexpr int kNumRed = 4;                  // doubles per workgroup partial slot
+
+enum StepMode : int { kForward = 0, kAdjoint = 1 };
+enum StepStatus : int { kOk = 0, kNoConv = 1, kNonFinite = 2, kTimeout = 4 };
+
+struct Geom {
+  int nx, ny, nz;
+  int TX, TY, TZ, txs;                      // tile extents, txs = log2(TX)
+  int ntx, nty, ntz, ntiles;
+  long long nxy, ng;
+};
+
+template <typename R>
+struct StepArgs {
+  Geom g;
+  R sx, sy, sz;                             // 2 dt / h_d^2 per axis
+  const R* alpha;
+  R* x;                                     // the unknown, solved in place
+  const R* xprev;                           // forward: T^{n-1} (null = zero state); adjoint: null
+  R* z;                                     // preconditioned residual
+  R* p0;                                    // search direction, ping-pong pair
+  R* p1;
+  const R* top_src;                         // [ny][nx] added on k = 0 (forward q_xy, adjoint g^n)
+  R top_scale;                              // forward dt*q_t[n-1], adjoint 1
+  R* surf_out;                              // forward: frame of T^n on k = 0 (or null)
+  R* ckpt_out;                              // forward: copy of T^n (or null)
+  const R* T_grad;                          // adjoint: T^n for the gradient (or null)
+  double* G;                                // adjoint: dL/dalpha accumulator
+  double* partials;                         // [2][team][kNumRed]
+  unsigned* bar;                            // team barrier words (count at [0], generation at [32])
+  double rtol2;
+  int max_iter;
+  int mode;
+  int team;
+  int xcd_order;                            // 1: give each XCD a contiguous range of tiles
+  int* out_iters;                           // per-step outputs written by rank 0
+  double* out_relres;
+  int* out_status;
+  int* err_flag;                            // |= kTimeout by any workgroup whose barrier timed out
+  long long timeout_ticks;                  // barrier time limit in wall-clock ticks
+};
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers
+
+template <typename R> __device__ __forceinline__ R rcp(R v);
+template <> __device__ __forceinline__ float rcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ __forceinline__ double rcp<double>(double v) { return 1.0 / v; }
+
+// dt * c_f = s * a*b/(a+b) with s = 2 dt / h^2 (Prop. 1); b = 0 outside the grid gives 0.
+template <typename R>
+__device__ __forceinline__ R face(R s, R a, R b) { return s * (a * b) * rcp<R>(a + b); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// team barrier: self-resetting counter + generation word, device scope.
+// Returns false (on thread 0) if the time limit was exceeded.
+
+__device__ __forceinline__ bool team_barrier(unsigned* bar, int team, long long timeout_ticks,
+                                             int* lds_flag) {
+  __syncthreads();
+  if (team > 1) {
+    if (threadIdx.x == 0) {
+      unsigned* count = bar;
+      unsigned* gen = bar + 32;
+      const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned arrived =
+          __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      int ok = 1;
+      if (arrived == (unsigned)team) {
+        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gen, g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const long long t0 = wall_clock64();
+        while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+          __builtin_amdgcn_s_sleep(1);
+          if (wall_clock64() - t0 > timeout_ticks) { ok = 0; break; }
+        }
+      }
+      *lds_flag = ok;
+    }
+    __syncthreads();
+    return *lds_flag != 0;
+  }
+  return true;
+}
+
+// Shared state of one workgroup.
+template <typename R>
+struct Smem {
+  R a[kMaxPlane];
+  R v[2][kMaxPlane];
+  double red[kWaves][kNumRed];
+  double bc[kNumRed];
+  int flag;
+};
+
+// Sum NV doubles over the workgroup; the result lands in every thread's v.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed], double* bc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < kWaves; ++w) s += red[w][i];
+      bc[i] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = bc[i];
+  __syncthreads();
+}
+
+// Team all-reduce of NV doubles: workgroup sums go to a partial slot, the team
+// barrier publishes them, every workgroup sums all slots in the same order.
+template <typename R, int NV>
+__device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, int& red_ctr,
+                                         double (&v)[NV], Smem<R>& sh) {
+  block_sum<NV>(v, sh.red, sh.bc);
+  if (S.team == 1) return true;
+  double* part = S.partials + (size_t)(red_ctr & 1) * S.team * kNumRed;
+  ++red_ctr;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) part[rank * kNumRed + i] = v[i];
+  }
+  const bool ok = team_barrier(S.bar, S.team, S.timeout_ticks, &sh.flag);
+  double s[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) s[i] = 0.0;
+  for (int b = threadIdx.x; b < S.team; b += kBlock) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      s[i] += __hip_atomic_load(part + b * kNumRed + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum<NV>(s, sh.red, sh.bc);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = s[i];
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+
+struct Tile {
+  int x0, y0, z0, z1;
+};
+
+__device__ __forceinline__ Tile tile_of(const Geom& g, int t) {
+  const int itz = t % g.ntz;
+  const int rest = t / g.ntz;
+  const int itx = rest % g.ntx;
+  const int ity = rest / g.ntx;
+  Tile T;
+  T.x0 = itx * g.TX;
+  T.y0 = ity * g.TY;
+  T.z0 = itz * g.TZ;
+  T.z1 = min(T.z0 + g.TZ, g.nz);
+  return T;
+}
+
+// Workgroup rank -> first tile. With xcd_order the ranks that the hardware
+// places on one XCD (rank % 8, dispatch is round-robin over the 8 XCDs) get a
+// contiguous tile range, so most halo reads hit that XCD's L2.
+__device__ __forceinline__ int first_tile(int rank, int team, int xcd_order) {
+  if (xcd_order && (team & 7) == 0) return (rank & 7) * (team >> 3) + (rank >> 3);
+  return rank;
+}
+
+// Stencil values of one cell: index 0 centre, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z.
+template <typename R, int NV>
+struct Pt {
+  R a[7];
+  R v[NV][7];
+};
+
+// March one tile along z. Op supplies: NV, alpha, load(k, i), point(P, i, k).
+template <typename R, typename Op>
+__device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op, Smem<R>& sh) {
+  constexpr int NV = Op::NV;
+  const int tid = threadIdx.x;
+  const int TX = g.TX, TY = g.TY, PW = TX + 2;
+  const int tx = tid & (TX - 1), ty = tid >> g.txs;
+  const int gx = T.x0 + tx, gy = T.y0 + ty;
+  const bool own = gx < g.nx && gy < g.ny;
+  const long long col = own ? (long long)gx + (long long)g.nx * gy : 0;
+  const int oslot = (ty + 1) * PW + tx + 1;
+
+  // the halo cell this thread stages (perimeter of the TX x TY tile)
+  int hslot = -1;
+  bool hin = false;
+  long long hcol = 0;
+  {
+    int h = tid, hx = 0, hy = 0;
+    if (h < TX) { hx = T.x0 + h; hy = T.y0 - 1; hslot = h + 1; }
+    else if ((h -= TX) < TX) { hx = T.x0 + h; hy = T.y0 + TY; hslot = (TY + 1) * PW + h + 1; }
+    else if ((h -= TX) < TY) { hx = T.x0 - 1; hy = T.y0 + h; hslot = (h + 1) * PW; }
+    else if ((h -= TY) < TY) { hx = T.x0 + TX; hy = T.y0 + h; hslot = (h + 1) * PW + TX + 1; }
+    if (hslot >= 0) {
+      hin = hx >= 0 && hx < g.nx && hy >= 0 && hy < g.ny;
+      if (hin) hcol = (long long)hx + (long long)g.nx * hy;
+    }
+  }
+
+  R am = 0, ac = 0, ap = 0, ha = 0;
+  R vm[NV], vc[NV], vp[NV], hv[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) { vm[k] = 0; vc[k] = 0; vp[k] = 0; hv[k] = 0; }
+
+  if (own) {
+    if (T.z0 > 0) {
+      const long long i = col + (long long)(T.z0 - 1) * g.nxy;
+      am = op.alpha[i];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) vm[k] = op.load(k, i);
+    }
+    {
+      const long long i = col + (long long)T.z0 * g.nxy;
+      ac = op.alpha[i];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) vc[k] = op.load(k, i);
+    }
+    if (T.z0 + 1 < g.nz) {
+      const long long i = col + (long long)(T.z0 + 1) * g.nxy;
+      ap = op.alpha[i];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) vp[k] = op.load(k, i);
+    }
+  }
+  if (hin) {
+    const long long i = hcol + (long long)T.z0 * g.nxy;
+    ha = op.alpha[i];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) hv[k] = op.load(k, i);
+  }
+
+  for (int z = T.z0; z < T.z1; ++z) {
+    // prefetch: own column two planes ahead, halo one plane ahead
+    R an = 0, han = 0;
+    R vn[NV], hvn[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { vn[k] = 0; hvn[k] = 0; }
+    if (own && z + 2 < g.nz) {
+      const long long i = col + (long long)(z + 2) * g.nxy;
+      an = op.alpha[i];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) vn[k] = op.load(k, i);
+    }
+    if (hin && z + 1 < T.z1) {
+      const long long i = hcol + (long long)(z + 1) * g.nxy;
+      han = op.alpha[i];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) hvn[k] = op.load(k, i);
+    }
+
+    __syncthreads();
+    sh.a[oslot] = ac;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh.v[k][oslot] = vc[k];
+    if (hslot >= 0) {
+      sh.a[hslot] = ha;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) sh.v[k][hslot] = hv[k];
+    }
+    __syncthreads();
+
+    if (own) {
+      Pt<R, NV> P;
+      P.a[0] = ac;
+      P.a[1] = sh.a[oslot - 1];
+      P.a[2] = sh.a[oslot + 1];
+      P.a[3] = sh.a[oslot - PW];
+      P.a[4] = sh.a[oslot + PW];
+      P.a[5] = am;
+      P.a[6] = ap;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        P.v[k][0] = vc[k];
+        P.v[k][1] = sh.v[k][oslot - 1];
+        P.v[k][2] = sh.v[k][oslot + 1];
+        P.v[k][3] = sh.v[k][oslot - PW];
+        P.v[k][4] = sh.v[k][oslot + PW];
+        P.v[k][5] = vm[k];
+        P.v[k][6] = vp[k];
+      }
+      op.point(P, col + (long long)z * g.nxy, z);
+    }
+
+    am = ac; ac = ap; ap = an; ha = han;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { vm[k] = vc[k]; vc[k] = vp[k]; vp[k] = vn[k]; hv[k] = hvn[k]; }
+  }
+}
+
+// A v and the diagonal D of A at one cell, from staged alpha and v (row k of P).
+template <typename R, int NV>
+__device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, R sx, R sy, R sz, R& Av, R& D) {
+  const R a = P.a[0];
+  const R c1 = face<R>(sx, a, P.a[1]), c2 = face<R>(sx, a, P.a[2]);
+  const R c3 = face<R>(sy, a, P.a[3]), c4 = face<R>(sy, a, P.a[4]);
+  const R c5 = face<R>(sz, a, P.a[5]), c6 = face<R>(sz, a, P.a[6]);
+  const R v = P.v[k][0];
+  R s = c1 * (v - P.v[k][1]);
+  s += c2 * (v - P.v[k][2]);
+  s += c3 * (v - P.v[k][3]);
+  s += c4 * (v - P.v[k][4]);
+  s += c5 * (v - P.v[k][5]);
+  s += c6 * (v - P.v[k][6]);
+  Av = v + s;
+  D = R(1) + (((c1 + c2) + (c3 + c4)) + (c5 + c6));
+}
+
+// ---------------------------------------------------------------------------
+// phase operators
+
+// Set-up: b = x0 + top source, r = b - A x0, z = r / D.
+template <typename R>
+struct InitOp {
+  static constexpr int NV = 1;
+  const R* alpha;
+  const R* src;                             // staged x0 (null = zero state)
+  R* xw;                                    // x to initialise with x0 (null = already there)
+  R* z;
+  const R* top;
+  R top_scale;
+  R sx, sy, sz;
+  long long nxy;
+  double acc[3];                            // |b|^2, r.z, |r|^2
+  __device__ R load(int, long long i) const { return src ? src[i] : R(0); }
+  __device__ void point(const Pt<R, 1>& P, long long i, int kz) {
+    R Av, D;
+    stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
+    R b = P.v[0][0];
+    if (kz == 0) b += top_scale * top[i];
+    const R r = b - Av;
+    const R zz = r * rcp<R>(D);
+    z[i] = zz;
+    if (xw) xw[i] = P.v[0][0];
+    const double bd = b, rd = r;
+    acc[0] += bd * bd;
+    acc[1] += rd * (double)zz;
+    acc[2] += rd * rd;
+  }
+};
+
+// Phase A: p_new = z + beta p_old, w = A p_new, accumulate p_new . w.
+template <typename R>
+struct DirOp {
+  static constexpr int NV = 1;
+  const R* alpha;
+  const R* z;
+  const R* pold;
+  R* pnew;
+  R beta;
+  int first;
+  R sx, sy, sz;
+  double acc[1];
+  __device__ R load(int, long long i) const { return first ? z[i] : z[i] + beta * pold[i]; }
+  __device__ void point(const Pt<R, 1>& P, long long i, int) {
+    R Av, D;
+    stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
+    pnew[i] = P.v[0][0];
+    acc[0] += (double)P.v[0][0] * (double)Av;
+  }
+};
+
+// Phase B: x += a p, z -= a (A p) / D, accumulate r.z = D z^2 and |r|^2 = (D z)^2.
+template <typename R>
+struct UpdOp {
+  static constexpr int NV = 1;
+  const R* alpha;
+  const R* p;
+  R* x;
+  R* z;
+  R a;
+  R sx, sy, sz;
+  double acc[2];
+  __device__ R load(int, long long i) const { return p[i]; }
+  __device__ void point(const Pt<R, 1>& P, long long i, int) {
+    R Ap, D;
+    stencil<R, 1>(P, 0, sx, sy, sz, Ap, D);
+    x[i] = x[i] + a * P.v[0][0];
+    const R zn = z[i] - a * (Ap * rcp<R>(D));
+    z[i] = zn;
+    const double zd = zn, rd = (double)D * zd;
+    acc[0] += rd * zd;
+    acc[1] += rd * rd;
+  }
+};
+
+// Adjoint epilogue: G_p -= sum_f s_f (a_q/(a_p+a_q))^2 (T_p-T_q)(mu_p-mu_q),
+// s_f = 2 dt / h^2, i.e. G += -dt dc_f/da_p dT dmu (eq. grad_assembly).
+template <typename R>
+struct GradOp {
+  static constexpr int NV = 2;
+  const R* alpha;
+  const R* mu;
+  const R* T;
+  double* G;
+  double sx, sy, sz;
+  __device__ R load(int k, long long i) const { return k == 0 ? mu[i] : T[i]; }
+  __device__ void point(const Pt<R, 2>& P, long long i, int) {
+    const double a = P.a[0], m = P.v[0][0], t = P.v[1][0];
+    const double s[7] = {0.0, sx, sx, sy, sy, sz, sz};
+    double acc = 0.0;
+#pragma unroll
+    for (int f = 1; f < 7; ++f) {
+      const double q = P.a[f];
+      const double w = q / (a + q);
+      acc += s[f] * (w * w) * ((t - (double)P.v[1][f]) * (m - (double)P.v[0][f]));
+    }
+    G[i] -= acc;
+  }
+};
+
+// y = A x on its own (operator tests).
+template <typename R>
+struct ApplyOp {
+  static constexpr int NV = 1;
+  const R* alpha;
+  const R* xin;
+  R* y;
+  R sx, sy, sz;
+  __device__ R load(int, long long i) const { return xin[i]; }
+  __device__ void point(const Pt<R, 1>& P, long long i, int) {
+    R Av, D;
+    stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
+    y[i] = Av;
+  }
+};
+
+template <typename R, typename Op>
+__device__ __forceinline__ void sweep(const Geom& g, int rank, int team, int xcd, Op& op, Smem<R>& sh) {
+  for (int t = first_tile(rank, team, xcd); t < g.ntiles; t += team) {
+    const Tile T = tile_of(g, t);
+    march_tile<R, Op>(g, T, op, sh);
+  }
+}
+
+// Own cells of the workgroup's tiles (no stencil): fn(i, col, kz).
+template <typename F>
+__device__ __forceinline__ void own_cells(const Geom& g, int rank, int team, int xcd, F fn) {
+  const int tx = threadIdx.x & (g.TX - 1), ty = threadIdx.x >> g.txs;
+  for (int t = first_tile(rank, team, xcd); t < g.ntiles; t += team) {
+    const Tile T = tile_of(g, t);
+    const int gx = T.x0 + tx, gy = T.y0 + ty;
+    if (gx >= g.nx || gy >= g.ny) continue;
+    const long long col = (long long)gx + (long long)g.nx * gy;
+    for (int z = T.z0; z < T.z1; ++z) fn(col + (long long)z * g.nxy, col, z);
+  }
+}
+
+// Top-plane cells (k = 0) of the workgroup's tiles: fn(col).
+template <typename F>
+__device__ __forceinline__ void top_cells(const Geom& g, int rank, int team, int xcd, F fn) {
+  const int tx = threadIdx.x & (g.TX - 1), ty = threadIdx.x >> g.txs;
+  for (int t = first_tile(rank, team, xcd); t < g.ntiles; t += team) {
+    const Tile T = tile_of(g, t);
+    if (T.z0 != 0) continue;
+    const int gx = T.x0 + tx, gy = T.y0 + ty;
+    if (gx >= g.nx || gy >= g.ny) continue;
+    fn((long long)gx + (long long)g.nx * gy);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one implicit-Euler step (forward or adjoint) for one team
+
+template <typename R>
+__device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
+  const Geom& g = S.g;
+  int red = 0;
+  bool ok = true;
+
+  // set-up
+  InitOp<R> init;
+  init.alpha = S.alpha;
+  init.sx = S.sx; init.sy = S.sy; init.sz = S.sz;
+  init.z = S.z;
+  init.top = S.top_src;
+  init.top_scale = S.top_scale;
+  init.nxy = g.nxy;
+  init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
+  if (S.mode == kForward) {
+    init.src = S.xprev;
+    init.xw = (S.xprev == S.x) ? nullptr : S.x;
+  } else {
+    init.src = S.x;
+    init.xw = nullptr;
+  }
+  sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
+  double v3[3] = {init.acc[0], init.acc[1], init.acc[2]};
+  ok &= team_sum<R, 3>(S, rank, red, v3, sh);
+  const double bb = v3[0];
+  double rz = v3[1], rr = v3[2];
+
+  int it = 0, status = kOk;
+  if (ok && bb == 0.0) {
+    // b = 0: the solution is x = 0
+    own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) { S.x[i] = R(0); });
+    ok &= team_barrier(S.bar, S.team, S.timeout_ticks, &sh.flag);
+    rr = 0.0;
+  } else {
+    R* pc = S.p0;
+    R* pn = S.p1;
+    double rz_old = 1.0;
+    while (ok && rr > S.rtol2 * bb) {
+      if (it >= S.max_iter) { status |= kNoConv; break; }
+      DirOp<R> A;
+      A.alpha = S.alpha; A.z = S.z; A.pold = pc; A.pnew = pn;
+      A.first = (it == 0);
+      A.beta = (R)(it == 0 ? 0.0 : rz / rz_old);
+      A.sx = S.sx; A.sy = S.sy; A.sz = S.sz;
+      A.acc[0] = 0.0;
+      sweep<R>(g, rank, S.team, S.xcd_order, A, sh);
+      double v1[1] = {A.acc[0]};
+      ok &= team_sum<R, 1>(S, rank, red, v1, sh);
+      if (!ok) break;
+      const double alpha_cg = rz / v1[0];
+
+      UpdOp<R> B;
+      B.alpha = S.alpha; B.p = pn; B.x = S.x; B.z = S.z;
+      B.a = (R)alpha_cg;
+      B.sx = S.sx; B.sy = S.sy; B.sz = S.sz;
+      B.acc[0] = B.acc[1] = 0.0;
+      sweep<R>(g, rank, S.team, S.xcd_order, B, sh);
+      double v2[2] = {B.acc[0], B.acc[1]};
+      ok &= team_sum<R, 2>(S, rank, red, v2, sh);
+      rz_old = rz;
+      rz = v2[0];
+      rr = v2[1];
+      ++it;
+      R* t = pc; pc = pn; pn = t;
+    }
+  }
+  if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
+  if (!ok) {
+    status |= kTimeout;
+    if (threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
+  }
+
+  // epilogue
+  if (S.mode == kForward) {
+    if (S.ckpt_out) {
+      own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long col, int kz) {
+        const R v = S.x[i];
+        if (kz == 0 && S.surf_out) S.surf_out[col] = v;
+        S.ckpt_out[i] = v;
+      });
+    } else if (S.surf_out) {
+      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { S.surf_out[col] = S.x[col]; });
+    }
+  } else if (S.T_grad && ok) {
+    GradOp<R> Gop;
+    Gop.alpha = S.alpha; Gop.mu = S.x; Gop.T = S.T_grad; Gop.G = S.G;
+    Gop.sx = S.sx; Gop.sy = S.sy; Gop.sz = S.sz;
+    sweep<R>(g, rank, S.team, S.xcd_order, Gop, sh);
+  }
+
+  if (rank == 0 && threadIdx.x == 0) {
+    S.out_iters[0] = it;
+    S.out_relres[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    S.out_status[0] = status;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock, 2) step_kernel(StepArgs<R> S) {
+  __shared__ Smem<R> sh;
+  run_step<R>(S, blockIdx.x, sh);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock, 2) apply_kernel(Geom g, const R* alpha, const R* x, R* y,
+                                                          R sx, R sy, R sz) {
+  __shared__ Smem<R> sh;
+  ApplyOp<R> op;
+  op.alpha = alpha; op.xin = x; op.y = y;
+  op.sx = sx; op.sy = sy; op.sz = sz;
+  sweep<R>(g, blockIdx.x, gridDim.x, 0, op, sh);
+}
+
+// flag |= 1 if some alpha is not finite and positive
+template <typename R>
+__global__ void validate_kernel(const R* a, long long n, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const R v = a[i];
+    if (!(v > R(0)) || !(v < R(INFINITY))) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// flag |= 1 if some value is not finite
+template <typename R>
+__global__ void finite_kernel(const R* a, long long n, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const R v = a[i];
+    if (!(v == v) || !(v < R(INFINITY)) || !(v > R(-INFINITY))) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+template <typename T>
+__global__ void fill_kernel(T* p, long long n, T v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void copy_kernel(const T* __restrict__ s, T* __restrict__ d, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+}  // namespace nh

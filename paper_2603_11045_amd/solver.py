@@ -1,0 +1,189 @@
+"""Python front end of the HIP heat solver: a ``Solver`` object over one C
+context and the ``HeatSolve`` autograd function.
+
+PyTorch supplies device memory and the stream; every step of the forward
+and adjoint sweeps runs in the library's kernels (``libnefty_heat.so``).
+The loss stays with the caller: the adjoint takes ``dL/dT_surf`` and returns
+``dL/dalpha`` (the vector-Jacobian product of the paper's Sec. 4.3).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _check(code: int, ctx, func: str, allow=()):
+    if code != _lib.NH_OK and code not in allow:
+        raise _lib.NHError(code, func, _lib.last_error(ctx))
+    return code
+
+
+def _dev_tensor(t: torch.Tensor, name: str, dtype: torch.dtype, numel: int) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements (got {t.numel()})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Solver:
+    """One implicit-Euler heat problem on one GPU (one C context, one stream).
+
+    ``precision`` is ``"f32"`` (FP32 vectors, FP64 reductions and gradient) or
+    ``"f64"``. ``checkpoint_every = k > 0`` keeps every k-th state and
+    recomputes segments in the adjoint; 0 keeps all states.
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, h: Sequence[float] = (1.0, 1.0, 1.0),
+                 rtol: float = 1e-6, max_iter: int = 1000, checkpoint_every: int = 0,
+                 precision: str = "f32", device: Optional[int] = None,
+                 stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
+                 tile_z: int = 0, profile: bool = False):
+        if precision not in ("f32", "f64"):
+            raise ValueError("precision must be 'f32' or 'f64'")
+        self.lib = _lib.load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.h = tuple(float(v) for v in h)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "f32" else torch.float64
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        _check(self.lib.nh_create(ctypes.byref(self._ctx), self.device.index,
+                                  ctypes.c_void_p(self.stream.cuda_stream)), None, "nh_create")
+        _check(self.lib.nh_set_grid(self._ctx, self.nx, self.ny, self.nz, *self.h), self._ctx,
+               "nh_set_grid")
+        self.set_solver(rtol, max_iter, checkpoint_every)
+        if team_blocks_max or tile_z or profile:
+            self.set_launch(team_blocks_max, tile_z, profile)
+        self.generation = 0
+        self.nsteps = 0
+        self.last_status = _lib.NH_OK
+
+    # -- configuration ----------------------------------------------------
+    def set_solver(self, rtol: float, max_iter: int, checkpoint_every: int = 0):
+        _check(self.lib.nh_set_solver(self._ctx, float(rtol), int(max_iter), int(checkpoint_every)),
+               self._ctx, "nh_set_solver")
+        self.rtol, self.max_iter, self.checkpoint_every = float(rtol), int(max_iter), int(checkpoint_every)
+
+    def set_launch(self, team_blocks_max: int = 0, tile_z: int = 0, profile: bool = False):
+        _check(self.lib.nh_set_launch(self._ctx, int(team_blocks_max), int(tile_z), int(bool(profile))),
+               self._ctx, "nh_set_launch")
+
+    def set_barrier_timeout(self, seconds: float):
+        _check(self.lib.nh_set_barrier_timeout(self._ctx, float(seconds)), self._ctx,
+               "nh_set_barrier_timeout")
+
+    @property
+    def ng(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    # -- solver ------------------------------------------------------------
+    def forward(self, alpha: torch.Tensor, q_xy: torch.Tensor, q_t, dt: float, nsteps: int,
+                out: Optional[torch.Tensor] = None, allow_noconv: bool = False) -> torch.Tensor:
+        """Surface temperature ``[nsteps][ny][nx]`` of the forward sweep."""
+        nsteps = int(nsteps)
+        _dev_tensor(alpha, "alpha", self.dtype, self.ng)
+        _dev_tensor(q_xy, "q_xy", self.dtype, self.nx * self.ny)
+        qt = np.ascontiguousarray(np.asarray(q_t, dtype=np.float64).reshape(-1))
+        if qt.size != nsteps:
+            raise ValueError(f"q_t must have nsteps={nsteps} entries (got {qt.size})")
+        if out is None:
+            out = torch.empty((nsteps, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        _dev_tensor(out, "T_surf", self.dtype, nsteps * self.nx * self.ny)
+        fn = self.lib.nh_forward if self.precision == "f32" else self.lib.nh_forward_f64
+        code = fn(self._ctx, alpha.data_ptr(), q_xy.data_ptr(),
+                  qt.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt), nsteps,
+                  out.data_ptr())
+        allow = (_lib.NH_ENOCONV,) if allow_noconv else ()
+        self.last_status = _check(code, self._ctx, "nh_forward", allow)
+        self.generation += 1
+        self.nsteps = nsteps
+        return out
+
+    def adjoint(self, dL_dTsurf: torch.Tensor, out: Optional[torch.Tensor] = None,
+                allow_noconv: bool = False) -> torch.Tensor:
+        """``dL/dalpha`` (float64, ``[nz][ny][nx]``) of the last forward."""
+        _dev_tensor(dL_dTsurf, "dL_dTsurf", self.dtype, self.nsteps * self.nx * self.ny)
+        if out is None:
+            out = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        _dev_tensor(out, "dL_dalpha", torch.float64, self.ng)
+        fn = self.lib.nh_adjoint if self.precision == "f32" else self.lib.nh_adjoint_f64
+        code = fn(self._ctx, dL_dTsurf.data_ptr(), out.data_ptr())
+        allow = (_lib.NH_ENOCONV,) if allow_noconv else ()
+        self.last_status = _check(code, self._ctx, "nh_adjoint", allow)
+        return out
+
+    def get_state(self, n: int) -> torch.Tensor:
+        out = torch.empty((self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        _check(self.lib.nh_get_state(self._ctx, int(n), out.data_ptr()), self._ctx, "nh_get_state")
+        return out
+
+    def apply_A(self, alpha: torch.Tensor, x: torch.Tensor, dt: float) -> torch.Tensor:
+        """``A x`` with the FP32 stencil kernel (operator tests)."""
+        _dev_tensor(alpha, "alpha", torch.float32, self.ng)
+        _dev_tensor(x, "x", torch.float32, self.ng)
+        y = torch.empty_like(x)
+        _check(self.lib.nh_apply_A(self._ctx, alpha.data_ptr(), x.data_ptr(), y.data_ptr(), float(dt)),
+               self._ctx, "nh_apply_A")
+        return y
+
+    def stats(self) -> dict:
+        s = _lib.nh_stats()
+        _check(self.lib.nh_get_stats(self._ctx, ctypes.byref(s)), self._ctx, "nh_get_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self.lib.nh_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HeatSolve(torch.autograd.Function):
+    """``T_surf = HeatSolve.apply(alpha, solver, q_xy, q_t, dt, nsteps)``.
+
+    Backward runs the library's adjoint sweep and returns ``dL/dalpha`` in
+    ``alpha``'s dtype (accumulated in FP64). If the solver ran another forward
+    in between, the forward of this call is recomputed first.
+    """
+
+    @staticmethod
+    def forward(ctx, alpha, solver: Solver, q_xy, q_t, dt, nsteps):
+        a = alpha.detach().to(solver.dtype).contiguous()
+        T = solver.forward(a, q_xy, q_t, dt, nsteps)
+        ctx.solver = solver
+        ctx.gen = solver.generation
+        ctx.args = (q_xy, q_t, dt, nsteps)
+        ctx.alpha_dtype = alpha.dtype
+        ctx.save_for_backward(a)
+        return T
+
+    @staticmethod
+    def backward(ctx, g):
+        solver: Solver = ctx.solver
+        (a,) = ctx.saved_tensors
+        if solver.generation != ctx.gen:
+            solver.forward(a, *ctx.args)
+        G = solver.adjoint(g.detach().to(solver.dtype).contiguous())
+        return G.to(ctx.alpha_dtype), None, None, None, None, None
+
+
+def heat_solve(alpha, solver: Solver, q_xy, q_t, dt, nsteps):
+    return HeatSolve.apply(alpha, solver, q_xy, q_t, dt, nsteps)

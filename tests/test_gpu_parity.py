@@ -1,0 +1,228 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Norms (global relative L2 over the whole array) and tolerances: surface
+temperature 1e-5 and dL/dalpha 1e-4 for the FP32-vector path; the FP64 path
+is held to 1e-9 / 1e-8. The oracle solves every step to 1e-13, the GPU to the
+workload's own tolerance, so the CG tolerance (not FP32 rounding) sets the
+FP32 gap.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import heat as orc
+from paper_2603_11045_amd import _lib
+from paper_2603_11045_amd import workloads as wl
+from paper_2603_11045_amd.solver import HeatSolve, Solver
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="session", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    _lib.load()
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None):
+    """Forward (and adjoint when gs is given) of workload w on the GPU."""
+    prec = precision or w.precision
+    dt_t = torch.float32 if prec == "f32" else torch.float64
+    s = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=rtol or w.rtol, max_iter=5000,
+               checkpoint_every=checkpoint_every, precision=prec, team_blocks_max=team, tile_z=tile_z)
+    S = s.forward(to_dev(w.alpha, dt_t), to_dev(w.q_xy, dt_t), w.q_t, w.dt, w.nsteps)
+    out = dict(S=S.cpu().numpy().astype(np.float64), stats_fwd=s.stats(), solver=s)
+    if gs is not None:
+        G = s.adjoint(to_dev(gs, dt_t))
+        out["G"] = G.cpu().numpy()
+        out["stats_adj"] = s.stats()
+    return out
+
+
+# ------------------------------------------------------------------ operator
+@pytest.mark.parametrize("shape", [(3, 5, 7), (9, 33, 65), (11, 17, 130), (8, 16, 16), (32, 64, 64),
+                                   (1, 1, 1), (5, 1, 70)])
+def test_apply_A_matches_oracle(shape):
+    nz, ny, nx = shape
+    say("apply_A", shape)
+    rng = np.random.default_rng(sum(shape))
+    alpha = np.exp(0.7 * rng.standard_normal(shape)).astype(np.float32)
+    x = rng.uniform(-1, 1, size=shape).astype(np.float32)
+    dt = 1.7
+    s = Solver(nx, ny, nz, h=(1.0, 0.8, 1.3))
+    y = s.apply_A(to_dev(alpha, torch.float32), to_dev(x, torch.float32), dt).cpu().numpy()
+    ref = orc.apply_A(alpha, x, dt, h=(1.0, 0.8, 1.3))
+    scale = np.abs(x).max() * (1 + 12 * dt * alpha.max())
+    assert np.abs(y - ref).max() <= 4e-6 * scale
+    if shape != (1, 1, 1):
+        assert rel_l2(y, ref) <= 1e-6
+
+
+# ------------------------------------------------------------------ small problems
+SMALL = [
+    # (nx, ny, nz, nsteps, seed, team, tile_z)
+    (7, 5, 3, 6, 1, 0, 0),
+    (37, 21, 13, 5, 2, 3, 4),
+    (70, 40, 9, 4, 3, 5, 3),
+    (33, 17, 6, 7, 4, 8, 2),
+    (16, 16, 8, 5, 5, 0, 0),
+    (130, 9, 5, 3, 6, 0, 1),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_t{c[5]}_z{c[6]}" for c in SMALL])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_small_forward_adjoint(case, precision):
+    nx, ny, nz, nsteps, seed, team, tz = case
+    say("small", case, precision)
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=seed, dt=2.5, precision=precision,
+                         rtol=1e-12 if precision == "f64" else 1e-7)
+    gs = wl.random_surface_weights(nsteps, ny, nx, seed=100 + seed)
+    src = orc.source_series(w.q_xy, w.q_t)
+    S_o, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt)
+    out = run_gpu(w, team=team, tile_z=tz, gs=gs)
+    tol_s, tol_g = (1e-9, 1e-8) if precision == "f64" else (1e-5, 1e-4)
+    es, eg = rel_l2(out["S"], S_o), rel_l2(out["G"], G_o)
+    say("  rel-L2 S", es, "G", eg, "team", out["stats_fwd"]["team_blocks"])
+    assert es <= tol_s and eg <= tol_g
+
+
+def test_plain_fp64_16x16x8():
+    """16x16x8, 50 steps, dt=2, FP64 at rtol 1e-12, MSE against the alpha=0.2 target."""
+    w = wl.plain_fp64_16x16x8()
+    say("plain fp64", w.name)
+    ref = orc.run_workload(w)
+    out = run_gpu(w, gs=ref["gs"])
+    es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
+    say("  rel-L2 S", es, "G", eg, "iters", out["stats_fwd"]["fwd_iters"], out["stats_adj"]["adj_iters"])
+    assert es <= 1e-10
+    assert eg <= 1e-9
+
+
+# ------------------------------------------------------------------ 64x64x32 mixed precision
+@pytest.fixture(scope="module")
+def mixed_ref():
+    w = wl.mixed_64x64x32()
+    say("oracle for", w.name)
+    return w, orc.run_workload(w)
+
+
+@pytest.mark.timeout(600)
+def test_mixed_64x64x32_forward_and_adjoint(mixed_ref):
+    w, ref = mixed_ref
+    say("gpu", w.name)
+    out = run_gpu(w, gs=ref["gs"].astype(np.float32))
+    es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
+    mx = float(np.abs(out["G"] - ref["G"]).max() / np.abs(ref["G"]).max())
+    say("  rel-L2 S", es, "G", eg, "max|dG|/max|G|", mx, "iters", out["stats_fwd"]["fwd_iters"],
+        out["stats_adj"]["adj_iters"])
+    assert es <= 1e-5
+    assert eg <= 1e-4
+
+
+# ------------------------------------------------------------------ checkpointing, determinism
+def test_checkpoint_recompute_is_bitwise():
+    w = wl.small_problem(40, 24, 10, 20, seed=9, dt=3.0, precision="f32", rtol=1e-6)
+    gs = wl.random_surface_weights(20, 24, 40, seed=19).astype(np.float32)
+    say("checkpoint full")
+    full = run_gpu(w, gs=gs, team=4, tile_z=3)
+    for k in (1, 7, 64):
+        say("checkpoint k", k)
+        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=4, tile_z=3)
+        assert np.array_equal(ck["S"], full["S"])
+        assert np.array_equal(ck["G"], full["G"])
+        if k < 20:
+            assert ck["stats_adj"]["recompute_iters"] == full["stats_fwd"]["fwd_iters"]
+
+
+def test_runs_are_bitwise_deterministic():
+    w = wl.small_problem(64, 40, 12, 6, seed=11, dt=4.0, precision="f32", rtol=1e-6)
+    gs = wl.random_surface_weights(6, 40, 64, seed=21).astype(np.float32)
+    a = run_gpu(w, gs=gs, team=6, tile_z=4)
+    b = run_gpu(w, gs=gs, team=6, tile_z=4)
+    assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["G"], b["G"])
+
+
+def test_get_state_conserves_heat():
+    """Zero flux: total heat after step n is dt * sum of the injected source."""
+    w = wl.small_problem(48, 30, 10, 5, seed=12, dt=2.0, precision="f64", rtol=1e-12)
+    out = run_gpu(w)
+    s = out["solver"]
+    injected = np.cumsum(w.dt * w.q_t * w.q_xy.sum())
+    for n in range(1, 6):
+        T = s.get_state(n).cpu().numpy()
+        assert abs(T.sum() - injected[n - 1]) <= 1e-10 * injected[n - 1]
+
+
+# ------------------------------------------------------------------ autograd
+def test_heat_solve_autograd_matches_adjoint_and_gradcheck():
+    nx, ny, nz, nsteps = 5, 4, 3, 4
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=13, dt=1.5, precision="f64", rtol=1e-13)
+    s = Solver(nx, ny, nz, rtol=1e-13, max_iter=2000, precision="f64")
+    q = to_dev(w.q_xy, torch.float64)
+    a = to_dev(w.alpha, torch.float64).requires_grad_(True)
+    T = HeatSolve.apply(a, s, q, w.q_t, w.dt, nsteps)
+    gs = torch.from_numpy(wl.random_surface_weights(nsteps, ny, nx, seed=31)).cuda()
+    (T * gs).sum().backward()
+    src = orc.source_series(w.q_xy, w.q_t)
+    _, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs.cpu().numpy(), w.dt)
+    assert rel_l2(a.grad.cpu().numpy(), G_o) <= 1e-9
+    f = lambda al: HeatSolve.apply(al, s, q, w.q_t, w.dt, nsteps)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (a.detach().clone().requires_grad_(True),), eps=1e-6,
+                                    atol=1e-7, rtol=1e-5)
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_paths():
+    nx, ny, nz = 8, 6, 4
+    s = Solver(nx, ny, nz)
+    q = torch.ones((ny, nx), device="cuda")
+    g = torch.ones((3, ny, nx), device="cuda")
+    with pytest.raises(_lib.NHError) as e:
+        s.nsteps = 3
+        s.adjoint(g)
+    assert e.value.code == _lib.NH_ESTATE
+    bad = torch.ones((nz, ny, nx), device="cuda")
+    bad[1, 2, 3] = 0.0
+    with pytest.raises(_lib.NHError) as e:
+        s.forward(bad, q, [1.0, 0, 0], 1.0, 3)
+    assert e.value.code == _lib.NH_EINVAL
+    bad[1, 2, 3] = float("nan")
+    with pytest.raises(_lib.NHError) as e:
+        s.forward(bad, q, [1.0, 0, 0], 1.0, 3)
+    assert e.value.code == _lib.NH_EINVAL
+    good = torch.ones((nz, ny, nx), device="cuda")
+    with pytest.raises(_lib.NHError) as e:
+        s.forward(good, q, [1.0, 0, 0], -1.0, 3)
+    assert e.value.code == _lib.NH_EINVAL
+    s.set_solver(1e-10, 1, 0)
+    T = s.forward(good, q, [1.0, 0, 0], 5.0, 3, allow_noconv=True)
+    assert s.last_status == _lib.NH_ENOCONV and torch.isfinite(T).all()
+    # a zero time limit on the team barrier makes the kernel leave early; the context recovers
+    s2 = Solver(64, 32, 16, rtol=1e-6, team_blocks_max=8, tile_z=2)
+    s2.set_barrier_timeout(0.0)
+    a2 = torch.ones((16, 32, 64), device="cuda")
+    q2 = torch.ones((32, 64), device="cuda")
+    with pytest.raises(_lib.NHError) as e:
+        s2.forward(a2, q2, [1.0, 0.0], 1.0, 2)
+    assert e.value.code == _lib.NH_ETIMEOUT
+    s2.set_barrier_timeout(20.0)
+    T2 = s2.forward(a2, q2, [1.0, 0.0], 1.0, 2)
+    assert torch.isfinite(T2).all()
