@@ -1,0 +1,182 @@
+"""Throughput of the differentiable heat solver on one MI355X.
+
+One bench step = one forward sweep plus one adjoint sweep of the whole
+workload (every implicit-Euler step, every CG iteration, the surface frames,
+the MSE gradient on the surface and dL/dalpha), with inputs resident in HBM.
+Default workload: 256x256x64 voxels, 1000 steps, dt = 10, lognormal alpha
+(sigma 0.3) with 16 ellipsoidal inclusions, uniform top pulse, CG rtol 1e-6,
+FP32 vectors with FP64 reductions and gradient.
+
+Prints one JSON line. ``value`` is fwd+adjoint voxel-steps/s
+(voxels * steps / time of one forward plus one adjoint).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+
+def make_workload(name: str, nsteps: int = 0):
+    from paper_2603_11045_amd import workloads as wl
+
+    if name == "stiff_256x256x64":
+        w = wl.stiff_256x256x64(nsteps=nsteps or 1000)
+    elif name == "long_512x512x64":
+        w = wl.long_512x512x64(nsteps=nsteps or 2000)
+    elif name == "mixed_64x64x32":
+        w = wl.mixed_64x64x32(nsteps=nsteps or 200)
+    elif name == "plain_fp64_16x16x8":
+        w = wl.plain_fp64_16x16x8()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return w
+
+
+def cpu_baseline(w, sample_steps: int):
+    """The FP64 oracle, as it stands, on the first `sample_steps` steps of the
+    same workload (forward + adjoint at the workload's own rtol)."""
+    from oracle import heat as orc
+
+    src = orc.source_series(w.q_xy, w.q_t)[:sample_steps]
+    t0 = time.perf_counter()
+    S, T_all, it_f = orc.forward(w.alpha, src, w.dt, h=w.h, rtol=w.rtol)
+    gs = np.random.default_rng(0).standard_normal(S.shape) * 1e-3
+    G, _, _, it_a = orc.adjoint(w.alpha, T_all, gs, w.dt, h=w.h, rtol=w.rtol)
+    t = time.perf_counter() - t0
+    vs = w.ng * sample_steps / t
+    return {"value": vs, "unit": "voxel-steps/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{w.nx}x{w.ny}x{w.nz}, first {sample_steps} of {w.nsteps} steps, forward+adjoint, "
+                      f"FP64 matrix-free Jacobi-PCG at rtol {w.rtol:g} (OpenMP), {t:.1f} s",
+            "cg_iters": int(it_f.sum() + it_a.sum()), "seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="stiff_256x256x64")
+    ap.add_argument("--nsteps", type=int, default=0, help="override the time-step count (testing)")
+    ap.add_argument("--checkpoint-every", type=int, default=-1)
+    ap.add_argument("--team", type=int, default=0)
+    ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=16)
+    ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(one problem per GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_11045_amd import Solver
+
+    dev = torch.device("cuda", 0)
+    w = make_workload(args.workload, args.nsteps)
+    ck = w.checkpoint_every if args.checkpoint_every < 0 else args.checkpoint_every
+    dtype = torch.float32 if w.precision == "f32" else torch.float64
+    print(f"[bench] workload {w.name}: {w.nx}x{w.ny}x{w.nz}, {w.nsteps} steps, dt {w.dt}, rtol {w.rtol}, "
+          f"checkpoint_every {ck}", file=sys.stderr, flush=True)
+
+    solver = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=w.rtol, max_iter=2000, checkpoint_every=ck,
+                    precision=w.precision, device=0, team_blocks_max=args.team, tile_z=args.tile_z,
+                    profile=not args.no_profile)
+    alpha = torch.from_numpy(w.alpha).to(dev)
+    q_xy = torch.from_numpy(w.q_xy).to(dev)
+    # synthetic measurement: the surface of the target diffusivity
+    target = solver.forward(torch.from_numpy(w.alpha_target).to(dev), q_xy, w.q_t, w.dt, w.nsteps).clone()
+    m = target.numel()
+
+    def one_step():
+        S = solver.forward(alpha, q_xy, w.q_t, w.dt, w.nsteps)
+        g = (2.0 / m) * (S - target)           # d/dS of mean((S - target)^2), caller side
+        G = solver.adjoint(g)
+        return S, G
+
+    for i in range(args.warmup):
+        one_step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    t_fwd = t_adj = tk_f = tk_a = bytes_f = bytes_a = 0.0
+    it_f = it_a = it_r = launches = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step()
+        st = solver.stats()
+        t_fwd += st["t_fwd_s"]
+        t_adj += st["t_adj_s"]
+        tk_f += st["t_kernel_fwd_s"]
+        tk_a += st["t_kernel_adj_s"]
+        bytes_f += st["bytes_alg_fwd"]
+        bytes_a += st["bytes_alg_adj"]
+        it_f += st["fwd_iters"]
+        it_a += st["adj_iters"]
+        it_r += st["recompute_iters"]
+        launches += st["launches_fwd"] + st["launches_adj"]
+        print(f"[bench] step {i + 1}/{args.steps}: fwd {st['t_fwd_s']:.3f} s ({st['fwd_iters']} CG it), "
+              f"adj {st['t_adj_s']:.3f} s ({st['adj_iters']} CG it)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    K = args.steps
+    vox_steps = float(w.ng) * w.nsteps * K
+    value = vox_steps / elapsed
+    iters = it_f + it_a + it_r
+    st = solver.stats()
+    roof = None
+    if not args.no_profile and (tk_f + tk_a) > 0:
+        achieved = (bytes_f + bytes_a) / (tk_f + tk_a) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "nh::step_kernel<float>" if w.precision == "f32" else "nh::step_kernel<double>",
+                "avg_launch_us": round((tk_f + tk_a) / max(launches, 1) * 1e6, 2),
+                "alg_bytes_per_launch": (bytes_f + bytes_a) / max(launches, 1),
+                "kernel_time_frac": round((tk_f + tk_a) / elapsed, 4)}
+    rec = {
+        "metric": "fwd+adjoint voxel-steps/s",
+        "value": value,
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "nsteps": w.nsteps, "dt": w.dt,
+                   "rtol": w.rtol, "checkpoint_every": ck, "team_blocks": st["team_blocks"],
+                   "tile": [st["tile_x"], st["tile_y"], st["tile_z"]]},
+        "cg_iters_per_s": iters / elapsed,
+        "voxel_iters_per_s": iters * float(w.ng) / elapsed,
+        "cg_iters_per_step": {"fwd": it_f / K, "adj": it_a / K, "recompute": it_r / K},
+        "t_fwd_s": t_fwd / K,
+        "t_adj_s": t_adj / K,
+        "roofline": roof,
+        "peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps))
+        rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

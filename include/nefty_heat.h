@@ -81,9 +81,11 @@ typedef struct {
     int tile_x, tile_y, tile_z; /* tile extents of the stencil kernels */
 } nh_stats;
 
-/* Create a context on HIP device `hip_device`. `hip_stream` (a hipStream_t)
- * is borrowed and must outlive the context; NULL makes the context create
- * and own a stream of default priority. */
+/* Create a context on HIP device `hip_device`. All work of the context is
+ * issued on `hip_stream` (a hipStream_t of that device, borrowed: it must
+ * outlive the context); NULL means the device's null stream. Work the
+ * caller queued earlier on the same stream is ordered before the context's
+ * work. */
 nh_status nh_create(nh_ctx **out, int hip_device, void *hip_stream);
 
 /* Set the grid: nx, ny, nz >= 1 cells, spacings hx, hy, hz > 0. Frees the

@@ -37,7 +37,6 @@ struct Buf {
 struct nh_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  bool own_stream = false;
   int num_cu = 0;
   long long wallclock_khz = 100000;
   int occ_f32 = 0, occ_f64 = 0;              // co-resident step kernels per CU
@@ -60,7 +59,8 @@ struct nh_ctx {
   std::vector<double> saved_qt;
 
   // workspaces
-  Buf alpha, qxy, z, p0, p1, mu, w0, w1, traj, seg, partials, bar, steps, flag;
+  Buf alpha, qxy, z, p0, p1, mu, w0, w1, traj, seg, slots, steps, flag;
+  unsigned long long launch_ctr = 0;         // makes every launch's reduction epochs unique
   size_t ws_bytes = 0, ws_peak = 0;
 
   Geom geom{};
@@ -232,8 +232,8 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.z = (R*)c->z.p;
   S.p0 = (R*)c->p0.p;
   S.p1 = (R*)c->p1.p;
-  S.partials = (double*)c->partials.p;
-  S.bar = (unsigned*)c->bar.p;
+  S.slots = c->slots.p;
+  S.epoch_base = (++c->launch_ctr) << 24;
   S.rtol2 = c->rtol * c->rtol;
   S.max_iter = c->max_iter;
   S.team = c->team;
@@ -271,8 +271,8 @@ nh_status check_flag(nh_ctx* c) {
   NH_HIP(c, hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   if (h & nh::kTimeout) {
-    // a workgroup left a barrier early: reset the barrier words and the flag
-    NH_HIP(c, hipMemsetAsync(c->bar.p, 0, c->bar.bytes, c->stream));
+    // a workgroup left a reduction early; later launches use fresh epochs, so
+    // only the flag needs clearing
     NH_HIP(c, hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
     NH_HIP(c, hipStreamSynchronize(c->stream));
     return fail(c, NH_ETIMEOUT, "a device-side team barrier exceeded its time limit");
@@ -348,10 +348,10 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   NH_TRY(ensure(c, c->z, vb));
   NH_TRY(ensure(c, c->p0, vb));
   NH_TRY(ensure(c, c->p1, vb));
-  NH_TRY(ensure(c, c->partials, sizeof(double) * 2 * (size_t)c->team * nh::kNumRed));
-  if (!c->bar.p) {
-    NH_TRY(ensure(c, c->bar, 256));
-    NH_HIP(c, hipMemsetAsync(c->bar.p, 0, 256, c->stream));
+  const size_t slot_bytes = sizeof(nh::Slot) * ((size_t)c->team + 1);
+  if (c->slots.bytes < slot_bytes || !c->slots.p) {
+    NH_TRY(ensure(c, c->slots, slot_bytes));
+    NH_HIP(c, hipMemsetAsync(c->slots.p, 0, c->slots.bytes, c->stream));  // epoch 0 is never used
   }
   if (!c->flag.p) {
     NH_TRY(ensure(c, c->flag, 64));
@@ -608,12 +608,7 @@ nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
   }
   c->device = hip_device;
   if (hipSetDevice(hip_device) != hipSuccess) { delete c; return NH_EHIP; }
-  if (hip_stream) {
-    c->stream = (hipStream_t)hip_stream;
-  } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return NH_EHIP; }
-    c->own_stream = true;
-  }
+  c->stream = (hipStream_t)hip_stream;  // NULL: the null stream
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) { delete c; return NH_EHIP; }
   c->num_cu = prop.multiProcessorCount;
@@ -755,10 +750,9 @@ void nh_destroy(nh_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->mu, &c->w0, &c->w1, &c->traj,
-                 &c->seg, &c->partials, &c->bar, &c->steps, &c->flag};
+                 &c->seg, &c->slots, &c->steps, &c->flag};
   for (Buf* b : bufs) release(c, *b);
   for (auto e : c->ev) (void)hipEventDestroy(e);
-  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 

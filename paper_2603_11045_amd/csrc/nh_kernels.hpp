@@ -5,9 +5,12 @@
 // set-up, every Jacobi-preconditioned CG iteration until convergence, and the
 // step's epilogue (surface frame and checkpoint in the forward sweep, the
 // gradient accumulation in the adjoint sweep). The workgroups of a launch form
-// a "team" that synchronises through a device-scope barrier; reductions are
-// FP64, per-workgroup partials summed in a fixed order by every workgroup, so
-// all of them take bit-identical decisions and a rerun is bit-identical.
+// a "team" that synchronises only through FP64 reductions: every workgroup
+// publishes its partial sums in a slot of its own, one master workgroup waits
+// for all slots, sums them in a fixed order and publishes the result. No
+// read-modify-write atomics are involved (no contention on one address, which
+// grows linearly with the team), every workgroup receives the same bits, and a
+// rerun is bit-identical.
 //
 // CG in the form used here (M = diag(A), the Jacobi preconditioner of
 // App. D.2, as a preconditioner instead of as the solver):
@@ -62,8 +65,8 @@ struct StepArgs {
   R* ckpt_out;                              // forward: copy of T^n (or null)
   const R* T_grad;                          // adjoint: T^n for the gradient (or null)
   double* G;                                // adjoint: dL/dalpha accumulator
-  double* partials;                         // [2][team][kNumRed]
-  unsigned* bar;                            // team barrier words (count at [0], generation at [32])
+  void* slots;                              // [team + 1] Slot: per-workgroup partials, then the result
+  unsigned long long epoch_base;            // unique per launch; each reduction uses epoch_base + k
   double rtol2;
   int max_iter;
   int mode;
@@ -72,7 +75,7 @@ struct StepArgs {
   int* out_iters;                           // per-step outputs written by rank 0
   double* out_relres;
   int* out_status;
-  int* err_flag;                            // |= kTimeout by any workgroup whose barrier timed out
+  int* err_flag;                            // |= kTimeout by any workgroup whose wait timed out
   long long timeout_ticks;                  // barrier time limit in wall-clock ticks
 };
 
@@ -94,36 +97,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// team barrier: self-resetting counter + generation word, device scope.
-// Returns false (on thread 0) if the time limit was exceeded.
+// team reduction slots
 
-__device__ __forceinline__ bool team_barrier(unsigned* bar, int team, long long timeout_ticks,
-                                             int* lds_flag) {
-  __syncthreads();
-  if (team > 1) {
-    if (threadIdx.x == 0) {
-      unsigned* count = bar;
-      unsigned* gen = bar + 32;
-      const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned arrived =
-          __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-      int ok = 1;
-      if (arrived == (unsigned)team) {
-        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(gen, g0 + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        const long long t0 = wall_clock64();
-        while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-          __builtin_amdgcn_s_sleep(1);
-          if (wall_clock64() - t0 > timeout_ticks) { ok = 0; break; }
-        }
-      }
-      *lds_flag = ok;
-    }
-    __syncthreads();
-    return *lds_flag != 0;
-  }
-  return true;
+struct alignas(64) Slot {
+  double v[kNumRed];
+  unsigned long long epoch;
+  unsigned long long pad[3];
+};
+
+__device__ __forceinline__ unsigned long long ld_epoch(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_val(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Shared state of one workgroup.
@@ -161,32 +147,76 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
   __syncthreads();
 }
 
-// Team all-reduce of NV doubles: workgroup sums go to a partial slot, the team
-// barrier publishes them, every workgroup sums all slots in the same order.
+// Team all-reduce of NV doubles; also the team's barrier. Every workgroup
+// stores its workgroup sum in its slot and releases it with the epoch of this
+// reduction (the release also publishes the workgroup's earlier global
+// stores). The master (rank 0) waits for every slot, sums the slots in rank
+// order with a fixed reduction tree, and releases the result slot; the other
+// workgroups wait for that. Waits are bounded by timeout_ticks; a timeout
+// returns false and is recorded in err_flag.
 template <typename R, int NV>
-__device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, int& red_ctr,
+__device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigned long long& epoch,
                                          double (&v)[NV], Smem<R>& sh) {
   block_sum<NV>(v, sh.red, sh.bc);
   if (S.team == 1) return true;
-  double* part = S.partials + (size_t)(red_ctr & 1) * S.team * kNumRed;
-  ++red_ctr;
-  if (threadIdx.x == 0) {
+  const unsigned long long e = ++epoch;
+  Slot* slots = (Slot*)S.slots;
+  Slot* res = slots + S.team;
+  int ok = 1;
+  if (rank != 0) {
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) part[rank * kNumRed + i] = v[i];
+      for (int i = 0; i < NV; ++i)
+        __hip_atomic_store(&slots[rank].v[i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&slots[rank].epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const long long t0 = wall_clock64();
+      while (ld_epoch(&res->epoch) != e) {
+        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sh.bc[i] = ld_val(&res->v[i]);
+      sh.flag = ok;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = sh.bc[i];
+    ok = sh.flag;
+    __syncthreads();
+  } else {
+    double s[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s[i] = 0.0;
+    for (int b = threadIdx.x; b < S.team; b += kBlock) {
+      if (b == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s[i] += v[i];
+        continue;
+      }
+      const long long t0 = wall_clock64();
+      while (ld_epoch(&slots[b].epoch) != e) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
+      }
+#pragma unroll
+      for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
+    }
+    ok = __syncthreads_and(ok);
+    block_sum<NV>(s, sh.red, sh.bc);
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        __hip_atomic_store(&res->v[i], s[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&res->epoch, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = s[i];
   }
-  const bool ok = team_barrier(S.bar, S.team, S.timeout_ticks, &sh.flag);
-  double s[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) s[i] = 0.0;
-  for (int b = threadIdx.x; b < S.team; b += kBlock) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-      s[i] += __hip_atomic_load(part + b * kNumRed + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<NV>(s, sh.red, sh.bc);
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = s[i];
-  return ok;
+  if (!ok && threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
+  return ok != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -224,10 +254,14 @@ struct Pt {
   R v[NV][7];
 };
 
-// March one tile along z. Op supplies: NV, alpha, load(k, i), point(P, i, k).
+// March one tile along z. Op supplies: NV staged vectors (load(k, i)), NO
+// operands of type OT read only at the cell itself (own(k, i), prefetched one
+// plane ahead without staging), alpha, and point(P, o, i, kz).
 template <typename R, typename Op>
 __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op, Smem<R>& sh) {
   constexpr int NV = Op::NV;
+  constexpr int NO = Op::NO;
+  using OT = typename Op::OT;
   const int tid = threadIdx.x;
   const int TX = g.TX, TY = g.TY, PW = TX + 2;
   const int tx = tid & (TX - 1), ty = tid >> g.txs;
@@ -254,8 +288,11 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
 
   R am = 0, ac = 0, ap = 0, ha = 0;
   R vm[NV], vc[NV], vp[NV], hv[NV];
+  OT oc[NO];
 #pragma unroll
   for (int k = 0; k < NV; ++k) { vm[k] = 0; vc[k] = 0; vp[k] = 0; hv[k] = 0; }
+#pragma unroll
+  for (int k = 0; k < NO; ++k) oc[k] = 0;
 
   if (own) {
     if (T.z0 > 0) {
@@ -269,6 +306,8 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
       ac = op.alpha[i];
 #pragma unroll
       for (int k = 0; k < NV; ++k) vc[k] = op.load(k, i);
+#pragma unroll
+      for (int k = 0; k < NO; ++k) oc[k] = op.own(k, i);
     }
     if (T.z0 + 1 < g.nz) {
       const long long i = col + (long long)(T.z0 + 1) * g.nxy;
@@ -285,16 +324,25 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
   }
 
   for (int z = T.z0; z < T.z1; ++z) {
-    // prefetch: own column two planes ahead, halo one plane ahead
+    // prefetch: staged own column two planes ahead, own-only operands and
+    // the halo one plane ahead
     R an = 0, han = 0;
     R vn[NV], hvn[NV];
+    OT on[NO];
 #pragma unroll
     for (int k = 0; k < NV; ++k) { vn[k] = 0; hvn[k] = 0; }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) on[k] = 0;
     if (own && z + 2 < g.nz) {
       const long long i = col + (long long)(z + 2) * g.nxy;
       an = op.alpha[i];
 #pragma unroll
       for (int k = 0; k < NV; ++k) vn[k] = op.load(k, i);
+    }
+    if (own && z + 1 < T.z1) {
+      const long long i = col + (long long)(z + 1) * g.nxy;
+#pragma unroll
+      for (int k = 0; k < NO; ++k) on[k] = op.own(k, i);
     }
     if (hin && z + 1 < T.z1) {
       const long long i = hcol + (long long)(z + 1) * g.nxy;
@@ -333,12 +381,14 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
         P.v[k][5] = vm[k];
         P.v[k][6] = vp[k];
       }
-      op.point(P, col + (long long)z * g.nxy, z);
+      op.point(P, oc, col + (long long)z * g.nxy, z);
     }
 
     am = ac; ac = ap; ap = an; ha = han;
 #pragma unroll
     for (int k = 0; k < NV; ++k) { vm[k] = vc[k]; vc[k] = vp[k]; vp[k] = vn[k]; hv[k] = hvn[k]; }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) oc[k] = on[k];
   }
 }
 
@@ -367,6 +417,8 @@ __device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, R sx, R sy, R
 template <typename R>
 struct InitOp {
   static constexpr int NV = 1;
+  static constexpr int NO = 1;
+  using OT = R;
   const R* alpha;
   const R* src;                             // staged x0 (null = zero state)
   R* xw;                                    // x to initialise with x0 (null = already there)
@@ -377,7 +429,8 @@ struct InitOp {
   long long nxy;
   double acc[3];                            // |b|^2, r.z, |r|^2
   __device__ R load(int, long long i) const { return src ? src[i] : R(0); }
-  __device__ void point(const Pt<R, 1>& P, long long i, int kz) {
+  __device__ R own(int, long long) const { return R(0); }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
     R Av, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
     R b = P.v[0][0];
@@ -397,6 +450,8 @@ struct InitOp {
 template <typename R>
 struct DirOp {
   static constexpr int NV = 1;
+  static constexpr int NO = 1;
+  using OT = R;
   const R* alpha;
   const R* z;
   const R* pold;
@@ -406,7 +461,8 @@ struct DirOp {
   R sx, sy, sz;
   double acc[1];
   __device__ R load(int, long long i) const { return first ? z[i] : z[i] + beta * pold[i]; }
-  __device__ void point(const Pt<R, 1>& P, long long i, int) {
+  __device__ R own(int, long long) const { return R(0); }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
     R Av, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
     pnew[i] = P.v[0][0];
@@ -418,6 +474,8 @@ struct DirOp {
 template <typename R>
 struct UpdOp {
   static constexpr int NV = 1;
+  static constexpr int NO = 2;
+  using OT = R;
   const R* alpha;
   const R* p;
   R* x;
@@ -426,11 +484,12 @@ struct UpdOp {
   R sx, sy, sz;
   double acc[2];
   __device__ R load(int, long long i) const { return p[i]; }
-  __device__ void point(const Pt<R, 1>& P, long long i, int) {
+  __device__ R own(int k, long long i) const { return k == 0 ? x[i] : z[i]; }
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int) {
     R Ap, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Ap, D);
-    x[i] = x[i] + a * P.v[0][0];
-    const R zn = z[i] - a * (Ap * rcp<R>(D));
+    x[i] = o[0] + a * P.v[0][0];
+    const R zn = o[1] - a * (Ap * rcp<R>(D));
     z[i] = zn;
     const double zd = zn, rd = (double)D * zd;
     acc[0] += rd * zd;
@@ -443,13 +502,16 @@ struct UpdOp {
 template <typename R>
 struct GradOp {
   static constexpr int NV = 2;
+  static constexpr int NO = 1;
+  using OT = double;
   const R* alpha;
   const R* mu;
   const R* T;
   double* G;
   double sx, sy, sz;
   __device__ R load(int k, long long i) const { return k == 0 ? mu[i] : T[i]; }
-  __device__ void point(const Pt<R, 2>& P, long long i, int) {
+  __device__ double own(int, long long i) const { return G[i]; }
+  __device__ void point(const Pt<R, 2>& P, const double (&o)[1], long long i, int) {
     const double a = P.a[0], m = P.v[0][0], t = P.v[1][0];
     const double s[7] = {0.0, sx, sx, sy, sy, sz, sz};
     double acc = 0.0;
@@ -459,7 +521,7 @@ struct GradOp {
       const double w = q / (a + q);
       acc += s[f] * (w * w) * ((t - (double)P.v[1][f]) * (m - (double)P.v[0][f]));
     }
-    G[i] -= acc;
+    G[i] = o[0] - acc;
   }
 };
 
@@ -467,12 +529,15 @@ struct GradOp {
 template <typename R>
 struct ApplyOp {
   static constexpr int NV = 1;
+  static constexpr int NO = 1;
+  using OT = R;
   const R* alpha;
   const R* xin;
   R* y;
   R sx, sy, sz;
   __device__ R load(int, long long i) const { return xin[i]; }
-  __device__ void point(const Pt<R, 1>& P, long long i, int) {
+  __device__ R own(int, long long) const { return R(0); }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
     R Av, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
     y[i] = Av;
@@ -519,7 +584,7 @@ __device__ __forceinline__ void top_cells(const Geom& g, int rank, int team, int
 template <typename R>
 __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
   const Geom& g = S.g;
-  int red = 0;
+  unsigned long long red = S.epoch_base;
   bool ok = true;
 
   // set-up
@@ -548,7 +613,8 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
   if (ok && bb == 0.0) {
     // b = 0: the solution is x = 0
     own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) { S.x[i] = R(0); });
-    ok &= team_barrier(S.bar, S.team, S.timeout_ticks, &sh.flag);
+    double v0[1] = {0.0};
+    ok &= team_sum<R, 1>(S, rank, red, v0, sh);
     rr = 0.0;
   } else {
     R* pc = S.p0;
@@ -584,10 +650,7 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
     }
   }
   if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
-  if (!ok) {
-    status |= kTimeout;
-    if (threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
-  }
+  if (!ok) status |= kTimeout;
 
   // epilogue
   if (S.mode == kForward) {
