@@ -139,6 +139,13 @@ nh_status nh_apply_A(nh_ctx *ctx, const float *alpha, const float *x, float *y, 
  * profile != 0 times every step kernel with HIP events (nh_stats.t_kernel_*). */
 nh_status nh_set_launch(nh_ctx *ctx, int team_blocks_max, int tile_z, int profile);
 
+/* Form of the preconditioned CG iteration (both reach the same fixed point):
+ * 0 = the textbook form with two team reductions per iteration (p.Ap, then
+ * r.z and |r|^2); 1 (default) = the single-reduction form of Chronopoulos and
+ * Gear, which carries A u and A p as extra vectors so that r.z, u.Au and
+ * |r|^2 are reduced together once per iteration. Frees the saved forward. */
+nh_status nh_set_cg_variant(nh_ctx *ctx, int variant);
+
 /* Time limit of the device-side team barrier in seconds (default 20). A
  * barrier that waits longer makes its kernel exit and the call return
  * NH_ETIMEOUT; the context stays usable. */

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "NH_OK", -1: "NH_EINVAL", -2: "NH_ENOMEM", -3: "NH_ESTATE", -
 
 EXPORTED = ["nh_create", "nh_set_grid", "nh_set_solver", "nh_forward", "nh_adjoint",
             "nh_forward_f64", "nh_adjoint_f64", "nh_get_state", "nh_apply_A", "nh_set_launch",
-            "nh_set_barrier_timeout", "nh_get_stats", "nh_last_error", "nh_destroy", "nh_copy_f32"]
+            "nh_set_cg_variant", "nh_set_barrier_timeout", "nh_get_stats", "nh_last_error", "nh_destroy", "nh_copy_f32"]
 
 
 class nh_stats(ctypes.Structure):
@@ -90,6 +90,7 @@ def load():
     lib.nh_get_state.argtypes = [vp, ip, vp]
     lib.nh_apply_A.argtypes = [vp, vp, vp, vp, dp]
     lib.nh_set_launch.argtypes = [vp, ip, ip, ip]
+    lib.nh_set_cg_variant.argtypes = [vp, ip]
     lib.nh_set_barrier_timeout.argtypes = [vp, dp]
     lib.nh_get_stats.argtypes = [vp, ctypes.POINTER(nh_stats)]
     lib.nh_last_error.argtypes = [vp]

@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,7 +25,6 @@
 namespace {
 
 using nh::Geom;
-using nh::kBlock;
 using nh::StepArgs;
 
 struct Buf {
@@ -59,7 +59,8 @@ struct nh_ctx {
   std::vector<double> saved_qt;
 
   // workspaces
-  Buf alpha, qxy, z, p0, p1, mu, w0, w1, traj, seg, slots, steps, flag;
+  Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, mu, w0, w1, traj, seg, slots, steps, flag;
+  int variant = 1;                           // CG form: 0 two reductions per iteration, 1 one
   unsigned long long launch_ctr = 0;         // makes every launch's reduction epochs unique
   size_t ws_bytes = 0, ws_peak = 0;
 
@@ -68,6 +69,10 @@ struct nh_ctx {
   nh_stats st{};
   std::string err = "";
   std::vector<hipEvent_t> ev;
+  // diagnostics: NH_TRACE_STEP=n prints phase timings of forward step n
+  int trace_step = 0;
+  int trace_rank = 0;
+  Buf trace;
 };
 
 namespace {
@@ -137,8 +142,8 @@ nh_status fill(nh_ctx* c, T* p, long long n, T v) {
   return NH_OK;
 }
 
-// Tile shape and team size for the current grid.
-void plan(nh_ctx* c, int occ) {
+// Tile shape and team size for the current grid, for workgroups of `block` threads.
+void plan(nh_ctx* c, int occ, int block) {
   Geom g{};
   g.nx = c->nx;
   g.ny = c->ny;
@@ -146,7 +151,7 @@ void plan(nh_ctx* c, int occ) {
   g.nxy = (long long)c->nx * c->ny;
   g.ng = g.nxy * c->nz;
   g.TX = c->nx > 32 ? 64 : (c->nx > 16 ? 32 : 16);
-  g.TY = kBlock / g.TX;
+  g.TY = block / g.TX;
   g.txs = g.TX == 64 ? 6 : (g.TX == 32 ? 5 : 4);
   g.ntx = (g.nx + g.TX - 1) / g.TX;
   g.nty = (g.ny + g.TY - 1) / g.TY;
@@ -172,7 +177,7 @@ void plan(nh_ctx* c, int occ) {
   c->geom = g;
   c->team = std::max(1, team);
   c->st.team_blocks = c->team;
-  c->st.block_threads = kBlock;
+  c->st.block_threads = block;
   c->st.tile_x = g.TX;
   c->st.tile_y = g.TY;
   c->st.tile_z = g.TZ;
@@ -192,7 +197,7 @@ nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) 
     e1 = c->ev[2 * slot_ev + 1];
     NH_HIP(c, hipEventRecord(e0, c->stream));
   }
-  NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(kBlock),
+  NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(nh::Cfg<R>::kBlock),
                                        args, 0, c->stream));
   if (c->profile) NH_HIP(c, hipEventRecord(e1, c->stream));
   (void)t_kernel;
@@ -232,6 +237,12 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.z = (R*)c->z.p;
   S.p0 = (R*)c->p0.p;
   S.p1 = (R*)c->p1.p;
+  S.u1 = (R*)c->u1.p;
+  S.w0 = (R*)c->vw0.p;
+  S.w1 = (R*)c->vw1.p;
+  S.s0 = (R*)c->vs0.p;
+  S.s1 = (R*)c->vs1.p;
+  S.variant = c->variant;
   S.slots = c->slots.p;
   S.epoch_base = (++c->launch_ctr) << 24;
   S.rtol2 = c->rtol * c->rtol;
@@ -240,6 +251,7 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.xcd_order = 1;
   S.err_flag = (int*)c->flag.p;
   S.timeout_ticks = (long long)(c->barrier_timeout_s * (double)c->wallclock_khz * 1000.0);
+  S.trace = nullptr;
 }
 
 // Per-step device outputs: [3][nsteps] iterations (forward, adjoint, recompute),
@@ -325,7 +337,7 @@ nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
 }
 
 // Per-voxel algorithmic bytes of one step kernel (R = vector element size).
-double step_bytes(const Geom& g, int R, int mode, int iters, bool first_step, bool surf, bool ckpt) {
+double step_bytes(const Geom& g, int R, int variant, int mode, int iters, bool first_step, bool surf, bool ckpt) {
   const double ng = (double)g.ng, nxy = (double)g.nxy;
   double b = 0;
   if (mode == nh::kForward) {
@@ -337,7 +349,12 @@ double step_bytes(const Geom& g, int R, int mode, int iters, bool first_step, bo
     b += 3.0 * R * ng + R * nxy;                  // read x, alpha, g^n; write z
     b += (3.0 * R + 16.0) * ng;                   // gradient: read mu, T, alpha; G read+write
   }
-  if (iters > 0) b += (10.0 * iters - 1.0) * R * ng;  // 4R+6R per iteration, no p_old on the first
+  if (iters > 0) {
+    if (variant == 0)
+      b += (10.0 * iters - 1.0) * R * ng;   // 4R + 6R per iteration, no p_old on the first
+    else
+      b += (11.0 * iters + 1.0) * R * ng;   // set-up 3R, first iteration 9R, then 11R each
+  }
   return b;
 }
 
@@ -347,7 +364,21 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   NH_TRY(ensure(c, c->alpha, vb));
   NH_TRY(ensure(c, c->z, vb));
   NH_TRY(ensure(c, c->p0, vb));
-  NH_TRY(ensure(c, c->p1, vb));
+  if (c->variant == 0) {
+    NH_TRY(ensure(c, c->p1, vb));
+    NH_TRY(release(c, c->u1));
+    NH_TRY(release(c, c->vw0));
+    NH_TRY(release(c, c->vw1));
+    NH_TRY(release(c, c->vs0));
+    NH_TRY(release(c, c->vs1));
+  } else {
+    NH_TRY(release(c, c->p1));
+    NH_TRY(ensure(c, c->u1, vb));
+    NH_TRY(ensure(c, c->vw0, vb));
+    NH_TRY(ensure(c, c->vw1, vb));
+    NH_TRY(ensure(c, c->vs0, vb));
+    NH_TRY(ensure(c, c->vs1, vb));
+  }
   const size_t slot_bytes = sizeof(nh::Slot) * ((size_t)c->team + 1);
   if (c->slots.bytes < slot_bytes || !c->slots.p) {
     NH_TRY(ensure(c, c->slots, slot_bytes));
@@ -379,7 +410,41 @@ nh_status forward_step(nh_ctx* c, int n, const R* xprev, R* x, const R* q_xy, do
   S.out_iters = o.iters;
   S.out_relres = o.relres;
   S.out_status = o.status;
-  return launch_step<R>(c, S, ev_slot, nullptr);
+  const bool tracing = region == 0 && n == c->trace_step;
+  const int cap = c->trace_rank < 0 ? 256 : 4096;
+  const size_t tn = c->trace_rank < 0 ? (size_t)cap * c->team : (size_t)cap;
+  if (tracing) {
+    NH_TRY(ensure(c, c->trace, sizeof(long long) * tn));
+    NH_HIP(c, hipMemsetAsync(c->trace.p, 0, c->trace.bytes, c->stream));
+    S.trace = (long long*)c->trace.p;
+    S.trace_rank = c->trace_rank < 0 ? -1 : std::min(c->trace_rank, c->team - 1);
+    S.trace_cap = cap;
+  }
+  NH_TRY(launch_step<R>(c, S, ev_slot, nullptr));
+  if (tracing) {
+    std::vector<long long> tall(tn);
+    NH_HIP(c, hipMemcpyAsync(tall.data(), c->trace.p, sizeof(long long) * tn, hipMemcpyDeviceToHost, c->stream));
+    NH_HIP(c, hipStreamSynchronize(c->stream));
+    // stamps: start, set-up sweep(s) and reduction(s), then per iteration its
+    // sweep(s) and reduction(s): two pairs (variant 0) or one pair (variant 1)
+    const double us = 1e3 / (double)c->wallclock_khz;
+    const int head = c->variant == 0 ? 3 : 5, per = c->variant == 0 ? 4 : 2;
+    const int nranks = c->trace_rank < 0 ? c->team : 1;
+    for (int r = 0; r < nranks; ++r) {
+      const long long* t = tall.data() + (size_t)r * cap;
+      int m = 0;
+      while (m < cap && t[m] != 0) ++m;
+      std::vector<double> acc(per, 0.0);
+      const int its = m > head ? (m - head) / per : 0;
+      for (int k = 0; k < its; ++k)
+        for (int j = 0; j < per; ++j) acc[j] += (t[head + per * k + j] - t[head + per * k + j - 1]) * us;
+      std::fprintf(stderr, "[nh trace] step %d rank %d variant %d: set-up %.2f us, %d iterations, mean us per phase:",
+                   n, nranks > 1 ? r : S.trace_rank, c->variant, m >= head ? (t[head - 1] - t[0]) * us : 0.0, its);
+      for (int j = 0; j < per; ++j) std::fprintf(stderr, " %.2f", its ? acc[j] / its : 0.0);
+      std::fprintf(stderr, "\n");
+    }
+  }
+  return NH_OK;
 }
 
 template <typename R>
@@ -395,7 +460,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     if (!std::isfinite(q_t[i])) return fail(c, NH_EINVAL, "q_t holds a non-finite value");
 
   drop_forward(c);
-  plan(c, occupancy<R>(c));
+  plan(c, occupancy<R>(c), nh::Cfg<R>::kBlock);
   NH_TRY(ensure_common<R>(c, nsteps));
   NH_TRY(ensure_events(c));
   const Geom& g = c->geom;
@@ -471,7 +536,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     NH_HIP(c, hipStreamSynchronize(c->stream));
     double bytes = 0;
     for (int n = 1; n <= nsteps; ++n)
-      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1], n == 1, true,
+      bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, it[n - 1], n == 1, true,
                           k > 0 && n % k == 0 && n < nsteps);
     c->st.bytes_alg_fwd = bytes;
   }
@@ -571,7 +636,8 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
   std::vector<int> it(N);
   NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 1, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
   NH_HIP(c, hipStreamSynchronize(c->stream));
-  for (int n = 1; n <= N; ++n) bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1], false, false, false);
+  for (int n = 1; n <= N; ++n)
+    bytes += step_bytes(g, sizeof(R), c->variant, nh::kAdjoint, it[n - 1], false, false, false);
   c->st.recompute_iters = 0;
   if (k > 0) {
     long long rsum = 0;
@@ -583,7 +649,8 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     std::vector<int> ir(N);
     NH_HIP(c, hipMemcpyAsync(ir.data(), step_out(c, 2, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
     NH_HIP(c, hipStreamSynchronize(c->stream));
-    for (int n = 1; n <= N; ++n) bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1], n == 1, false, false);
+    for (int n = 1; n <= N; ++n)
+      bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, ir[n - 1], n == 1, false, false);
   }
   c->st.bytes_alg_adj = bytes;
   c->st.workspace_bytes = c->ws_bytes;
@@ -616,13 +683,17 @@ nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
     c->wallclock_khz = khz;
   int o32 = 0, o64 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, (const void*)nh::step_kernel<float>, kBlock, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, (const void*)nh::step_kernel<double>, kBlock, 0) != hipSuccess) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o32, (const void*)nh::step_kernel<float>,
+                                                   nh::Cfg<float>::kBlock, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&o64, (const void*)nh::step_kernel<double>,
+                                                   nh::Cfg<double>::kBlock, 0) != hipSuccess) {
     delete c;
     return NH_EHIP;
   }
   c->occ_f32 = std::max(1, o32);
   c->occ_f64 = std::max(1, o64);
+  if (const char* e = std::getenv("NH_TRACE_STEP")) c->trace_step = std::atoi(e);
+  if (const char* e = std::getenv("NH_TRACE_RANK")) c->trace_rank = std::atoi(e);
   *out = c;
   return NH_OK;
 }
@@ -642,7 +713,7 @@ nh_status nh_set_grid(nh_ctx* c, int nx, int ny, int nz, double hx, double hy, d
   NH_TRY(release(c, c->p0));
   NH_TRY(release(c, c->p1));
   NH_TRY(release(c, c->mu));
-  plan(c, c->occ_f32);
+  plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
   return NH_OK;
 }
 
@@ -703,10 +774,10 @@ nh_status nh_apply_A(nh_ctx* c, const float* alpha, const float* x, float* y, do
   if (!alpha || !x || !y) return fail(c, NH_EINVAL, "null pointer argument");
   if (x == y) return fail(c, NH_EINVAL, "y must not alias x");
   if (!(dt >= 0) || !std::isfinite(dt)) return fail(c, NH_EINVAL, "dt must be finite and >= 0");
-  plan(c, c->occ_f32);
+  plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
   const Geom& g = c->geom;
   const int blocks = std::min(g.ntiles, std::max(1, c->occ_f32 * c->num_cu));
-  hipLaunchKernelGGL(nh::apply_kernel<float>, dim3(blocks), dim3(kBlock), 0, c->stream, g, alpha, x, y,
+  hipLaunchKernelGGL(nh::apply_kernel<float>, dim3(blocks), dim3(nh::Cfg<float>::kBlock), 0, c->stream, g, alpha, x, y,
                      (float)(2.0 * dt / (c->hx * c->hx)), (float)(2.0 * dt / (c->hy * c->hy)),
                      (float)(2.0 * dt / (c->hz * c->hz)));
   NH_HIP(c, hipGetLastError());
@@ -721,7 +792,15 @@ nh_status nh_set_launch(nh_ctx* c, int team_blocks_max, int tile_z, int profile)
   c->team_max = team_blocks_max;
   c->tile_z = tile_z;
   c->profile = profile != 0;
-  if (c->grid_set) plan(c, c->occ_f32);
+  if (c->grid_set) plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
+  return NH_OK;
+}
+
+nh_status nh_set_cg_variant(nh_ctx* c, int variant) {
+  if (!c) return NH_EINVAL;
+  if (variant != 0 && variant != 1) return fail(c, NH_EINVAL, "variant must be 0 or 1");
+  drop_forward(c);
+  c->variant = variant;
   return NH_OK;
 }
 
@@ -749,7 +828,8 @@ void nh_destroy(nh_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  Buf* bufs[] = {&c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->mu, &c->w0, &c->w1, &c->traj,
+  Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
+                 &c->vs0, &c->vs1, &c->mu, &c->w0, &c->w1, &c->traj,
                  &c->seg, &c->slots, &c->steps, &c->flag};
   for (Buf* b : bufs) release(c, *b);
   for (auto e : c->ev) (void)hipEventDestroy(e);

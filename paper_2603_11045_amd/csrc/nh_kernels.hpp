@@ -34,9 +34,14 @@
 
 namespace nh {
 
-constexpr int kBlock = 512;                 // threads per workgroup (8 wave64)
-constexpr int kWaves = kBlock / 64;
-constexpr int kMaxPlane = 660;              // max (TX+2)*(TY+2): TX=64,TY=8 -> 66*10
+// Threads per workgroup: 1024 (16 wave64, one workgroup per CU) for the
+// FP32 path, 512 for the FP64 path, whose kernel needs more registers.
+template <typename R> struct Cfg;
+template <> struct Cfg<float> { static constexpr int kBlock = 1024; };
+template <> struct Cfg<double> { static constexpr int kBlock = 512; };
+constexpr int kMaxBlock = 1024;
+constexpr int kMaxWaves = kMaxBlock / 64;
+constexpr int kMaxPlane = 1188;             // max (TX+2)*(TY+2) with TX*TY <= 1024: 66*18
 constexpr int kNumRed = 4;                  // doubles per workgroup partial slot
 
 enum StepMode : int { kForward = 0, kAdjoint = 1 };
@@ -59,6 +64,12 @@ struct StepArgs {
   R* z;                                     // preconditioned residual
   R* p0;                                    // search direction, ping-pong pair
   R* p1;
+  R* u1;                                    // single-reduction variant: second u buffer,
+  R* w0;                                    //   A u / D and A p / D ping-pong pairs
+  R* w1;
+  R* s0;
+  R* s1;
+  int variant;                              // 0: two reductions per iteration, 1: one
   const R* top_src;                         // [ny][nx] added on k = 0 (forward q_xy, adjoint g^n)
   R top_scale;                              // forward dt*q_t[n-1], adjoint 1
   R* surf_out;                              // forward: frame of T^n on k = 0 (or null)
@@ -77,6 +88,9 @@ struct StepArgs {
   int* out_status;
   int* err_flag;                            // |= kTimeout by any workgroup whose wait timed out
   long long timeout_ticks;                  // barrier time limit in wall-clock ticks
+  long long* trace;                         // optional: wall-clock stamps of phase ends
+  int trace_rank;                           // workgroup whose thread 0 writes the stamps
+  int trace_cap;                            // capacity of trace in entries
 };
 
 // ---------------------------------------------------------------------------
@@ -85,6 +99,11 @@ struct StepArgs {
 template <typename R> __device__ __forceinline__ R rcp(R v);
 template <> __device__ __forceinline__ float rcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double rcp<double>(double v) { return 1.0 / v; }
+
+// Store of a sweep output. (Non-temporal stores were measured slower here:
+// they bypass the last-level cache that the next sweep reads from.)
+template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) { *p = v; }
 
 // dt * c_f = s * a*b/(a+b) with s = 2 dt / h^2 (Prop. 1); b = 0 outside the grid gives 0.
 template <typename R>
@@ -117,13 +136,13 @@ template <typename R>
 struct Smem {
   R a[kMaxPlane];
   R v[2][kMaxPlane];
-  double red[kWaves][kNumRed];
+  double red[kMaxWaves][kNumRed];
   double bc[kNumRed];
   int flag;
 };
 
-// Sum NV doubles over the workgroup; the result lands in every thread's v.
-template <int NV>
+// Sum NV doubles over the workgroup of WAVES wave64; the result lands in every thread's v.
+template <int NV, int WAVES>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed], double* bc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -137,7 +156,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       double s = 0.0;
-      for (int w = 0; w < kWaves; ++w) s += red[w][i];
+      for (int w = 0; w < WAVES; ++w) s += red[w][i];
       bc[i] = s;
     }
   }
@@ -157,7 +176,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
 template <typename R, int NV>
 __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigned long long& epoch,
                                          double (&v)[NV], Smem<R>& sh) {
-  block_sum<NV>(v, sh.red, sh.bc);
+  constexpr int BLOCK = Cfg<R>::kBlock;
+  block_sum<NV, BLOCK / 64>(v, sh.red, sh.bc);
   if (S.team == 1) return true;
   const unsigned long long e = ++epoch;
   Slot* slots = (Slot*)S.slots;
@@ -188,7 +208,7 @@ __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigne
     double s[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) s[i] = 0.0;
-    for (int b = threadIdx.x; b < S.team; b += kBlock) {
+    for (int b = threadIdx.x; b < S.team; b += BLOCK) {
       if (b == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) s[i] += v[i];
@@ -203,7 +223,7 @@ __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigne
       for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
     }
     ok = __syncthreads_and(ok);
-    block_sum<NV>(s, sh.red, sh.bc);
+    block_sum<NV, BLOCK / 64>(s, sh.red, sh.bc);
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
@@ -255,12 +275,18 @@ struct Pt {
 };
 
 // March one tile along z. Op supplies: NV staged vectors (load(k, i)), NO
-// operands of type OT read only at the cell itself (own(k, i), prefetched one
-// plane ahead without staging), alpha, and point(P, o, i, kz).
+// operands of type OT read only at the cell itself (own(k, i), not staged),
+// alpha, and point(P, o, i, kz). Loads run kPrefetch planes ahead of use
+// (register queues), so each thread keeps several planes of loads in flight
+// across the two workgroup barriers of a plane.
+constexpr int kPrefetch = 3;
+
 template <typename R, typename Op>
 __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op, Smem<R>& sh) {
   constexpr int NV = Op::NV;
   constexpr int NO = Op::NO;
+  constexpr int PD = kPrefetch;
+  constexpr int QS = PD + 2;                // staged own column: planes z-1 .. z+PD
   using OT = typename Op::OT;
   const int tid = threadIdx.x;
   const int TX = g.TX, TY = g.TY, PW = TX + 2;
@@ -286,109 +312,135 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
     }
   }
 
-  R am = 0, ac = 0, ap = 0, ha = 0;
-  R vm[NV], vc[NV], vp[NV], hv[NV];
-  OT oc[NO];
+  // register queues; index 0 is the oldest plane
+  R qa[QS], qv[QS][NV];                     // own column, planes z-1 .. z+PD
+  R ha[PD + 1], hv[PD + 1][NV];             // halo cell, planes z .. z+PD
+  OT qo[PD + 1][NO];                        // own-only operands, planes z .. z+PD
 #pragma unroll
-  for (int k = 0; k < NV; ++k) { vm[k] = 0; vc[k] = 0; vp[k] = 0; hv[k] = 0; }
+  for (int j = 0; j < QS; ++j) {
+    qa[j] = 0;
 #pragma unroll
-  for (int k = 0; k < NO; ++k) oc[k] = 0;
-
-  if (own) {
-    if (T.z0 > 0) {
-      const long long i = col + (long long)(T.z0 - 1) * g.nxy;
-      am = op.alpha[i];
+    for (int k = 0; k < NV; ++k) qv[j][k] = 0;
+  }
 #pragma unroll
-      for (int k = 0; k < NV; ++k) vm[k] = op.load(k, i);
-    }
-    {
-      const long long i = col + (long long)T.z0 * g.nxy;
-      ac = op.alpha[i];
+  for (int j = 0; j <= PD; ++j) {
+    ha[j] = 0;
 #pragma unroll
-      for (int k = 0; k < NV; ++k) vc[k] = op.load(k, i);
+    for (int k = 0; k < NV; ++k) hv[j][k] = 0;
 #pragma unroll
-      for (int k = 0; k < NO; ++k) oc[k] = op.own(k, i);
-    }
-    if (T.z0 + 1 < g.nz) {
-      const long long i = col + (long long)(T.z0 + 1) * g.nxy;
-      ap = op.alpha[i];
+    for (int k = 0; k < NO; ++k) qo[j][k] = 0;
+  }
+  // fill: own planes z0-1 .. z0+PD-1, own-only and halo planes z0 .. z0+PD-1
 #pragma unroll
-      for (int k = 0; k < NV; ++k) vp[k] = op.load(k, i);
+  for (int j = 0; j < QS - 1; ++j) {
+    const int z = T.z0 - 1 + j;
+    if (own && z >= 0 && z < g.nz) {
+      const long long i = col + (long long)z * g.nxy;
+      qa[j] = op.alpha[i];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) qv[j][k] = op.load(k, i);
     }
   }
-  if (hin) {
-    const long long i = hcol + (long long)T.z0 * g.nxy;
-    ha = op.alpha[i];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) hv[k] = op.load(k, i);
+  for (int j = 0; j < PD; ++j) {
+    const int z = T.z0 + j;
+    if (z < T.z1) {
+      const long long io = col + (long long)z * g.nxy;
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < NO; ++k) qo[j][k] = op.own(k, io);
+      }
+      if (hin) {
+        const long long ih = hcol + (long long)z * g.nxy;
+        ha[j] = op.alpha[ih];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) hv[j][k] = op.load(k, ih);
+      }
+    }
   }
 
   for (int z = T.z0; z < T.z1; ++z) {
-    // prefetch: staged own column two planes ahead, own-only operands and
-    // the halo one plane ahead
-    R an = 0, han = 0;
-    R vn[NV], hvn[NV];
-    OT on[NO];
+    // issue the loads of plane z+PD (own staged column, own-only operands, halo)
+    {
+      const int zs = z + PD;
+      qa[QS - 1] = 0;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { vn[k] = 0; hvn[k] = 0; }
+      for (int k = 0; k < NV; ++k) qv[QS - 1][k] = 0;
+      if (own && zs < g.nz) {
+        const long long i = col + (long long)zs * g.nxy;
+        qa[QS - 1] = op.alpha[i];
 #pragma unroll
-    for (int k = 0; k < NO; ++k) on[k] = 0;
-    if (own && z + 2 < g.nz) {
-      const long long i = col + (long long)(z + 2) * g.nxy;
-      an = op.alpha[i];
+        for (int k = 0; k < NV; ++k) qv[QS - 1][k] = op.load(k, i);
+      }
+      const int zh = z + PD;
+      ha[PD] = 0;
 #pragma unroll
-      for (int k = 0; k < NV; ++k) vn[k] = op.load(k, i);
-    }
-    if (own && z + 1 < T.z1) {
-      const long long i = col + (long long)(z + 1) * g.nxy;
+      for (int k = 0; k < NV; ++k) hv[PD][k] = 0;
 #pragma unroll
-      for (int k = 0; k < NO; ++k) on[k] = op.own(k, i);
-    }
-    if (hin && z + 1 < T.z1) {
-      const long long i = hcol + (long long)(z + 1) * g.nxy;
-      han = op.alpha[i];
+      for (int k = 0; k < NO; ++k) qo[PD][k] = 0;
+      if (zh < T.z1) {
+        if (own) {
+          const long long i = col + (long long)zh * g.nxy;
 #pragma unroll
-      for (int k = 0; k < NV; ++k) hvn[k] = op.load(k, i);
+          for (int k = 0; k < NO; ++k) qo[PD][k] = op.own(k, i);
+        }
+        if (hin) {
+          const long long i = hcol + (long long)zh * g.nxy;
+          ha[PD] = op.alpha[i];
+#pragma unroll
+          for (int k = 0; k < NV; ++k) hv[PD][k] = op.load(k, i);
+        }
+      }
     }
 
     __syncthreads();
-    sh.a[oslot] = ac;
+    sh.a[oslot] = qa[1];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sh.v[k][oslot] = vc[k];
+    for (int k = 0; k < NV; ++k) sh.v[k][oslot] = qv[1][k];
     if (hslot >= 0) {
-      sh.a[hslot] = ha;
+      sh.a[hslot] = ha[0];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) sh.v[k][hslot] = hv[k];
+      for (int k = 0; k < NV; ++k) sh.v[k][hslot] = hv[0][k];
     }
     __syncthreads();
 
     if (own) {
       Pt<R, NV> P;
-      P.a[0] = ac;
+      P.a[0] = qa[1];
       P.a[1] = sh.a[oslot - 1];
       P.a[2] = sh.a[oslot + 1];
       P.a[3] = sh.a[oslot - PW];
       P.a[4] = sh.a[oslot + PW];
-      P.a[5] = am;
-      P.a[6] = ap;
+      P.a[5] = qa[0];
+      P.a[6] = qa[2];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        P.v[k][0] = vc[k];
+        P.v[k][0] = qv[1][k];
         P.v[k][1] = sh.v[k][oslot - 1];
         P.v[k][2] = sh.v[k][oslot + 1];
         P.v[k][3] = sh.v[k][oslot - PW];
         P.v[k][4] = sh.v[k][oslot + PW];
-        P.v[k][5] = vm[k];
-        P.v[k][6] = vp[k];
+        P.v[k][5] = qv[0][k];
+        P.v[k][6] = qv[2][k];
       }
-      op.point(P, oc, col + (long long)z * g.nxy, z);
+      op.point(P, qo[0], col + (long long)z * g.nxy, z);
     }
 
-    am = ac; ac = ap; ap = an; ha = han;
+    // advance the queues by one plane
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { vm[k] = vc[k]; vc[k] = vp[k]; vp[k] = vn[k]; hv[k] = hvn[k]; }
+    for (int j = 0; j < QS - 1; ++j) {
+      qa[j] = qa[j + 1];
 #pragma unroll
-    for (int k = 0; k < NO; ++k) oc[k] = on[k];
+      for (int k = 0; k < NV; ++k) qv[j][k] = qv[j + 1][k];
+    }
+#pragma unroll
+    for (int j = 0; j < PD; ++j) {
+      ha[j] = ha[j + 1];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) hv[j][k] = hv[j + 1][k];
+#pragma unroll
+      for (int k = 0; k < NO; ++k) qo[j][k] = qo[j + 1][k];
+    }
   }
 }
 
@@ -437,8 +489,8 @@ struct InitOp {
     if (kz == 0) b += top_scale * top[i];
     const R r = b - Av;
     const R zz = r * rcp<R>(D);
-    z[i] = zz;
-    if (xw) xw[i] = P.v[0][0];
+    st_nt(z + i, zz);
+    if (xw) st_nt(xw + i, P.v[0][0]);
     const double bd = b, rd = r;
     acc[0] += bd * bd;
     acc[1] += rd * (double)zz;
@@ -465,7 +517,7 @@ struct DirOp {
   __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
     R Av, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
-    pnew[i] = P.v[0][0];
+    st_nt(pnew + i, P.v[0][0]);
     acc[0] += (double)P.v[0][0] * (double)Av;
   }
 };
@@ -488,9 +540,9 @@ struct UpdOp {
   __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int) {
     R Ap, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Ap, D);
-    x[i] = o[0] + a * P.v[0][0];
+    st_nt(x + i, o[0] + a * P.v[0][0]);
     const R zn = o[1] - a * (Ap * rcp<R>(D));
-    z[i] = zn;
+    st_nt(z + i, zn);
     const double zd = zn, rd = (double)D * zd;
     acc[0] += rd * zd;
     acc[1] += rd * rd;
@@ -521,7 +573,84 @@ struct GradOp {
       const double w = q / (a + q);
       acc += s[f] * (w * w) * ((t - (double)P.v[1][f]) * (m - (double)P.v[0][f]));
     }
-    G[i] = o[0] - acc;
+    st_nt(G + i, o[0] - acc);
+  }
+};
+
+// Single-reduction set-up, second part: w = A u, store w / D, accumulate u.w.
+template <typename R>
+struct WOp {
+  static constexpr int NV = 1;
+  static constexpr int NO = 1;
+  using OT = R;
+  const R* alpha;
+  const R* u;
+  R* what;
+  R sx, sy, sz;
+  double acc[1];
+  __device__ R load(int, long long i) const { return u[i]; }
+  __device__ R own(int, long long) const { return R(0); }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
+    R w, D;
+    stencil<R, 1>(P, 0, sx, sy, sz, w, D);
+    st_nt(what + i, w * rcp<R>(D));
+    acc[0] += (double)P.v[0][0] * (double)w;
+  }
+};
+
+// One iteration of the single-reduction (Chronopoulos-Gear) form of the
+// preconditioned CG, with u = r / D, w = A u and s = A p kept as w/D, s/D:
+//   s_i = w_i + b s_{i-1},  p_i = u_i + b p_{i-1},  x += a p_i,
+//   u_{i+1} = u_i - a s_i   (staged: needed at the halo for the stencil),
+//   w_{i+1} = A u_{i+1};  accumulate u.r = D u^2, u.w and |r|^2 = (D u)^2.
+// The next a, b follow from these three sums alone, so an iteration needs a
+// single team reduction.
+template <typename R>
+struct FusedOp {
+  static constexpr int NV = 1;
+  static constexpr int NO = 5;
+  using OT = R;
+  const R* alpha;
+  const R* u;                               // u_i
+  const R* wh;                              // w_i / D
+  const R* sho;                             // s_{i-1} / D
+  R* x;
+  R* p;                                     // p_{i-1} in, p_i out
+  R* un;                                    // u_{i+1}
+  R* whn;                                   // w_{i+1} / D
+  R* shn;                                   // s_i / D
+  R a, b;
+  int first;
+  R sx, sy, sz;
+  double acc[3];
+  __device__ R load(int, long long i) const {
+    const R sv = first ? wh[i] : wh[i] + b * sho[i];
+    return u[i] - a * sv;
+  }
+  __device__ R own(int k, long long i) const {
+    switch (k) {
+      case 0: return x[i];
+      case 1: return first ? R(0) : p[i];
+      case 2: return u[i];
+      case 3: return wh[i];
+      default: return first ? R(0) : sho[i];
+    }
+  }
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[5], long long i, int) {
+    const R sv = first ? o[3] : o[3] + b * o[4];
+    const R pv = first ? o[2] : o[2] + b * o[1];
+    st_nt(x + i, o[0] + a * pv);
+    st_nt(p + i, pv);
+    st_nt(shn + i, sv);
+    R w, D;
+    stencil<R, 1>(P, 0, sx, sy, sz, w, D);
+    const R uv = P.v[0][0];
+    st_nt(un + i, uv);
+    st_nt(whn + i, w * rcp<R>(D));
+    const double ud = uv, Dd = D, rd = Dd * ud;
+    acc[0] += rd * ud;
+    acc[1] += (double)w * ud;
+    acc[2] += rd * rd;
   }
 };
 
@@ -586,6 +715,15 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
   const Geom& g = S.g;
   unsigned long long red = S.epoch_base;
   bool ok = true;
+  int ntr = 0;
+  // trace_rank >= 0: that workgroup stamps into trace[0..cap); -1: every
+  // workgroup stamps into its own window of cap entries
+  const bool tr = S.trace && (rank == S.trace_rank || S.trace_rank < 0) && threadIdx.x == 0;
+  long long* trace = S.trace ? S.trace + (S.trace_rank < 0 ? (long long)rank * S.trace_cap : 0) : nullptr;
+  auto stamp = [&]() {
+    if (tr && ntr < S.trace_cap) trace[ntr++] = wall_clock64();
+  };
+  stamp();
 
   // set-up
   InitOp<R> init;
@@ -604,8 +742,10 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
     init.xw = nullptr;
   }
   sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
+  stamp();
   double v3[3] = {init.acc[0], init.acc[1], init.acc[2]};
   ok &= team_sum<R, 3>(S, rank, red, v3, sh);
+  stamp();
   const double bb = v3[0];
   double rz = v3[1], rr = v3[2];
 
@@ -616,7 +756,7 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
     double v0[1] = {0.0};
     ok &= team_sum<R, 1>(S, rank, red, v0, sh);
     rr = 0.0;
-  } else {
+  } else if (S.variant == 0) {
     R* pc = S.p0;
     R* pn = S.p1;
     double rz_old = 1.0;
@@ -629,8 +769,10 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
       A.sx = S.sx; A.sy = S.sy; A.sz = S.sz;
       A.acc[0] = 0.0;
       sweep<R>(g, rank, S.team, S.xcd_order, A, sh);
+      stamp();
       double v1[1] = {A.acc[0]};
       ok &= team_sum<R, 1>(S, rank, red, v1, sh);
+      stamp();
       if (!ok) break;
       const double alpha_cg = rz / v1[0];
 
@@ -640,13 +782,57 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
       B.sx = S.sx; B.sy = S.sy; B.sz = S.sz;
       B.acc[0] = B.acc[1] = 0.0;
       sweep<R>(g, rank, S.team, S.xcd_order, B, sh);
+      stamp();
       double v2[2] = {B.acc[0], B.acc[1]};
       ok &= team_sum<R, 2>(S, rank, red, v2, sh);
+      stamp();
       rz_old = rz;
       rz = v2[0];
       rr = v2[1];
       ++it;
       R* t = pc; pc = pn; pn = t;
+    }
+  } else if (ok && rr > S.rtol2 * bb) {
+    // single-reduction form: w_0 = A u_0, then one fused sweep per iteration
+    WOp<R> W;
+    W.alpha = S.alpha; W.u = S.z; W.what = S.w0;
+    W.sx = S.sx; W.sy = S.sy; W.sz = S.sz;
+    W.acc[0] = 0.0;
+    sweep<R>(g, rank, S.team, S.xcd_order, W, sh);
+    stamp();
+    double vd[1] = {W.acc[0]};
+    ok &= team_sum<R, 1>(S, rank, red, vd, sh);
+    stamp();
+    double gam = rz;
+    double a_cg = gam / vd[0], b_cg = 0.0;
+    R* ub[2] = {S.z, S.u1};
+    R* wb[2] = {S.w0, S.w1};
+    R* sb[2] = {S.s0, S.s1};
+    int cur = 0;
+    while (ok) {
+      if (it >= S.max_iter) { status |= kNoConv; break; }
+      FusedOp<R> F;
+      F.alpha = S.alpha;
+      F.u = ub[cur]; F.wh = wb[cur]; F.sho = sb[cur];
+      F.x = S.x; F.p = S.p0;
+      F.un = ub[cur ^ 1]; F.whn = wb[cur ^ 1]; F.shn = sb[cur ^ 1];
+      F.a = (R)a_cg; F.b = (R)b_cg;
+      F.first = (it == 0);
+      F.sx = S.sx; F.sy = S.sy; F.sz = S.sz;
+      F.acc[0] = F.acc[1] = F.acc[2] = 0.0;
+      sweep<R>(g, rank, S.team, S.xcd_order, F, sh);
+      stamp();
+      double v3n[3] = {F.acc[0], F.acc[1], F.acc[2]};
+      ok &= team_sum<R, 3>(S, rank, red, v3n, sh);
+      stamp();
+      ++it;
+      cur ^= 1;
+      rr = v3n[2];
+      if (!(rr > S.rtol2 * bb)) break;
+      const double gn = v3n[0], dn = v3n[1];
+      b_cg = gn / gam;
+      a_cg = gn / (dn - b_cg * gn / a_cg);
+      gam = gn;
     }
   }
   if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
@@ -678,13 +864,13 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock, 2) step_kernel(StepArgs<R> S) {
+__global__ void __launch_bounds__(Cfg<R>::kBlock, 1) step_kernel(StepArgs<R> S) {
   __shared__ Smem<R> sh;
   run_step<R>(S, blockIdx.x, sh);
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock, 2) apply_kernel(Geom g, const R* alpha, const R* x, R* y,
+__global__ void __launch_bounds__(Cfg<R>::kBlock, 1) apply_kernel(Geom g, const R* alpha, const R* x, R* y,
                                                           R sx, R sy, R sz) {
   __shared__ Smem<R> sh;
   ApplyOp<R> op;

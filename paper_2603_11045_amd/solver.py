@@ -49,7 +49,7 @@ class Solver:
                  rtol: float = 1e-6, max_iter: int = 1000, checkpoint_every: int = 0,
                  precision: str = "f32", device: Optional[int] = None,
                  stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
-                 tile_z: int = 0, profile: bool = False):
+                 tile_z: int = 0, profile: bool = False, cg_variant: int = 1):
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.lib = _lib.load()
@@ -64,6 +64,7 @@ class Solver:
                                   ctypes.c_void_p(self.stream.cuda_stream)), None, "nh_create")
         _check(self.lib.nh_set_grid(self._ctx, self.nx, self.ny, self.nz, *self.h), self._ctx,
                "nh_set_grid")
+        self.set_cg_variant(cg_variant)
         self.set_solver(rtol, max_iter, checkpoint_every)
         if team_blocks_max or tile_z or profile:
             self.set_launch(team_blocks_max, tile_z, profile)
@@ -80,6 +81,10 @@ class Solver:
     def set_launch(self, team_blocks_max: int = 0, tile_z: int = 0, profile: bool = False):
         _check(self.lib.nh_set_launch(self._ctx, int(team_blocks_max), int(tile_z), int(bool(profile))),
                self._ctx, "nh_set_launch")
+
+    def set_cg_variant(self, variant: int):
+        _check(self.lib.nh_set_cg_variant(self._ctx, int(variant)), self._ctx, "nh_set_cg_variant")
+        self.cg_variant = int(variant)
 
     def set_barrier_timeout(self, seconds: float):
         _check(self.lib.nh_set_barrier_timeout(self._ctx, float(seconds)), self._ctx,

@@ -39,12 +39,13 @@ def to_dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None):
+def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=1):
     """Forward (and adjoint when gs is given) of workload w on the GPU."""
     prec = precision or w.precision
     dt_t = torch.float32 if prec == "f32" else torch.float64
     s = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=rtol or w.rtol, max_iter=5000,
-               checkpoint_every=checkpoint_every, precision=prec, team_blocks_max=team, tile_z=tile_z)
+               checkpoint_every=checkpoint_every, precision=prec, team_blocks_max=team, tile_z=tile_z,
+               cg_variant=variant)
     S = s.forward(to_dev(w.alpha, dt_t), to_dev(w.q_xy, dt_t), w.q_t, w.dt, w.nsteps)
     out = dict(S=S.cpu().numpy().astype(np.float64), stats_fwd=s.stats(), solver=s)
     if gs is not None:
@@ -87,16 +88,17 @@ SMALL = [
 
 @pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_t{c[5]}_z{c[6]}" for c in SMALL])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_small_forward_adjoint(case, precision):
+@pytest.mark.parametrize("variant", [1, 0])
+def test_small_forward_adjoint(case, precision, variant):
     nx, ny, nz, nsteps, seed, team, tz = case
-    say("small", case, precision)
+    say("small", case, precision, "variant", variant)
     w = wl.small_problem(nx, ny, nz, nsteps, seed=seed, dt=2.5, precision=precision,
                          rtol=1e-12 if precision == "f64" else 1e-7)
     gs = wl.random_surface_weights(nsteps, ny, nx, seed=100 + seed)
     src = orc.source_series(w.q_xy, w.q_t)
     S_o, T_o, _ = orc.forward(w.alpha, src, w.dt)
     G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt)
-    out = run_gpu(w, team=team, tile_z=tz, gs=gs)
+    out = run_gpu(w, team=team, tile_z=tz, gs=gs, variant=variant)
     tol_s, tol_g = (1e-9, 1e-8) if precision == "f64" else (1e-5, 1e-4)
     es, eg = rel_l2(out["S"], S_o), rel_l2(out["G"], G_o)
     say("  rel-L2 S", es, "G", eg, "team", out["stats_fwd"]["team_blocks"])
@@ -124,10 +126,11 @@ def mixed_ref():
 
 
 @pytest.mark.timeout(600)
-def test_mixed_64x64x32_forward_and_adjoint(mixed_ref):
+@pytest.mark.parametrize("variant", [1, 0])
+def test_mixed_64x64x32_forward_and_adjoint(mixed_ref, variant):
     w, ref = mixed_ref
-    say("gpu", w.name)
-    out = run_gpu(w, gs=ref["gs"].astype(np.float32))
+    say("gpu", w.name, "variant", variant)
+    out = run_gpu(w, gs=ref["gs"].astype(np.float32), variant=variant)
     es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
     mx = float(np.abs(out["G"] - ref["G"]).max() / np.abs(ref["G"]).max())
     say("  rel-L2 S", es, "G", eg, "max|dG|/max|G|", mx, "iters", out["stats_fwd"]["fwd_iters"],
@@ -137,14 +140,15 @@ def test_mixed_64x64x32_forward_and_adjoint(mixed_ref):
 
 
 # ------------------------------------------------------------------ checkpointing, determinism
-def test_checkpoint_recompute_is_bitwise():
+@pytest.mark.parametrize("variant", [1, 0])
+def test_checkpoint_recompute_is_bitwise(variant):
     w = wl.small_problem(40, 24, 10, 20, seed=9, dt=3.0, precision="f32", rtol=1e-6)
     gs = wl.random_surface_weights(20, 24, 40, seed=19).astype(np.float32)
     say("checkpoint full")
-    full = run_gpu(w, gs=gs, team=4, tile_z=3)
+    full = run_gpu(w, gs=gs, team=4, tile_z=3, variant=variant)
     for k in (1, 7, 64):
         say("checkpoint k", k)
-        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=4, tile_z=3)
+        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=4, tile_z=3, variant=variant)
         assert np.array_equal(ck["S"], full["S"])
         assert np.array_equal(ck["G"], full["G"])
         if k < 20:
