@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=16)
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (nh_copy_f32) three times, so that "
+                         "hardware byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -86,6 +89,23 @@ def main():
     from paper_2603_11045_amd import Solver
 
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        import ctypes
+
+        from paper_2603_11045_amd import _lib
+
+        n = 1 << 28                                   # 2^28 floats = 1 GiB read + 1 GiB written
+        src = torch.zeros(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        lib = _lib.load()
+        for _ in range(3):
+            code = lib.nh_copy_f32(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n,
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            assert code == 0, code
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] calibration copy: 3 x nh::copy_kernel<float> of 2^28 elements", file=sys.stderr,
+              flush=True)
     w = make_workload(args.workload, args.nsteps)
     ck = w.checkpoint_every if args.checkpoint_every < 0 else args.checkpoint_every
     dtype = torch.float32 if w.precision == "f32" else torch.float64

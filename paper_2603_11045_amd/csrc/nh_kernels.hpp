@@ -103,7 +103,7 @@ template <> __device__ __forceinline__ double rcp<double>(double v) { return 1.0
 // Store of a sweep output. (Non-temporal stores were measured slower here:
 // they bypass the last-level cache that the next sweep reads from.)
 template <typename T>
-__device__ __forceinline__ void st_nt(T* p, T v) { *p = v; }
+__device__ __forceinline__ void st_out(T* p, T v) { *p = v; }
 
 // dt * c_f = s * a*b/(a+b) with s = 2 dt / h^2 (Prop. 1); b = 0 outside the grid gives 0.
 template <typename R>
@@ -489,8 +489,8 @@ struct InitOp {
     if (kz == 0) b += top_scale * top[i];
     const R r = b - Av;
     const R zz = r * rcp<R>(D);
-    st_nt(z + i, zz);
-    if (xw) st_nt(xw + i, P.v[0][0]);
+    st_out(z + i, zz);
+    if (xw) st_out(xw + i, P.v[0][0]);
     const double bd = b, rd = r;
     acc[0] += bd * bd;
     acc[1] += rd * (double)zz;
@@ -517,7 +517,7 @@ struct DirOp {
   __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
     R Av, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
-    st_nt(pnew + i, P.v[0][0]);
+    st_out(pnew + i, P.v[0][0]);
     acc[0] += (double)P.v[0][0] * (double)Av;
   }
 };
@@ -540,9 +540,9 @@ struct UpdOp {
   __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int) {
     R Ap, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Ap, D);
-    st_nt(x + i, o[0] + a * P.v[0][0]);
+    st_out(x + i, o[0] + a * P.v[0][0]);
     const R zn = o[1] - a * (Ap * rcp<R>(D));
-    st_nt(z + i, zn);
+    st_out(z + i, zn);
     const double zd = zn, rd = (double)D * zd;
     acc[0] += rd * zd;
     acc[1] += rd * rd;
@@ -573,7 +573,7 @@ struct GradOp {
       const double w = q / (a + q);
       acc += s[f] * (w * w) * ((t - (double)P.v[1][f]) * (m - (double)P.v[0][f]));
     }
-    st_nt(G + i, o[0] - acc);
+    st_out(G + i, o[0] - acc);
   }
 };
 
@@ -593,7 +593,7 @@ struct WOp {
   __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
     R w, D;
     stencil<R, 1>(P, 0, sx, sy, sz, w, D);
-    st_nt(what + i, w * rcp<R>(D));
+    st_out(what + i, w * rcp<R>(D));
     acc[0] += (double)P.v[0][0] * (double)w;
   }
 };
@@ -639,14 +639,14 @@ struct FusedOp {
   __device__ void point(const Pt<R, 1>& P, const R (&o)[5], long long i, int) {
     const R sv = first ? o[3] : o[3] + b * o[4];
     const R pv = first ? o[2] : o[2] + b * o[1];
-    st_nt(x + i, o[0] + a * pv);
-    st_nt(p + i, pv);
-    st_nt(shn + i, sv);
+    st_out(x + i, o[0] + a * pv);
+    st_out(p + i, pv);
+    st_out(shn + i, sv);
     R w, D;
     stencil<R, 1>(P, 0, sx, sy, sz, w, D);
     const R uv = P.v[0][0];
-    st_nt(un + i, uv);
-    st_nt(whn + i, w * rcp<R>(D));
+    st_out(un + i, uv);
+    st_out(whn + i, w * rcp<R>(D));
     const double ud = uv, Dd = D, rd = Dd * ud;
     acc[0] += rd * ud;
     acc[1] += (double)w * ud;
