@@ -79,6 +79,8 @@ typedef struct {
     int team_blocks;            /* workgroups cooperating on one step */
     int block_threads;          /* threads per workgroup */
     int tile_x, tile_y, tile_z; /* tile extents of the stencil kernels */
+    int resident;               /* 1: the register-resident step kernel runs this grid */
+    int resident_occupancy;     /* workgroups of that kernel that fit one CU (0: unusable) */
 } nh_stats;
 
 /* Create a context on HIP device `hip_device`. All work of the context is

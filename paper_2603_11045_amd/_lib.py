@@ -54,6 +54,8 @@ class nh_stats(ctypes.Structure):
         ("tile_x", ctypes.c_int),
         ("tile_y", ctypes.c_int),
         ("tile_z", ctypes.c_int),
+        ("resident", ctypes.c_int),
+        ("resident_occupancy", ctypes.c_int),
     ]
 
     def as_dict(self):

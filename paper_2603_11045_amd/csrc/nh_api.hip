@@ -10,6 +10,7 @@
 // reproduces the stored states bit for bit.
 #include "nefty_heat.h"
 #include "nh_kernels.hpp"
+#include "nh_resident.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -40,6 +41,7 @@ struct nh_ctx {
   int num_cu = 0;
   long long wallclock_khz = 100000;
   int occ_f32 = 0, occ_f64 = 0;              // co-resident step kernels per CU
+  int res_occ = 0;                           // co-resident resident kernels per CU (0: unusable)
 
   bool grid_set = false;
   int nx = 0, ny = 0, nz = 0;
@@ -60,7 +62,8 @@ struct nh_ctx {
 
   // workspaces
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, mu, w0, w1, traj, seg, slots, steps, flag;
-  int variant = 1;                           // CG form: 0 two reductions per iteration, 1 one
+  int variant = 2;                           // 0 two reductions per iteration, 1 one, 2 one + register-resident
+  bool resident = false;                     // the current plan uses nh::resident_step_kernel
   unsigned long long launch_ctr = 0;         // makes every launch's reduction epochs unique
   size_t ws_bytes = 0, ws_peak = 0;
 
@@ -142,8 +145,9 @@ nh_status fill(nh_ctx* c, T* p, long long n, T v) {
   return NH_OK;
 }
 
-// Tile shape and team size for the current grid, for workgroups of `block` threads.
-void plan(nh_ctx* c, int occ, int block) {
+// Tile shape and team size for the current grid, for workgroups of `block`
+// threads; resident_ok allows the register-resident kernel (FP32, variant 2).
+void plan(nh_ctx* c, int occ, int block, bool resident_ok = false) {
   Geom g{};
   g.nx = c->nx;
   g.ny = c->ny;
@@ -174,6 +178,29 @@ void plan(nh_ctx* c, int occ, int block) {
   g.ntiles = (int)(xy_tiles * g.ntz);
   int team = std::min(g.ntiles, maxteam);
   if (g.ng <= 65536 && c->team_max == 0) team = std::min(team, 1 + (int)(g.ng / 16384));
+  c->resident = false;
+  if (resident_ok && g.TX == 64) {
+    // one tile of 64 x 8 columns x TZ cells per CU, the tile's CG state in registers
+    Geom r = g;
+    r.TY = nh::kResBlock / r.TX;
+    r.nty = (r.ny + r.TY - 1) / r.TY;
+    const long long rxy = (long long)r.ntx * r.nty;
+    const int cap = c->team_max > 0 ? std::min(c->team_max, c->num_cu * c->res_occ) : c->num_cu * c->res_occ;
+    int tz0 = c->tile_z > 0 ? c->tile_z : (int)std::max<long long>(std::min(4, r.nz), ((long long)r.nz * rxy + cap - 1) / cap);
+    for (int tz = tz0; tz <= nh::kResTZ && (c->tile_z == 0 || tz == c->tile_z); ++tz) {
+      const long long nt = rxy * ((r.nz + tz - 1) / tz);
+      if (nt <= cap) {
+        r.TZ = std::min(tz, r.nz);
+        r.ntz = (r.nz + r.TZ - 1) / r.TZ;
+        r.ntiles = (int)(rxy * r.ntz);
+        g = r;
+        team = r.ntiles;
+        block = nh::kResBlock;
+        c->resident = true;
+        break;
+      }
+    }
+  }
   c->geom = g;
   c->team = std::max(1, team);
   c->st.team_blocks = c->team;
@@ -181,6 +208,8 @@ void plan(nh_ctx* c, int occ, int block) {
   c->st.tile_x = g.TX;
   c->st.tile_y = g.TY;
   c->st.tile_z = g.TZ;
+  c->st.resident = c->resident ? 1 : 0;
+  c->st.resident_occupancy = c->res_occ;
 }
 
 template <typename R>
@@ -197,8 +226,12 @@ nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) 
     e1 = c->ev[2 * slot_ev + 1];
     NH_HIP(c, hipEventRecord(e0, c->stream));
   }
-  NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(nh::Cfg<R>::kBlock),
-                                       args, 0, c->stream));
+  if (sizeof(R) == 4 && c->resident)
+    NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::resident_step_kernel<64>, dim3(S.team),
+                                         dim3(nh::kResBlock), args, (unsigned)nh::kResLdsBytes, c->stream));
+  else
+    NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(nh::Cfg<R>::kBlock),
+                                         args, 0, c->stream));
   if (c->profile) NH_HIP(c, hipEventRecord(e1, c->stream));
   (void)t_kernel;
   return NH_OK;
@@ -242,7 +275,7 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.w1 = (R*)c->vw1.p;
   S.s0 = (R*)c->vs0.p;
   S.s1 = (R*)c->vs1.p;
-  S.variant = c->variant;
+  S.variant = c->variant == 0 ? 0 : 1;
   S.slots = c->slots.p;
   S.epoch_base = (++c->launch_ctr) << 24;
   S.rtol2 = c->rtol * c->rtol;
@@ -337,9 +370,21 @@ nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
 }
 
 // Per-voxel algorithmic bytes of one step kernel (R = vector element size).
-double step_bytes(const Geom& g, int R, int variant, int mode, int iters, bool first_step, bool surf, bool ckpt) {
+double step_bytes(const Geom& g, int R, int variant, int mode, int iters, bool first_step, bool surf, bool ckpt,
+                  bool resident = false) {
   const double ng = (double)g.ng, nxy = (double)g.nxy;
   double b = 0;
+  if (resident) {
+    // alpha and the previous state in, the state out; per iteration only the
+    // tile faces move: 3 vectors written once and read by the neighbour
+    const double faces = (double)g.ntiles * (2.0 * g.TX * g.TY + 2.0 * (g.TX + g.TY) * g.TZ);
+    b += (first_step && mode == nh::kForward ? 2.0 : 3.0) * R * ng + R * nxy;
+    if (surf) b += 2.0 * R * nxy;
+    if (ckpt) b += R * ng;
+    if (mode == nh::kAdjoint) b += (R + 16.0) * ng + R * ng;   // T^n, G read+write, mu faces re-read
+    b += (iters + 1) * 6.0 * R * faces;
+    return b;
+  }
   if (mode == nh::kForward) {
     b += (first_step ? 3.0 : 4.0) * R * ng;        // read x0 (halo), alpha; write x, z
     if (surf) b += 2.0 * R * nxy;
@@ -419,6 +464,7 @@ nh_status forward_step(nh_ctx* c, int n, const R* xprev, R* x, const R* q_xy, do
     S.trace = (long long*)c->trace.p;
     S.trace_rank = c->trace_rank < 0 ? -1 : std::min(c->trace_rank, c->team - 1);
     S.trace_cap = cap;
+    S.trace_detail = (c->resident && std::getenv("NH_TRACE_DETAIL")) ? 1 : 0;
   }
   NH_TRY(launch_step<R>(c, S, ev_slot, nullptr));
   if (tracing) {
@@ -428,7 +474,7 @@ nh_status forward_step(nh_ctx* c, int n, const R* xprev, R* x, const R* q_xy, do
     // stamps: start, set-up sweep(s) and reduction(s), then per iteration its
     // sweep(s) and reduction(s): two pairs (variant 0) or one pair (variant 1)
     const double us = 1e3 / (double)c->wallclock_khz;
-    const int head = c->variant == 0 ? 3 : 5, per = c->variant == 0 ? 4 : 2;
+    const int head = c->variant == 0 ? 3 : 5, per = c->variant == 0 ? 4 : (S.trace_detail ? 5 : 2);
     const int nranks = c->trace_rank < 0 ? c->team : 1;
     for (int r = 0; r < nranks; ++r) {
       const long long* t = tall.data() + (size_t)r * cap;
@@ -460,7 +506,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     if (!std::isfinite(q_t[i])) return fail(c, NH_EINVAL, "q_t holds a non-finite value");
 
   drop_forward(c);
-  plan(c, occupancy<R>(c), nh::Cfg<R>::kBlock);
+  plan(c, occupancy<R>(c), nh::Cfg<R>::kBlock, sizeof(R) == 4 && c->variant == 2 && c->res_occ > 0);
   NH_TRY(ensure_common<R>(c, nsteps));
   NH_TRY(ensure_events(c));
   const Geom& g = c->geom;
@@ -537,7 +583,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     double bytes = 0;
     for (int n = 1; n <= nsteps; ++n)
       bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, it[n - 1], n == 1, true,
-                          k > 0 && n % k == 0 && n < nsteps);
+                          k > 0 && n % k == 0 && n < nsteps, sizeof(R) == 4 && c->resident);
     c->st.bytes_alg_fwd = bytes;
   }
   c->saved_prec = sizeof(R);
@@ -637,7 +683,8 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
   NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 1, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   for (int n = 1; n <= N; ++n)
-    bytes += step_bytes(g, sizeof(R), c->variant, nh::kAdjoint, it[n - 1], false, false, false);
+    bytes += step_bytes(g, sizeof(R), c->variant, nh::kAdjoint, it[n - 1], false, false, false,
+                        sizeof(R) == 4 && c->resident);
   c->st.recompute_iters = 0;
   if (k > 0) {
     long long rsum = 0;
@@ -650,7 +697,8 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     NH_HIP(c, hipMemcpyAsync(ir.data(), step_out(c, 2, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
     NH_HIP(c, hipStreamSynchronize(c->stream));
     for (int n = 1; n <= N; ++n)
-      bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, ir[n - 1], n == 1, false, false);
+      bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, ir[n - 1], n == 1, false, false,
+                          sizeof(R) == 4 && c->resident);
   }
   c->st.bytes_alg_adj = bytes;
   c->st.workspace_bytes = c->ws_bytes;
@@ -692,6 +740,17 @@ nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
   }
   c->occ_f32 = std::max(1, o32);
   c->occ_f64 = std::max(1, o64);
+  {
+    int ro = 0;
+    if (hipFuncSetAttribute((const void*)nh::resident_step_kernel<64>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)nh::kResLdsBytes) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&ro, (const void*)nh::resident_step_kernel<64>,
+                                                     nh::kResBlock, nh::kResLdsBytes) == hipSuccess)
+      c->res_occ = ro;
+    (void)hipGetLastError();
+    if (std::getenv("NH_TRACE_STEP"))
+      std::fprintf(stderr, "[nh] resident kernel: %zu B LDS, %d workgroups per CU\n", nh::kResLdsBytes, c->res_occ);
+  }
   if (const char* e = std::getenv("NH_TRACE_STEP")) c->trace_step = std::atoi(e);
   if (const char* e = std::getenv("NH_TRACE_RANK")) c->trace_rank = std::atoi(e);
   *out = c;
@@ -798,7 +857,7 @@ nh_status nh_set_launch(nh_ctx* c, int team_blocks_max, int tile_z, int profile)
 
 nh_status nh_set_cg_variant(nh_ctx* c, int variant) {
   if (!c) return NH_EINVAL;
-  if (variant != 0 && variant != 1) return fail(c, NH_EINVAL, "variant must be 0 or 1");
+  if (variant < 0 || variant > 2) return fail(c, NH_EINVAL, "variant must be 0, 1 or 2");
   drop_forward(c);
   c->variant = variant;
   return NH_OK;

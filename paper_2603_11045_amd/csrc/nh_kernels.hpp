@@ -91,6 +91,7 @@ struct StepArgs {
   long long* trace;                         // optional: wall-clock stamps of phase ends
   int trace_rank;                           // workgroup whose thread 0 writes the stamps
   int trace_cap;                            // capacity of trace in entries
+  int trace_detail;                         // resident kernel: extra stamps inside an iteration
 };
 
 // ---------------------------------------------------------------------------

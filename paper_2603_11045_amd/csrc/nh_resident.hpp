@@ -1,0 +1,549 @@
+// nh_resident.hpp -- register-resident variant of the per-step kernel (FP32).
+//
+// When every tile of the grid fits one workgroup per CU (a tile is 512
+// columns of at most kResTZ cells), the CG state of a tile -- p, u = r/D,
+// A u / D and A p / D, the vectors of the single-reduction iteration of
+// nh_kernels.hpp -- stays in the registers of the workgroup that owns the tile
+// for the whole time step, and alpha stays in LDS. Only x, which no neighbour
+// reads during the solve, is updated in place in memory (8 bytes per cell and
+// iteration, coalesced, no halo). The elementwise updates run in registers, the stencil
+// exchanges in-tile neighbours through LDS one z-plane at a time, and only the
+// values on the tile's faces are published (write-through, device-scope
+// stores) for the neighbouring tiles, which read them with device-scope loads
+// after the next team reduction. Because every inter-workgroup exchange uses
+// device-coherent accesses, the team reduction needs no L2 write-back or
+// invalidation. The arithmetic is the same as the streaming kernel's
+// single-reduction form; halo values are recomputed with the same fused
+// multiply-adds as the owner uses, so both sides see identical bits.
+#pragma once
+
+#include "nh_kernels.hpp"
+
+namespace nh {
+
+constexpr int kResBlock = 512;              // one workgroup (8 wave64, 256 VGPRs each) per CU
+constexpr int kResTZ = 32;                  // max cells per column of a tile
+constexpr int kRing = 144;                  // max 2*(TX+TY) with TX*TY = 512
+constexpr int kResPlane = 660;              // max (TX+2)*(TY+2) with TX*TY = 512
+
+__device__ __forceinline__ void st_dev(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_dev(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct ResRed {
+  double red[kMaxWaves][kNumRed];
+  double bc[kNumRed];
+  int flag;
+};
+
+// LDS layout of the resident kernel (bytes).
+constexpr size_t kResAlphaFloats = (size_t)(kResTZ + 2) * kResPlane;   // alpha tile + halos
+constexpr size_t kResPlaneFloats = 4 * (size_t)kResPlane;              // [2 vectors][2 buffers]
+constexpr size_t kResRingFloats = 2 * (size_t)kResTZ * kRing;          // [2 vectors][TZ][ring]
+constexpr size_t kResLdsBytes =
+    (kResAlphaFloats + kResPlaneFloats + kResRingFloats) * sizeof(float) + sizeof(ResRed) + 64;
+
+// Team reduction for the resident kernel: like team_sum, but every value
+// another workgroup reads was written with device-scope stores, so the
+// publication needs only the completion of this workgroup's stores (a full
+// s_waitcnt in every wave) and no cache maintenance.
+template <int NV>
+__device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank, unsigned long long& epoch,
+                                             double (&v)[NV], ResRed* rs) {
+  __builtin_amdgcn_s_waitcnt(0);
+  block_sum<NV, kResBlock / 64>(v, rs->red, rs->bc);
+  if (S.team == 1) return true;
+  const unsigned long long e = ++epoch;
+  Slot* slots = (Slot*)S.slots;
+  Slot* res = slots + S.team;
+  int ok = 1;
+  if (rank != 0) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        __hip_atomic_store(&slots[rank].v[i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(&slots[rank].epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const long long t0 = wall_clock64();
+      while (ld_epoch(&res->epoch) != e) {
+        __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
+      }
+#pragma unroll
+      for (int i = 0; i < NV; ++i) rs->bc[i] = ld_val(&res->v[i]);
+      rs->flag = ok;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = rs->bc[i];
+    ok = rs->flag;
+    __syncthreads();
+  } else {
+    double s[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s[i] = 0.0;
+    for (int b = threadIdx.x; b < S.team; b += kResBlock) {
+      if (b == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) s[i] += v[i];
+        continue;
+      }
+      const long long t0 = wall_clock64();
+      while (ld_epoch(&slots[b].epoch) != e) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
+      }
+#pragma unroll
+      for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
+    }
+    ok = __syncthreads_and(ok);
+    block_sum<NV, kResBlock / 64>(s, rs->red, rs->bc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+        __hip_atomic_store(&res->v[i], s[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_store(&res->epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = s[i];
+  }
+  if (!ok && threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
+  return ok != 0;
+}
+
+// Compile-time tile geometry: TX columns in x (a power of two), 512 / TX in y.
+template <int TX_>
+struct RG {
+  static constexpr int TX = TX_;
+  static constexpr int TY = kResBlock / TX_;
+  static constexpr int PW = TX + 2;
+  static constexpr int PL = (TX + 2) * (TY + 2);
+  static constexpr int RING = 2 * (TX + TY);
+  static_assert(PL <= kResPlane && RING <= kRing, "tile too large");
+};
+
+// Where one thread of the resident workgroup sits in its tile.
+struct ResPos {
+  int tx, ty;
+  int x0, y0, z0, tzn;
+  int gx, gy;
+  bool own;
+  int col;                                  // x + nx*y (the grid has fewer than 2^31 cells)
+  int oslot;
+  bool top_z, bot_z;                        // a tile exists below (z0-1) / above (z1)
+  bool edge;                                // column on the tile's x/y boundary
+};
+
+// Geometry of ring cell h (0 <= h < RING): grid column and LDS plane slot.
+template <class G>
+__device__ __forceinline__ void ring_cell(const Geom& g, const ResPos& q, int h, bool& in, int& hcol,
+                                          int& hslot) {
+  int hx, hy;
+  constexpr int TX = G::TX, TY = G::TY, PW = G::PW;
+  if (h < TX) { hx = q.x0 + h; hy = q.y0 - 1; hslot = h + 1; }
+  else if ((h -= TX) < TX) { hx = q.x0 + h; hy = q.y0 + TY; hslot = (TY + 1) * PW + h + 1; }
+  else if ((h -= TX) < TY) { hx = q.x0 - 1; hy = q.y0 + h; hslot = (h + 1) * PW; }
+  else { h -= TY; hx = q.x0 + TX; hy = q.y0 + h; hslot = (h + 1) * PW + TX + 1; }
+  in = hx >= 0 && hx < g.nx && hy >= 0 && hy < g.ny;
+  hcol = in ? hx + g.nx * hy : 0;
+}
+
+// Fill an LDS ring buffer for every plane of the tile: ring[z][h] =
+// val(global index) for in-grid ring cells, 0 outside. All loads of a thread
+// are issued before the first LDS store, so the fill costs one memory latency.
+template <class G, typename F>
+__device__ __forceinline__ void fill_ring(const Geom& g, const ResPos& q, float* ring, F val) {
+  constexpr int kMaxPer = (G::RING * kResTZ + kResBlock - 1) / kResBlock;
+  const int n = G::RING * q.tzn;
+  float v[kMaxPer];
+  int slot[kMaxPer];
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k) {
+    const int e = threadIdx.x + k * kResBlock;
+    v[k] = 0.f;
+    slot[k] = -1;
+    if (e < n) {
+      const int z = e / G::RING, h = e - z * G::RING;
+      bool in;
+      int hcol, hslot;
+      ring_cell<G>(g, q, h, in, hcol, hslot);
+      slot[k] = z * kRing + h;
+      if (in) v[k] = val(hcol + (q.z0 + z) * (int)g.nxy);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k)
+    if (slot[k] >= 0) ring[slot[k]] = v[k];
+}
+
+// Face conductance times dt and the neighbour values of one cell, from the
+// alpha tile in LDS (lz = z + 1 is the cell's plane) and the staged plane.
+struct Nb {
+  float c[6];                               // -x +x -y +y -z +z
+  float D;
+};
+
+template <class G>
+__device__ __forceinline__ Nb faces_at(const float* la, const ResPos& q, int z, float sx, float sy, float sz) {
+  const float* pl = la + (z + 1) * G::PL + q.oslot;
+  const float a = pl[0];
+  Nb n;
+  n.c[0] = face<float>(sx, a, pl[-1]);
+  n.c[1] = face<float>(sx, a, pl[1]);
+  n.c[2] = face<float>(sy, a, pl[-G::PW]);
+  n.c[3] = face<float>(sy, a, pl[G::PW]);
+  n.c[4] = face<float>(sz, a, pl[-G::PL]);
+  n.c[5] = face<float>(sz, a, pl[G::PL]);
+  n.D = 1.f + (((n.c[0] + n.c[1]) + (n.c[2] + n.c[3])) + (n.c[4] + n.c[5]));
+  return n;
+}
+
+// A v at one cell given the four in-plane neighbours from LDS and the two z neighbours.
+__device__ __forceinline__ float apply_at(const Nb& n, float v, const float* pl, int oslot, int PW, float vzm,
+                                          float vzp) {
+  float s = n.c[0] * (v - pl[oslot - 1]);
+  s += n.c[1] * (v - pl[oslot + 1]);
+  s += n.c[2] * (v - pl[oslot - PW]);
+  s += n.c[3] * (v - pl[oslot + PW]);
+  s += n.c[4] * (v - vzm);
+  s += n.c[5] * (v - vzp);
+  return v + s;
+}
+
+// Plane-by-plane sweep over the tile for NV staged vectors. own(k, z) gives
+// the thread's own value of vector k at plane z, ring[k] the LDS ring buffers,
+// zlo/zhi the values below and above the tile; cell(z, plane pointers) does the work.
+template <class G, int NV, typename OwnF, typename CellF>
+__device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, float* lp, const float* ring,
+                                            OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
+  // ring cells handled by this thread for the plane copy
+  const int h = threadIdx.x;
+  bool hin = false;
+  int hcol = 0;
+  int hslot = -1;
+  if (h < G::RING) ring_cell<G>(g, q, h, hin, hcol, hslot);
+#pragma unroll
+  for (int z = 0; z < kResTZ; ++z) {
+    if (z < q.tzn) {
+      float* pl[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) pl[k] = lp + (size_t)(2 * k + (z & 1)) * kResPlane;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        pl[k][q.oslot] = q.own ? own(k, z) : 0.f;
+        if (hslot >= 0) pl[k][hslot] = ring[(size_t)k * kResTZ * kRing + z * kRing + h];
+      }
+      __syncthreads();
+      if (q.own) {
+        float vzm[NV], vzp[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          vzm[k] = z == 0 ? zlo[k] : own(k, z > 0 ? z - 1 : 0);
+          vzp[k] = z + 1 == q.tzn ? zhi[k] : own(k, z + 1 < kResTZ ? z + 1 : kResTZ - 1);
+        }
+        cell(z, pl, vzm, vzp);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int TXC>
+__global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<float> S) {
+  using G = RG<TXC>;
+  constexpr int TZ = kResTZ;
+  extern __shared__ __align__(16) unsigned char dsm[];
+  float* la = (float*)dsm;
+  float* lp = la + kResAlphaFloats;
+  float* lring = lp + kResPlaneFloats;
+  ResRed* rs = (ResRed*)(lring + kResRingFloats);
+
+  const Geom& g = S.g;
+  const int rank = blockIdx.x;
+  const int tile = first_tile(rank, S.team, S.xcd_order);
+  const Tile T = tile_of(g, tile);
+
+  ResPos q;
+  q.tx = threadIdx.x % G::TX;
+  q.ty = threadIdx.x / G::TX;
+  q.x0 = T.x0; q.y0 = T.y0; q.z0 = T.z0;
+  q.tzn = T.z1 - T.z0;
+  q.gx = T.x0 + q.tx;
+  q.gy = T.y0 + q.ty;
+  q.own = q.gx < g.nx && q.gy < g.ny;
+  q.col = q.own ? q.gx + g.nx * q.gy : 0;
+  q.oslot = (q.ty + 1) * G::PW + q.tx + 1;
+  q.bot_z = T.z0 > 0;
+  q.top_z = T.z1 < g.nz;
+  q.edge = q.tx == 0 || q.tx == G::TX - 1 || q.ty == 0 || q.ty == G::TY - 1;
+  const float sx = S.sx, sy = S.sy, sz = S.sz;
+  const int nxy = (int)g.nxy;
+
+  unsigned long long red = S.epoch_base;
+  bool ok = true;
+  int ntr = 0;
+  const bool tr = S.trace && (rank == S.trace_rank || S.trace_rank < 0) && threadIdx.x == 0;
+  long long* trace = S.trace ? S.trace + (S.trace_rank < 0 ? (long long)rank * S.trace_cap : 0) : nullptr;
+  auto stamp = [&]() {
+    if (tr && ntr < S.trace_cap) trace[ntr++] = wall_clock64();
+  };
+  stamp();
+
+  // alpha tile with halos: planes z0-1 .. z0+tzn, each (TX+2) x (TY+2)
+  {
+    const int n = (q.tzn + 2) * G::PL;
+    for (int e = threadIdx.x; e < n; e += kResBlock) {
+      const int lz = e / G::PL, rem = e - lz * G::PL;
+      const int ly = rem / G::PW, lx = rem - ly * G::PW;
+      const int gz = T.z0 - 1 + lz, gxx = T.x0 - 1 + lx, gyy = T.y0 - 1 + ly;
+      float a = 0.f;
+      if (gz >= 0 && gz < g.nz && gxx >= 0 && gxx < g.nx && gyy >= 0 && gyy < g.ny)
+        a = S.alpha[gxx + g.nx * gyy + gz * nxy];
+      la[e] = a;
+    }
+  }
+
+  float pr[TZ], ur[TZ], wr[TZ], sr[TZ];
+#pragma unroll
+  for (int z = 0; z < TZ; ++z) { pr[z] = 0.f; ur[z] = 0.f; wr[z] = 0.f; sr[z] = 0.f; }
+  float (&xr)[TZ] = pr;                     // x0 lives in the p registers during the set-up
+
+  // ---------------- set-up: x0, b, r = b - A x0, u = r / D; x = x0 in memory
+  const float* x0src = S.mode == kForward ? S.xprev : S.x;
+  if (q.own && x0src) {
+#pragma unroll
+    for (int z = 0; z < TZ; ++z)
+      if (z < q.tzn) xr[z] = x0src[q.col + (T.z0 + z) * nxy];
+  }
+  if (q.own && x0src != S.x) {
+#pragma unroll
+    for (int z = 0; z < TZ; ++z)
+      if (z < q.tzn) S.x[q.col + (T.z0 + z) * nxy] = xr[z];
+  }
+  float zlo[2] = {0.f, 0.f}, zhi[2] = {0.f, 0.f};
+  if (x0src) {
+    if (q.own && q.bot_z) zlo[0] = x0src[q.col + (T.z0 - 1) * nxy];
+    if (q.own && q.top_z) zhi[0] = x0src[q.col + T.z1 * nxy];
+    fill_ring<G>(g, q, lring, [&](int i) { return x0src[i]; });
+  } else {
+    fill_ring<G>(g, q, lring, [&](int) { return 0.f; });
+  }
+  __syncthreads();
+  double acc3[3] = {0.0, 0.0, 0.0};
+  plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return xr[z]; }, zlo, zhi,
+                 [&](int z, float* const* pl, const float* vzm, const float* vzp) {
+                   const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
+                   const float Av = apply_at(n, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
+                   float b = xr[z];
+                   if (T.z0 + z == 0) b += S.top_scale * S.top_src[q.col];
+                   const float r = b - Av;
+                   const float u = r * rcp<float>(n.D);
+                   ur[z] = u;
+                   const double bd = b, rd = r;
+                   acc3[0] += bd * bd;
+                   acc3[1] += rd * (double)u;
+                   acc3[2] += rd * rd;
+                 });
+  stamp();
+  // publish u0 on the tile's faces
+  if (q.own) {
+#pragma unroll
+    for (int z = 0; z < TZ; ++z)
+      if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(S.z + q.col + (T.z0 + z) * nxy, ur[z]);
+  }
+  ok &= team_sum_dev<3>(S, rank, red, acc3, rs);
+  stamp();
+  const double bb = acc3[0];
+  double gam = acc3[1], rr = acc3[2];
+
+  float* ub[2] = {S.z, S.u1};
+  float* wb[2] = {S.w0, S.w1};
+  float* sb[2] = {S.s0, S.s1};
+  int it = 0, status = kOk;
+  if (ok && bb == 0.0) {
+    if (q.own) {
+#pragma unroll
+      for (int z = 0; z < TZ; ++z)
+        if (z < q.tzn) S.x[q.col + (T.z0 + z) * nxy] = 0.f;
+    }
+    rr = 0.0;
+  } else if (ok && rr > S.rtol2 * bb) {
+    // ---------------- w0 = A u0
+    if (q.own && q.bot_z) zlo[0] = ld_dev(ub[0] + q.col + (T.z0 - 1) * nxy);
+    if (q.own && q.top_z) zhi[0] = ld_dev(ub[0] + q.col + T.z1 * nxy);
+    fill_ring<G>(g, q, lring, [&](int i) { return ld_dev(ub[0] + i); });
+    __syncthreads();
+    double acc1[1] = {0.0};
+    plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
+                   [&](int z, float* const* pl, const float* vzm, const float* vzp) {
+                     const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
+                     const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
+                     wr[z] = w * rcp<float>(n.D);
+                     acc1[0] += (double)ur[z] * (double)w;
+                   });
+    stamp();
+    if (q.own) {
+#pragma unroll
+      for (int z = 0; z < TZ; ++z)
+        if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
+    }
+    ok &= team_sum_dev<1>(S, rank, red, acc1, rs);
+    stamp();
+    double a_cg = gam / acc1[0], b_cg = 0.0;
+    int cur = 0;
+    while (ok) {
+      if (it >= S.max_iter) { status |= kNoConv; break; }
+      // keep per-plane address arithmetic inside the loop (hoisting it for every
+      // plane would exhaust the register file)
+      int nxy_l = nxy;
+      int col_l = q.col;
+      asm volatile("" : "+s"(nxy_l));
+      asm volatile("" : "+v"(col_l));
+      const float a = (float)a_cg, b = (float)b_cg;
+      const bool first = it == 0;
+      // elementwise updates: s = w + b s, p = u + b p, u -= a s in registers, x += a p in memory
+#pragma unroll
+      for (int z = 0; z < TZ; ++z) {
+        const float s_ = first ? wr[z] : fmaf(b, sr[z], wr[z]);
+        const float p_ = first ? ur[z] : fmaf(b, pr[z], ur[z]);
+        if (q.own && z < q.tzn) {
+          float* xp = S.x + col_l + (T.z0 + z) * nxy_l;
+          *xp = fmaf(a, p_, *xp);
+        }
+        pr[z] = p_;
+        sr[z] = s_;
+        ur[z] = fmaf(-a, s_, ur[z]);
+      }
+      // halo values of the new u from the neighbours' published u, w/D, s/D
+      const float* uo = ub[cur];
+      const float* wo = wb[cur];
+      const float* so = sb[cur];
+      auto unew = [&](int i) {
+        const float s_ = first ? ld_dev(wo + i) : fmaf(b, ld_dev(so + i), ld_dev(wo + i));
+        return fmaf(-a, s_, ld_dev(uo + i));
+      };
+      if (q.own && q.bot_z) zlo[0] = unew(col_l + (T.z0 - 1) * nxy_l);
+      if (q.own && q.top_z) zhi[0] = unew(col_l + T.z1 * nxy_l);
+      if (S.trace_detail) stamp();
+      fill_ring<G>(g, q, lring, unew);
+      __syncthreads();
+      if (S.trace_detail) stamp();
+      double acc[3] = {0.0, 0.0, 0.0};
+      plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
+                     [&](int z, float* const* pl, const float* vzm, const float* vzp) {
+                       const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
+                       const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
+                       wr[z] = w * rcp<float>(n.D);
+                       const double ud = ur[z], Dd = n.D, rd = Dd * ud;
+                       acc[0] += rd * ud;
+                       acc[1] += (double)w * ud;
+                       acc[2] += rd * rd;
+                     });
+      stamp();
+      // publish u, w/D, s/D on the tile's faces for the next iteration
+      if (q.own) {
+#pragma unroll
+        for (int z = 0; z < TZ; ++z) {
+          if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) {
+            const int i = col_l + (T.z0 + z) * nxy_l;
+            st_dev(ub[cur ^ 1] + i, ur[z]);
+            st_dev(wb[cur ^ 1] + i, wr[z]);
+            st_dev(sb[cur ^ 1] + i, sr[z]);
+          }
+        }
+      }
+      if (S.trace_detail) stamp();
+      ok &= team_sum_dev<3>(S, rank, red, acc, rs);
+      stamp();
+      ++it;
+      cur ^= 1;
+      rr = acc[2];
+      if (!(rr > S.rtol2 * bb)) break;
+      const double gn = acc[0], dn = acc[1];
+      b_cg = gn / gam;
+      a_cg = gn / (dn - b_cg * gn / a_cg);
+      gam = gn;
+    }
+  }
+  if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
+  if (!ok) status |= kTimeout;
+
+  // ---------------- epilogue: surface frame, checkpoint copy; for the gradient
+  // the final x on the tile's faces is republished with device-scope stores
+  if (q.own) {
+    if (S.mode == kForward && S.surf_out && T.z0 == 0) S.surf_out[q.col] = S.x[q.col];
+    if (S.ckpt_out) {
+      for (int z = 0; z < q.tzn; ++z) {
+        const int i = q.col + (T.z0 + z) * nxy;
+        S.ckpt_out[i] = S.x[i];
+      }
+    }
+  }
+  if (S.mode == kAdjoint && S.T_grad && ok) {
+    // gradient: G_p -= sum_f s_f (a_q/(a_p+a_q))^2 (T_p-T_q)(mu_p-mu_q)
+    float (&mcol)[TZ] = ur;                 // the solve is over: mu and T columns reuse u and p
+    float (&tcol)[TZ] = pr;
+#pragma unroll
+    for (int z = 0; z < TZ; ++z) {
+      const bool in = q.own && z < q.tzn;
+      const int i = q.col + (T.z0 + z) * nxy;
+      mcol[z] = in ? S.x[i] : 0.f;
+      tcol[z] = in ? S.T_grad[i] : 0.f;
+      if (in && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(S.x + i, mcol[z]);
+    }
+    double dummy[1] = {0.0};
+    ok &= team_sum_dev<1>(S, rank, red, dummy, rs);
+    float* ring_mu = lring;
+    float* ring_T = lring + (size_t)kResTZ * kRing;
+    fill_ring<G>(g, q, ring_mu, [&](int i) { return ld_dev(S.x + i); });
+    fill_ring<G>(g, q, ring_T, [&](int i) { return S.T_grad[i]; });
+    float glo[2] = {0.f, 0.f}, ghi[2] = {0.f, 0.f};
+    if (q.own && q.bot_z) {
+      glo[0] = ld_dev(S.x + q.col + (T.z0 - 1) * nxy);
+      glo[1] = S.T_grad[q.col + (T.z0 - 1) * nxy];
+    }
+    if (q.own && q.top_z) {
+      ghi[0] = ld_dev(S.x + q.col + T.z1 * nxy);
+      ghi[1] = S.T_grad[q.col + T.z1 * nxy];
+    }
+    __syncthreads();
+    plane_sweep<G, 2>(g, q, lp, lring, [&](int k, int z) { return k == 0 ? mcol[z] : tcol[z]; }, glo, ghi,
+                   [&](int z, float* const* pl, const float* vzm, const float* vzp) {
+                     const float* plz = la + (z + 1) * G::PL + q.oslot;
+                     const double a = plz[0];
+                     const double m = mcol[z], t = tcol[z];
+                     double qa[6], dm[6], dT[6];
+                     qa[0] = plz[-1]; qa[1] = plz[1];
+                     qa[2] = plz[-G::PW]; qa[3] = plz[G::PW];
+                     qa[4] = plz[-G::PL]; qa[5] = plz[G::PL];
+                     dm[0] = m - (double)pl[0][q.oslot - 1]; dT[0] = t - (double)pl[1][q.oslot - 1];
+                     dm[1] = m - (double)pl[0][q.oslot + 1]; dT[1] = t - (double)pl[1][q.oslot + 1];
+                     dm[2] = m - (double)pl[0][q.oslot - G::PW]; dT[2] = t - (double)pl[1][q.oslot - G::PW];
+                     dm[3] = m - (double)pl[0][q.oslot + G::PW]; dT[3] = t - (double)pl[1][q.oslot + G::PW];
+                     dm[4] = m - (double)vzm[0]; dT[4] = t - (double)vzm[1];
+                     dm[5] = m - (double)vzp[0]; dT[5] = t - (double)vzp[1];
+                     const double sf[6] = {(double)sx, (double)sx, (double)sy, (double)sy, (double)sz, (double)sz};
+                     double gsum = 0.0;
+#pragma unroll
+                     for (int f = 0; f < 6; ++f) {
+                       const double w = qa[f] / (a + qa[f]);
+                       gsum += sf[f] * (w * w) * (dT[f] * dm[f]);
+                     }
+                     const int i = q.col + (T.z0 + z) * nxy;
+                     S.G[i] = S.G[i] - gsum;
+                   });
+  }
+
+  if (rank == 0 && threadIdx.x == 0) {
+    S.out_iters[0] = it;
+    S.out_relres[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    S.out_status[0] = status;
+  }
+}
+
+}  // namespace nh

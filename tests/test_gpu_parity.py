@@ -39,7 +39,7 @@ def to_dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=1):
+def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=2):
     """Forward (and adjoint when gs is given) of workload w on the GPU."""
     prec = precision or w.precision
     dt_t = torch.float32 if prec == "f32" else torch.float64
@@ -83,12 +83,18 @@ SMALL = [
     (33, 17, 6, 7, 4, 8, 2),
     (16, 16, 8, 5, 5, 0, 0),
     (130, 9, 5, 3, 6, 0, 1),
+    # shapes that the register-resident kernel takes (variant 2): ragged z tiles,
+    # a single tile, many tiles
+    (70, 40, 9, 4, 7, 0, 0),
+    (100, 20, 40, 3, 8, 0, 0),
+    (64, 8, 20, 4, 9, 0, 0),
+    (65, 17, 33, 3, 10, 0, 0),
 ]
 
 
 @pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_t{c[5]}_z{c[6]}" for c in SMALL])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("variant", [1, 0])
+@pytest.mark.parametrize("variant", [2, 1, 0])
 def test_small_forward_adjoint(case, precision, variant):
     nx, ny, nz, nsteps, seed, team, tz = case
     say("small", case, precision, "variant", variant)
@@ -101,7 +107,8 @@ def test_small_forward_adjoint(case, precision, variant):
     out = run_gpu(w, team=team, tile_z=tz, gs=gs, variant=variant)
     tol_s, tol_g = (1e-9, 1e-8) if precision == "f64" else (1e-5, 1e-4)
     es, eg = rel_l2(out["S"], S_o), rel_l2(out["G"], G_o)
-    say("  rel-L2 S", es, "G", eg, "team", out["stats_fwd"]["team_blocks"])
+    say("  rel-L2 S", es, "G", eg, "team", out["stats_fwd"]["team_blocks"], "block",
+        out["stats_fwd"]["block_threads"])
     assert es <= tol_s and eg <= tol_g
 
 
@@ -126,7 +133,7 @@ def mixed_ref():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("variant", [1, 0])
+@pytest.mark.parametrize("variant", [2, 1, 0])
 def test_mixed_64x64x32_forward_and_adjoint(mixed_ref, variant):
     w, ref = mixed_ref
     say("gpu", w.name, "variant", variant)
@@ -134,21 +141,22 @@ def test_mixed_64x64x32_forward_and_adjoint(mixed_ref, variant):
     es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
     mx = float(np.abs(out["G"] - ref["G"]).max() / np.abs(ref["G"]).max())
     say("  rel-L2 S", es, "G", eg, "max|dG|/max|G|", mx, "iters", out["stats_fwd"]["fwd_iters"],
-        out["stats_adj"]["adj_iters"])
+        out["stats_adj"]["adj_iters"], "resident", out["stats_fwd"]["resident"])
     assert es <= 1e-5
     assert eg <= 1e-4
 
 
 # ------------------------------------------------------------------ checkpointing, determinism
-@pytest.mark.parametrize("variant", [1, 0])
+@pytest.mark.parametrize("variant", [2, 1, 0])
 def test_checkpoint_recompute_is_bitwise(variant):
     w = wl.small_problem(40, 24, 10, 20, seed=9, dt=3.0, precision="f32", rtol=1e-6)
     gs = wl.random_surface_weights(20, 24, 40, seed=19).astype(np.float32)
     say("checkpoint full")
-    full = run_gpu(w, gs=gs, team=4, tile_z=3, variant=variant)
+    team, tz = (0, 0) if variant == 2 else (4, 3)
+    full = run_gpu(w, gs=gs, team=team, tile_z=tz, variant=variant)
     for k in (1, 7, 64):
         say("checkpoint k", k)
-        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=4, tile_z=3, variant=variant)
+        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=team, tile_z=tz, variant=variant)
         assert np.array_equal(ck["S"], full["S"])
         assert np.array_equal(ck["G"], full["G"])
         if k < 20:
