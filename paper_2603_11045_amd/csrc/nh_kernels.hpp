@@ -101,10 +101,11 @@ template <typename R> __device__ __forceinline__ R rcp(R v);
 template <> __device__ __forceinline__ float rcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ __forceinline__ double rcp<double>(double v) { return 1.0 / v; }
 
-// Store of a sweep output. (Non-temporal stores were measured slower here:
-// they bypass the last-level cache that the next sweep reads from.)
+// Store of a sweep output: device-scope (write-through), so the team barrier's
+// L2 write-back finds little dirty data. (Non-temporal stores were measured
+// slower: they bypass the last-level cache that the next sweep reads from.)
 template <typename T>
-__device__ __forceinline__ void st_out(T* p, T v) { *p = v; }
+__device__ __forceinline__ void st_out(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // dt * c_f = s * a*b/(a+b) with s = 2 dt / h^2 (Prop. 1); b = 0 outside the grid gives 0.
 template <typename R>

@@ -395,6 +395,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
     ok &= team_sum_dev<1>(S, rank, red, acc1, rs);
     stamp();
     double a_cg = gam / acc1[0], b_cg = 0.0;
+    float a_prev = 0.f;
     int cur = 0;
     while (ok) {
       if (it >= S.max_iter) { status |= kNoConv; break; }
@@ -406,19 +407,23 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
       asm volatile("" : "+v"(col_l));
       const float a = (float)a_cg, b = (float)b_cg;
       const bool first = it == 0;
-      // elementwise updates: s = w + b s, p = u + b p, u -= a s in registers, x += a p in memory
+      // elementwise updates: s = w + b s, p = u + b p, u -= a s in registers.
+      // x (in memory) is advanced every second iteration by both pending
+      // steps, x += a_prev p_prev + a p, which halves its traffic.
+      const bool xstep = (it & 1) != 0;
 #pragma unroll
       for (int z = 0; z < TZ; ++z) {
         const float s_ = first ? wr[z] : fmaf(b, sr[z], wr[z]);
         const float p_ = first ? ur[z] : fmaf(b, pr[z], ur[z]);
-        if (q.own && z < q.tzn) {
+        if (xstep && q.own && z < q.tzn) {
           float* xp = S.x + col_l + (T.z0 + z) * nxy_l;
-          *xp = fmaf(a, p_, *xp);
+          *xp = fmaf(a, p_, fmaf(a_prev, pr[z], *xp));
         }
         pr[z] = p_;
         sr[z] = s_;
         ur[z] = fmaf(-a, s_, ur[z]);
       }
+      a_prev = a;
       // halo values of the new u from the neighbours' published u, w/D, s/D
       const float* uo = ub[cur];
       const float* wo = wb[cur];
@@ -468,6 +473,16 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
       b_cg = gn / gam;
       a_cg = gn / (dn - b_cg * gn / a_cg);
       gam = gn;
+    }
+    if ((it & 1) && q.own) {
+      // the last iteration's step a p is still pending
+#pragma unroll
+      for (int z = 0; z < TZ; ++z) {
+        if (z < q.tzn) {
+          float* xp = S.x + q.col + (T.z0 + z) * nxy;
+          *xp = fmaf(a_prev, pr[z], *xp);
+        }
+      }
     }
   }
   if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
