@@ -165,6 +165,120 @@ void nh_destroy(nh_ctx *ctx);
  * traffic (8 bytes per element) to calibrate hardware byte counters. */
 nh_status nh_copy_f32(const float *src, float *dst, size_t n, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of inversion jobs (the reconstruction loop
+ * of Sec. 4.3 run for many independent requests on one GPU).
+ *
+ * A job is one forward + adjoint pass of a candidate field alpha against
+ * surface measurements: forward sweep T^1..T^N (eq. nefty_obj's implicit
+ * Euler steps, FP32 vectors with FP64 reductions), the mean squared error
+ * L = mean over all n, i, j of (S^n_ij - target^n_ij)^2 with its gradient
+ * dL/dS = 2 (S - target) / (N nx ny), then the adjoint sweep and dL/dalpha
+ * (eq. adjoint_eq and eq. grad_assembly), exactly as nh_forward + nh_adjoint
+ * compute them with full trajectory storage.
+ *
+ * The server keeps every admitted job's state in device memory and advances
+ * all admitted jobs together: each nh_server_tick() makes one cooperative
+ * launch in which each job performs one implicit-Euler step (forward, or
+ * adjoint once its forward is done) with its own team of workgroups and its
+ * own reductions. Before the launch the tick admits queued jobs in arrival
+ * order while the job's device bytes fit the HBM budget and its workgroups
+ * fit the co-resident limit; after it, finished jobs are retired and their
+ * memory freed. A job's team and tiling depend only on its own grid, so its
+ * result is bit-identical alone and among other jobs.
+ *
+ * Inputs of nh_server_submit are HOST arrays, copied at submission; results
+ * come back to HOST memory. One server is driven from one host thread.
+ * ---------------------------------------------------------------------- */
+typedef struct nh_server nh_server;
+
+typedef enum {
+    NH_JOB_QUEUED = 0,   /* submitted, waiting for memory or workgroups */
+    NH_JOB_FORWARD = 1,  /* admitted, forward sweep running */
+    NH_JOB_ADJOINT = 2,  /* adjoint sweep running */
+    NH_JOB_DONE = 3,     /* loss and dL/dalpha available */
+    NH_JOB_FAILED = 4    /* a reduction was non-finite or a barrier timed out */
+} nh_job_state;
+
+typedef struct {
+    int state;              /* nh_job_state */
+    int status;             /* OR of per-step flags: 1 max_iter reached, 2 non-finite, 4 barrier timeout */
+    int team_blocks;        /* workgroups of this job's team */
+    int nsteps;
+    long long fwd_iters;    /* CG iterations summed over the forward steps */
+    long long adj_iters;
+    double loss;            /* mean squared error (valid when DONE) */
+    double t_submit_s;      /* steady clock, seconds since the first server was created */
+    double t_admit_s;
+    double t_done_s;
+    size_t device_bytes;    /* device memory held while admitted */
+} nh_job_info;
+
+typedef struct {
+    long long ticks;        /* batched launches so far */
+    double kernel_s;        /* summed duration of those launches (HIP events) */
+    size_t used_bytes;      /* device bytes held by admitted jobs */
+    int used_blocks;        /* workgroups held by admitted jobs */
+    int max_blocks;         /* co-resident workgroup limit of the batched kernel */
+    int active;
+    int queued;
+    long long jobs_done;
+    double voxel_steps;     /* sum over finished jobs of 2 * voxels * nsteps (forward + adjoint) */
+    long long cg_iters;     /* CG iterations of finished jobs */
+} nh_server_stats;
+
+/* Create a server on `hip_device` working on `hip_stream` (NULL = the null
+ * stream). hbm_budget_bytes bounds the device bytes of admitted jobs;
+ * max_blocks > 0 lowers the workgroup limit (0 = all that fit co-resident). */
+nh_status nh_server_create(nh_server **out, int hip_device, void *hip_stream, double hbm_budget_bytes,
+                           int max_blocks);
+
+/* Queue a job. HOST inputs: alpha [nz][ny][nx] (finite, > 0), q_xy [ny][nx],
+ * q_t [nsteps] (FP64), target [nsteps][ny][nx]; uniform spacing h; CG to
+ * rtol with at most max_iter iterations per solve. Writes the job id.
+ * NH_ENOMEM if the job alone exceeds the budget. */
+nh_status nh_server_submit(nh_server *s, int nx, int ny, int nz, double h, double dt, int nsteps, double rtol,
+                           int max_iter, const float *alpha, const float *q_xy, const double *q_t,
+                           const float *target, long long *job_id);
+
+/* Admit what fits, advance every admitted job by one step (one launch),
+ * retire finished jobs. Writes up to finished_cap ids of jobs that finished
+ * in this tick to HOST finished_ids (may be NULL if finished_cap is 0) and
+ * the counts; a tick with nothing admitted does nothing. Blocks until the
+ * launch has completed. */
+nh_status nh_server_tick(nh_server *s, int *n_active, int *n_queued, long long *finished_ids, int finished_cap,
+                         int *n_finished);
+
+/* State of a job; copies dL/dalpha (FP64, [nz][ny][nx], HOST) when the job
+ * is DONE or FAILED and dL_dalpha is not NULL. */
+nh_status nh_server_job(nh_server *s, long long job_id, nh_job_info *info, double *dL_dalpha);
+
+/* Forget a finished job (its host copy of dL/dalpha). NH_ESTATE if it has
+ * not finished. */
+nh_status nh_server_release(nh_server *s, long long job_id);
+
+nh_status nh_server_get_stats(const nh_server *s, nh_server_stats *out);
+const char *nh_server_last_error(const nh_server *s);
+
+/* Synchronizes the server's stream and frees everything, including the
+ * memory of jobs still running. */
+void nh_server_destroy(nh_server *s);
+
+/* Host-only helpers of the admission policy (no device needed). */
+
+/* Workgroups of a job's team: one tile of at most about 32768 voxels per
+ * workgroup, at most max_blocks / 2 workgroups (0 on bad arguments). */
+int nh_serve_job_team(int nx, int ny, int nz, int max_blocks);
+
+/* Device bytes a job holds while admitted (0 on bad arguments). */
+size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks);
+
+/* Number of queued jobs, taken from the head of the queue in order, that the
+ * next tick admits: the longest prefix whose bytes and workgroups, added to
+ * those already in use, stay within the budget and the workgroup limit. */
+int nh_serve_admit_count(const size_t *bytes, const int *teams, int n_queued, size_t used_bytes, int used_blocks,
+                         double budget_bytes, int max_blocks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,13 @@ STATUS_NAMES = {0: "NH_OK", -1: "NH_EINVAL", -2: "NH_ENOMEM", -3: "NH_ESTATE", -
 
 EXPORTED = ["nh_create", "nh_set_grid", "nh_set_solver", "nh_forward", "nh_adjoint",
             "nh_forward_f64", "nh_adjoint_f64", "nh_get_state", "nh_apply_A", "nh_set_launch",
-            "nh_set_cg_variant", "nh_set_barrier_timeout", "nh_get_stats", "nh_last_error", "nh_destroy", "nh_copy_f32"]
+            "nh_set_cg_variant", "nh_set_barrier_timeout", "nh_get_stats", "nh_last_error", "nh_destroy", "nh_copy_f32",
+            "nh_server_create", "nh_server_submit", "nh_server_tick", "nh_server_job", "nh_server_release",
+            "nh_server_get_stats", "nh_server_last_error", "nh_server_destroy", "nh_serve_job_team",
+            "nh_serve_job_bytes", "nh_serve_admit_count"]
+
+NH_JOB_QUEUED, NH_JOB_FORWARD, NH_JOB_ADJOINT, NH_JOB_DONE, NH_JOB_FAILED = range(5)
+JOB_STATE_NAMES = {0: "queued", 1: "forward", 2: "adjoint", 3: "done", 4: "failed"}
 
 
 class nh_stats(ctypes.Structure):
@@ -56,6 +62,43 @@ class nh_stats(ctypes.Structure):
         ("tile_z", ctypes.c_int),
         ("resident", ctypes.c_int),
         ("resident_occupancy", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class nh_job_info(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("team_blocks", ctypes.c_int),
+        ("nsteps", ctypes.c_int),
+        ("fwd_iters", ctypes.c_longlong),
+        ("adj_iters", ctypes.c_longlong),
+        ("loss", ctypes.c_double),
+        ("t_submit_s", ctypes.c_double),
+        ("t_admit_s", ctypes.c_double),
+        ("t_done_s", ctypes.c_double),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class nh_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("ticks", ctypes.c_longlong),
+        ("kernel_s", ctypes.c_double),
+        ("used_bytes", ctypes.c_size_t),
+        ("used_blocks", ctypes.c_int),
+        ("max_blocks", ctypes.c_int),
+        ("active", ctypes.c_int),
+        ("queued", ctypes.c_int),
+        ("jobs_done", ctypes.c_longlong),
+        ("voxel_steps", ctypes.c_double),
+        ("cg_iters", ctypes.c_longlong),
     ]
 
     def as_dict(self):
@@ -100,9 +143,28 @@ def load():
     lib.nh_destroy.argtypes = [vp]
     lib.nh_destroy.restype = None
     lib.nh_copy_f32.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    llp = ctypes.POINTER(ctypes.c_longlong)
+    lib.nh_server_create.argtypes = [ctypes.POINTER(vp), ip, vp, dp, ip]
+    lib.nh_server_submit.argtypes = [vp, ip, ip, ip, dp, dp, ip, dp, ip, vp, vp, vp, vp, llp]
+    lib.nh_server_tick.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), llp, ip, ctypes.POINTER(ip)]
+    lib.nh_server_job.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(nh_job_info), vp]
+    lib.nh_server_release.argtypes = [vp, ctypes.c_longlong]
+    lib.nh_server_get_stats.argtypes = [vp, ctypes.POINTER(nh_server_stats)]
+    lib.nh_server_last_error.argtypes = [vp]
+    lib.nh_server_last_error.restype = ctypes.c_char_p
+    lib.nh_server_destroy.argtypes = [vp]
+    lib.nh_server_destroy.restype = None
+    lib.nh_serve_job_team.argtypes = [ip, ip, ip, ip]
+    lib.nh_serve_job_team.restype = ip
+    lib.nh_serve_job_bytes.argtypes = [ip, ip, ip, ip, ip]
+    lib.nh_serve_job_bytes.restype = ctypes.c_size_t
+    lib.nh_serve_admit_count.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ip), ip,
+                                         ctypes.c_size_t, ip, dp, ip]
+    lib.nh_serve_admit_count.restype = ip
     for name in EXPORTED:
         f = getattr(lib, name)
-        if name not in ("nh_last_error", "nh_destroy"):
+        if name not in ("nh_last_error", "nh_destroy", "nh_server_last_error", "nh_server_destroy",
+                        "nh_serve_job_team", "nh_serve_job_bytes", "nh_serve_admit_count"):
             f.restype = st
     _lib = lib
     return lib
@@ -110,3 +172,7 @@ def load():
 
 def last_error(ctx) -> str:
     return load().nh_last_error(ctx).decode(errors="replace")
+
+
+def server_last_error(srv) -> str:
+    return load().nh_server_last_error(srv).decode(errors="replace")

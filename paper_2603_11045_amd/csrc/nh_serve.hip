@@ -1,0 +1,591 @@
+// nh_serve.hip -- continuous-batching server for forward+adjoint inversion jobs.
+//
+// A job is one reconstruction request: a diffusivity field, a source, and the
+// surface measurements it is compared with (mean squared error). The server
+// keeps every admitted job's state resident in HBM and advances all of them
+// together: each tick is ONE cooperative launch of nh::batch_step_kernel in
+// which every active job performs one implicit-Euler step (forward, or
+// adjoint after its forward has finished) with its own team of workgroups and
+// its own team reductions (the same step code as the single-problem path).
+// Between ticks the host retires finished jobs, frees their memory and admits
+// queued jobs in arrival order while both the HBM budget and the co-resident
+// workgroup budget allow -- so requests that arrive while others run join at
+// the next step boundary. A job's team size and tiling depend only on the job
+// itself, so its result is bit-identical whether it runs alone or among others.
+#include "nefty_heat.h"
+#include "nh_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace nh {
+
+// Workgroup b works as rank map[b].y of job map[b].x.
+template <typename R>
+__global__ void __launch_bounds__(Cfg<R>::kBlock, 1) batch_step_kernel(const StepArgs<R>* jobs, const int2* map) {
+  __shared__ Smem<R> sh;
+  const int2 m = map[blockIdx.x];
+  const StepArgs<R> S = jobs[m.x];
+  run_step<R>(S, m.y, sh);
+}
+
+constexpr int kMseThreads = 256;
+
+// Mean squared error of the surface series: per-workgroup FP64 partial sums
+// of (S - target)^2, and g = scale * (S - target) with scale = 2 / m.
+__global__ void __launch_bounds__(kMseThreads) mse_grad_kernel(const float* S, const float* target, float* g,
+                                                               long long m, double scale, double* partial) {
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x) {
+    const double d = (double)S[i] - (double)target[i];
+    acc += d * d;
+    g[i] = (float)(scale * d);
+  }
+  __shared__ double red[kMseThreads / 64];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// loss = (sum of the partials in index order) / m
+__global__ void mse_finish_kernel(const double* partial, int n, double inv_m, double* loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    *loss = s * inv_m;
+  }
+}
+
+}  // namespace nh
+
+namespace {
+
+constexpr int kMseBlocks = 64;
+constexpr long long kVoxelsPerBlock = 32768;
+constexpr int kBlock = nh::Cfg<float>::kBlock;
+
+double now_s() {
+  static const auto t0 = std::chrono::steady_clock::now();
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Tiling of one job: x-y tiles as in the single-problem path, split in z so
+// that there are about ng / kVoxelsPerBlock tiles; one workgroup per tile up
+// to `cap` workgroups.
+void job_geom(int nx, int ny, int nz, int cap, nh::Geom& g, int& team) {
+  g = nh::Geom{};
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.nxy = (long long)nx * ny;
+  g.ng = g.nxy * nz;
+  g.TX = nx > 32 ? 64 : (nx > 16 ? 32 : 16);
+  g.TY = kBlock / g.TX;
+  g.txs = g.TX == 64 ? 6 : (g.TX == 32 ? 5 : 4);
+  g.ntx = (nx + g.TX - 1) / g.TX;
+  g.nty = (ny + g.TY - 1) / g.TY;
+  const long long xy = (long long)g.ntx * g.nty;
+  const long long want = std::max<long long>(1, (g.ng + kVoxelsPerBlock - 1) / kVoxelsPerBlock);
+  const long long want_ntz = std::max<long long>(1, (want + xy - 1) / xy);
+  int tz = (int)((nz + want_ntz - 1) / want_ntz);
+  if (tz < 4) tz = std::min(4, nz);
+  g.TZ = tz;
+  g.ntz = (nz + tz - 1) / tz;
+  g.ntiles = (int)(xy * g.ntz);
+  team = std::max(1, std::min(g.ntiles, cap));
+}
+
+size_t job_bytes(int nx, int ny, int nz, int nsteps, int team) {
+  const size_t ng = (size_t)nx * ny * nz, nxy = (size_t)nx * ny, N = (size_t)nsteps;
+  size_t b = 0;
+  b += align256(4 * ng) * 9;                                // alpha, z, p, u1, w0, w1, s0, s1, mu
+  b += align256(4 * ng * N);                                // trajectory T^1..T^N
+  b += align256(8 * ng);                                    // dL/dalpha (FP64)
+  b += align256(4 * nxy) + 3 * align256(4 * nxy * N);       // q_xy, target, S, dL/dS
+  b += align256(sizeof(nh::Slot) * ((size_t)team + 1));     // team reduction slots
+  b += align256(8 * kMseBlocks) + 4 * 256;                  // MSE partials, loss, step outputs
+  return b;
+}
+
+struct SJob {
+  long long id = 0;
+  int state = NH_JOB_QUEUED;
+  int nx = 0, ny = 0, nz = 0, nsteps = 0, max_iter = 0;
+  double h = 1, dt = 1, rtol = 1e-6;
+  std::vector<float> h_alpha, h_qxy, h_target;
+  std::vector<double> h_qt;
+  nh::Geom g{};
+  int team = 1;
+  size_t bytes = 0;
+  void* mem = nullptr;
+  float *alpha = nullptr, *qxy = nullptr, *target = nullptr, *traj = nullptr, *z = nullptr, *p0 = nullptr,
+        *u1 = nullptr, *w0 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr, *mu = nullptr,
+        *surf = nullptr, *gsurf = nullptr;
+  double *G = nullptr, *partial = nullptr, *lossbuf = nullptr, *rel_out = nullptr;
+  void* slots = nullptr;
+  int *it_out = nullptr, *st_out = nullptr;
+  int step = 0;            // the step being computed (the adjoint counts down from N)
+  long long fwd_iters = 0, adj_iters = 0;
+  int status = 0;
+  double loss = 0;
+  std::vector<double> h_G;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct nh_server {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0, max_blocks = 0;
+  double budget = 0;
+  size_t used_bytes = 0;
+  int used_blocks = 0;
+  long long next_id = 1;
+  unsigned long long launch_ctr = 0;
+  long long wallclock_khz = 100000;
+  double barrier_timeout_s = 20.0;
+  std::deque<SJob*> queue;
+  std::vector<SJob*> active;
+  std::map<long long, std::unique_ptr<SJob>> jobs;
+  std::vector<nh::StepArgs<float>> h_args;
+  std::vector<int2> h_map;
+  nh::StepArgs<float>* d_args = nullptr;
+  int2* d_map = nullptr;
+  size_t cap_args = 0, cap_map = 0;
+  int* d_flag = nullptr;
+  std::string err;
+  nh_server_stats st{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+nh_status sfail(nh_server* s, nh_status st, const std::string& m) {
+  if (s) s->err = m;
+  return st;
+}
+
+#define SV_HIP(s, call)                                                                                \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess) return sfail((s), NH_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Allocate and fill the job's device state; queues the copies on the stream.
+nh_status admit(nh_server* s, SJob* j) {
+  if (hipMalloc(&j->mem, j->bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    j->mem = nullptr;
+    return sfail(s, NH_ENOMEM, "hipMalloc for a job failed");
+  }
+  const size_t ng = (size_t)j->g.ng, nxy = (size_t)j->g.nxy, N = (size_t)j->nsteps;
+  char* p = (char*)j->mem;
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += align256(b);
+    return r;
+  };
+  j->alpha = (float*)take(4 * ng);
+  j->z = (float*)take(4 * ng);
+  j->p0 = (float*)take(4 * ng);
+  j->u1 = (float*)take(4 * ng);
+  j->w0 = (float*)take(4 * ng);
+  j->w1 = (float*)take(4 * ng);
+  j->s0 = (float*)take(4 * ng);
+  j->s1 = (float*)take(4 * ng);
+  j->mu = (float*)take(4 * ng);
+  j->traj = (float*)take(4 * ng * N);
+  j->G = (double*)take(8 * ng);
+  j->qxy = (float*)take(4 * nxy);
+  j->target = (float*)take(4 * nxy * N);
+  j->surf = (float*)take(4 * nxy * N);
+  j->gsurf = (float*)take(4 * nxy * N);
+  j->slots = take(sizeof(nh::Slot) * ((size_t)j->team + 1));
+  j->partial = (double*)take(8 * kMseBlocks);
+  j->lossbuf = (double*)take(256);
+  j->it_out = (int*)take(256);
+  j->rel_out = (double*)take(256);
+  j->st_out = (int*)take(256);
+  if ((size_t)(p - (char*)j->mem) > j->bytes) return sfail(s, NH_EINVAL, "internal: job layout exceeds its size");
+  SV_HIP(s, hipMemcpyAsync(j->alpha, j->h_alpha.data(), 4 * ng, hipMemcpyHostToDevice, s->stream));
+  SV_HIP(s, hipMemcpyAsync(j->qxy, j->h_qxy.data(), 4 * nxy, hipMemcpyHostToDevice, s->stream));
+  SV_HIP(s, hipMemcpyAsync(j->target, j->h_target.data(), 4 * nxy * N, hipMemcpyHostToDevice, s->stream));
+  SV_HIP(s, hipMemsetAsync(j->slots, 0, sizeof(nh::Slot) * ((size_t)j->team + 1), s->stream));
+  const int blocks = (int)std::min<size_t>((ng + 255) / 256, 2048);
+  hipLaunchKernelGGL(nh::fill_kernel<float>, dim3(blocks), dim3(256), 0, s->stream, j->mu, (long long)ng, 0.f);
+  hipLaunchKernelGGL(nh::fill_kernel<double>, dim3(blocks), dim3(256), 0, s->stream, j->G, (long long)ng, 0.0);
+  SV_HIP(s, hipGetLastError());
+  j->state = NH_JOB_FORWARD;
+  j->step = 1;
+  j->t_admit = now_s();
+  s->used_bytes += j->bytes;
+  s->used_blocks += j->team;
+  return NH_OK;
+}
+
+void retire(nh_server* s, SJob* j) {
+  if (j->mem) (void)hipFree(j->mem);
+  j->mem = nullptr;
+  s->used_bytes -= j->bytes;
+  s->used_blocks -= j->team;
+}
+
+// Arguments of job j's current step.
+nh::StepArgs<float> job_args(const nh_server* s, const SJob* j, unsigned long long epoch_base) {
+  nh::StepArgs<float> S;
+  std::memset(&S, 0, sizeof(S));
+  S.g = j->g;
+  const float sd = (float)(2.0 * j->dt / (j->h * j->h));
+  S.sx = S.sy = S.sz = sd;
+  S.alpha = j->alpha;
+  S.z = j->z;
+  S.p0 = j->p0;
+  S.u1 = j->u1;
+  S.w0 = j->w0;
+  S.w1 = j->w1;
+  S.s0 = j->s0;
+  S.s1 = j->s1;
+  S.variant = 1;
+  S.slots = j->slots;
+  S.epoch_base = epoch_base;
+  S.rtol2 = j->rtol * j->rtol;
+  S.max_iter = j->max_iter;
+  S.team = j->team;
+  S.xcd_order = 0;
+  S.out_iters = j->it_out;
+  S.out_relres = j->rel_out;
+  S.out_status = j->st_out;
+  S.err_flag = s->d_flag;
+  S.timeout_ticks = (long long)(s->barrier_timeout_s * (double)s->wallclock_khz * 1000.0);
+  const size_t ng = (size_t)j->g.ng, nxy = (size_t)j->g.nxy;
+  const int n = j->step;
+  if (j->state == NH_JOB_FORWARD) {
+    S.mode = nh::kForward;
+    S.x = j->traj + (size_t)(n - 1) * ng;
+    S.xprev = n == 1 ? nullptr : j->traj + (size_t)(n - 2) * ng;
+    S.top_src = j->qxy;
+    S.top_scale = (float)(j->dt * j->h_qt[n - 1]);
+    S.surf_out = j->surf + (size_t)(n - 1) * nxy;
+  } else {
+    S.mode = nh::kAdjoint;
+    S.x = j->mu;
+    S.top_src = j->gsurf + (size_t)(n - 1) * nxy;
+    S.top_scale = 1.f;
+    S.T_grad = j->traj + (size_t)(n - 1) * ng;
+    S.G = j->G;
+  }
+  return S;
+}
+
+template <typename T>
+nh_status grow(nh_server* s, T*& p, size_t& cap, size_t need) {
+  if (cap >= need) return NH_OK;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+  SV_HIP(s, hipMalloc(&p, sizeof(T) * need));
+  cap = need;
+  return NH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nh_serve_job_team(int nx, int ny, int nz, int max_blocks) {
+  if (nx < 1 || ny < 1 || nz < 1 || max_blocks < 1) return 0;
+  nh::Geom g;
+  int team = 0;
+  job_geom(nx, ny, nz, std::max(1, max_blocks / 2), g, team);
+  return team;
+}
+
+size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks) {
+  if (nx < 1 || ny < 1 || nz < 1 || nsteps < 1 || team_blocks < 1) return 0;
+  return job_bytes(nx, ny, nz, nsteps, team_blocks);
+}
+
+int nh_serve_admit_count(const size_t* bytes, const int* teams, int n_queued, size_t used_bytes, int used_blocks,
+                         double budget_bytes, int max_blocks) {
+  if (!bytes || !teams || n_queued < 1) return 0;
+  int n = 0;
+  double b = (double)used_bytes;
+  long long w = used_blocks;
+  for (; n < n_queued; ++n) {
+    if (b + (double)bytes[n] > budget_bytes || w + teams[n] > max_blocks) break;
+    b += (double)bytes[n];
+    w += teams[n];
+  }
+  return n;
+}
+
+nh_status nh_server_create(nh_server** out, int hip_device, void* hip_stream, double hbm_budget_bytes,
+                           int max_blocks) {
+  if (!out) return NH_EINVAL;
+  *out = nullptr;
+  if (!(hbm_budget_bytes > 0) || max_blocks < 0) return NH_EINVAL;
+  now_s();
+  std::unique_ptr<nh_server> s(new (std::nothrow) nh_server());
+  if (!s) return NH_ENOMEM;
+  if (hipSetDevice(hip_device) != hipSuccess) return NH_EINVAL;
+  s->device = hip_device;
+  s->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return NH_EHIP;
+  s->num_cu = prop.multiProcessorCount;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)nh::batch_step_kernel<float>, kBlock, 0) !=
+          hipSuccess ||
+      occ < 1)
+    return NH_EHIP;
+  s->max_blocks = occ * s->num_cu;
+  if (max_blocks > 0) s->max_blocks = std::min(s->max_blocks, max_blocks);
+  s->budget = hbm_budget_bytes;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
+    s->wallclock_khz = khz;
+  if (hipMalloc(&s->d_flag, 64) != hipSuccess) return NH_ENOMEM;
+  if (hipMemset(s->d_flag, 0, 64) != hipSuccess || hipEventCreate(&s->ev0) != hipSuccess ||
+      hipEventCreate(&s->ev1) != hipSuccess) {
+    (void)hipFree(s->d_flag);
+    return NH_EHIP;
+  }
+  s->st.max_blocks = s->max_blocks;
+  *out = s.release();
+  return NH_OK;
+}
+
+nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, double dt, int nsteps, double rtol,
+                           int max_iter, const float* alpha, const float* q_xy, const double* q_t,
+                           const float* target, long long* job_id) {
+  if (!s) return NH_EINVAL;
+  if (!job_id || !alpha || !q_xy || !q_t || !target) return sfail(s, NH_EINVAL, "null pointer argument");
+  if (nx < 1 || ny < 1 || nz < 1 || nsteps < 1 || !(dt > 0) || !std::isfinite(dt) || !(h > 0) ||
+      !std::isfinite(h) || !(rtol > 0) || !(rtol < 1) || max_iter < 1)
+    return sfail(s, NH_EINVAL, "bad job parameters");
+  const size_t ng = (size_t)nx * ny * nz, nxy = (size_t)nx * ny, N = (size_t)nsteps;
+  for (size_t i = 0; i < ng; ++i)
+    if (!(alpha[i] > 0.f) || !std::isfinite(alpha[i])) return sfail(s, NH_EINVAL, "alpha must be finite and > 0");
+  for (size_t i = 0; i < nxy; ++i)
+    if (!std::isfinite(q_xy[i])) return sfail(s, NH_EINVAL, "q_xy holds a non-finite value");
+  for (size_t i = 0; i < N; ++i)
+    if (!std::isfinite(q_t[i])) return sfail(s, NH_EINVAL, "q_t holds a non-finite value");
+  for (size_t i = 0; i < nxy * N; ++i)
+    if (!std::isfinite(target[i])) return sfail(s, NH_EINVAL, "target holds a non-finite value");
+  auto j = std::make_unique<SJob>();
+  j->nx = nx; j->ny = ny; j->nz = nz;
+  j->h = h;
+  j->dt = dt;
+  j->nsteps = nsteps;
+  j->rtol = rtol;
+  j->max_iter = max_iter;
+  int team = 0;
+  job_geom(nx, ny, nz, std::max(1, s->max_blocks / 2), j->g, team);
+  j->team = team;
+  j->bytes = job_bytes(nx, ny, nz, nsteps, team);
+  if ((double)j->bytes > s->budget) return sfail(s, NH_ENOMEM, "job larger than the HBM budget");
+  j->h_alpha.assign(alpha, alpha + ng);
+  j->h_qxy.assign(q_xy, q_xy + nxy);
+  j->h_qt.assign(q_t, q_t + N);
+  j->h_target.assign(target, target + nxy * N);
+  j->id = s->next_id++;
+  j->t_submit = now_s();
+  *job_id = j->id;
+  s->queue.push_back(j.get());
+  s->jobs[j->id] = std::move(j);
+  return NH_OK;
+}
+
+nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* finished_ids, int finished_cap,
+                         int* n_finished) {
+  if (!s) return NH_EINVAL;
+  if (finished_cap > 0 && !finished_ids) return sfail(s, NH_EINVAL, "finished_ids is null");
+  if (hipSetDevice(s->device) != hipSuccess) return sfail(s, NH_EHIP, "hipSetDevice failed");
+  int finished = 0;
+
+  // admission, in arrival order
+  {
+    std::vector<size_t> qb;
+    std::vector<int> qt;
+    for (const SJob* j : s->queue) {
+      qb.push_back(j->bytes);
+      qt.push_back(j->team);
+    }
+    const int na = nh_serve_admit_count(qb.data(), qt.data(), (int)qb.size(), s->used_bytes, s->used_blocks,
+                                        s->budget, s->max_blocks);
+    for (int k = 0; k < na; ++k) {
+      SJob* j = s->queue.front();
+      const nh_status st = admit(s, j);
+      if (st != NH_OK) return st;
+      s->queue.pop_front();
+      s->active.push_back(j);
+    }
+    if (na > 0) {
+      // the host copies of the inputs may go once the uploads are done
+      SV_HIP(s, hipStreamSynchronize(s->stream));
+      for (int k = 0; k < na; ++k) {
+        SJob* j = s->active[s->active.size() - na + k];
+        std::vector<float>().swap(j->h_alpha);
+        std::vector<float>().swap(j->h_target);
+      }
+    }
+  }
+
+  if (!s->active.empty()) {
+    const unsigned long long base = (++s->launch_ctr) << 24;
+    s->h_args.clear();
+    s->h_map.clear();
+    for (size_t k = 0; k < s->active.size(); ++k) {
+      const SJob* j = s->active[k];
+      s->h_args.push_back(job_args(s, j, base));
+      for (int r = 0; r < j->team; ++r) s->h_map.push_back(make_int2((int)k, r));
+    }
+    if ((int)s->h_map.size() > s->max_blocks) return sfail(s, NH_EINVAL, "internal: workgroups exceed the limit");
+    nh_status gs = grow(s, s->d_args, s->cap_args, std::max<size_t>(s->h_args.size(), 64));
+    if (gs != NH_OK) return gs;
+    gs = grow(s, s->d_map, s->cap_map, (size_t)s->max_blocks);
+    if (gs != NH_OK) return gs;
+    SV_HIP(s, hipMemcpyAsync(s->d_args, s->h_args.data(), sizeof(nh::StepArgs<float>) * s->h_args.size(),
+                             hipMemcpyHostToDevice, s->stream));
+    SV_HIP(s, hipMemcpyAsync(s->d_map, s->h_map.data(), sizeof(int2) * s->h_map.size(), hipMemcpyHostToDevice,
+                             s->stream));
+    void* args[] = {(void*)&s->d_args, (void*)&s->d_map};
+    SV_HIP(s, hipEventRecord(s->ev0, s->stream));
+    SV_HIP(s, hipLaunchCooperativeKernel((const void*)nh::batch_step_kernel<float>, dim3((unsigned)s->h_map.size()),
+                                         dim3(kBlock), args, 0, s->stream));
+    SV_HIP(s, hipEventRecord(s->ev1, s->stream));
+    // after a job's last forward step: loss and dL/dS of the mean squared error
+    for (const SJob* j : s->active) {
+      if (j->state == NH_JOB_FORWARD && j->step == j->nsteps) {
+        const long long m = j->g.nxy * (long long)j->nsteps;
+        hipLaunchKernelGGL(nh::mse_grad_kernel, dim3(kMseBlocks), dim3(nh::kMseThreads), 0, s->stream, j->surf,
+                           j->target, j->gsurf, m, 2.0 / (double)m, j->partial);
+        hipLaunchKernelGGL(nh::mse_finish_kernel, dim3(1), dim3(64), 0, s->stream, j->partial, kMseBlocks,
+                           1.0 / (double)m, j->lossbuf);
+        SV_HIP(s, hipGetLastError());
+      }
+    }
+    std::vector<int> its(s->active.size()), sts(s->active.size());
+    for (size_t k = 0; k < s->active.size(); ++k) {
+      SV_HIP(s, hipMemcpyAsync(&its[k], s->active[k]->it_out, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+      SV_HIP(s, hipMemcpyAsync(&sts[k], s->active[k]->st_out, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    }
+    SV_HIP(s, hipStreamSynchronize(s->stream));
+    float ms = 0.f;
+    SV_HIP(s, hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->st.kernel_s += 1e-3 * ms;
+    ++s->st.ticks;
+
+    std::vector<SJob*> still;
+    still.reserve(s->active.size());
+    for (size_t k = 0; k < s->active.size(); ++k) {
+      SJob* j = s->active[k];
+      j->status |= sts[k];
+      if (j->state == NH_JOB_FORWARD) {
+        j->fwd_iters += its[k];
+        if (j->step == j->nsteps)
+          j->state = NH_JOB_ADJOINT;  // the adjoint starts at step N
+        else
+          ++j->step;
+        still.push_back(j);
+        continue;
+      }
+      j->adj_iters += its[k];
+      if (j->step > 1) {
+        --j->step;
+        still.push_back(j);
+        continue;
+      }
+      const size_t ng = (size_t)j->g.ng;
+      j->h_G.resize(ng);
+      SV_HIP(s, hipMemcpyAsync(j->h_G.data(), j->G, 8 * ng, hipMemcpyDeviceToHost, s->stream));
+      SV_HIP(s, hipMemcpyAsync(&j->loss, j->lossbuf, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      SV_HIP(s, hipStreamSynchronize(s->stream));
+      j->state = (j->status & (nh::kNonFinite | nh::kTimeout)) ? NH_JOB_FAILED : NH_JOB_DONE;
+      j->t_done = now_s();
+      retire(s, j);
+      s->st.jobs_done += 1;
+      s->st.voxel_steps += 2.0 * (double)ng * j->nsteps;
+      s->st.cg_iters += j->fwd_iters + j->adj_iters;
+      if (finished < finished_cap) finished_ids[finished] = j->id;
+      ++finished;
+    }
+    s->active.swap(still);
+  }
+  if (n_active) *n_active = (int)s->active.size();
+  if (n_queued) *n_queued = (int)s->queue.size();
+  if (n_finished) *n_finished = finished;
+  return NH_OK;
+}
+
+nh_status nh_server_job(nh_server* s, long long job_id, nh_job_info* info, double* dL_dalpha) {
+  if (!s) return NH_EINVAL;
+  if (!info) return sfail(s, NH_EINVAL, "info is null");
+  auto it = s->jobs.find(job_id);
+  if (it == s->jobs.end()) return sfail(s, NH_EINVAL, "unknown job id");
+  const SJob* j = it->second.get();
+  std::memset(info, 0, sizeof(*info));
+  info->state = j->state;
+  info->status = j->status;
+  info->team_blocks = j->team;
+  info->nsteps = j->nsteps;
+  info->fwd_iters = j->fwd_iters;
+  info->adj_iters = j->adj_iters;
+  info->loss = j->loss;
+  info->t_submit_s = j->t_submit;
+  info->t_admit_s = j->t_admit;
+  info->t_done_s = j->t_done;
+  info->device_bytes = j->bytes;
+  if (dL_dalpha && !j->h_G.empty()) std::memcpy(dL_dalpha, j->h_G.data(), sizeof(double) * j->h_G.size());
+  return NH_OK;
+}
+
+nh_status nh_server_release(nh_server* s, long long job_id) {
+  if (!s) return NH_EINVAL;
+  auto it = s->jobs.find(job_id);
+  if (it == s->jobs.end()) return sfail(s, NH_EINVAL, "unknown job id");
+  if (it->second->state != NH_JOB_DONE && it->second->state != NH_JOB_FAILED)
+    return sfail(s, NH_ESTATE, "job has not finished");
+  s->jobs.erase(it);
+  return NH_OK;
+}
+
+nh_status nh_server_get_stats(const nh_server* s, nh_server_stats* out) {
+  if (!s || !out) return NH_EINVAL;
+  *out = s->st;
+  out->used_bytes = s->used_bytes;
+  out->used_blocks = s->used_blocks;
+  out->max_blocks = s->max_blocks;
+  out->active = (int)s->active.size();
+  out->queued = (int)s->queue.size();
+  return NH_OK;
+}
+
+const char* nh_server_last_error(const nh_server* s) { return s ? s->err.c_str() : "null server"; }
+
+void nh_server_destroy(nh_server* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  (void)hipStreamSynchronize(s->stream);
+  for (SJob* j : s->active) retire(s, j);
+  if (s->d_args) (void)hipFree(s->d_args);
+  if (s->d_map) (void)hipFree(s->d_map);
+  if (s->d_flag) (void)hipFree(s->d_flag);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  delete s;
+}
+
+}  // extern "C"

@@ -42,14 +42,17 @@ class Solver:
 
     ``precision`` is ``"f32"`` (FP32 vectors, FP64 reductions and gradient) or
     ``"f64"``. ``checkpoint_every = k > 0`` keeps every k-th state and
-    recomputes segments in the adjoint; 0 keeps all states.
+    recomputes segments in the adjoint; 0 keeps all states. ``cg_variant``
+    selects the CG form: 0 two reductions per iteration, 1 one reduction
+    (streaming kernel), 2 one reduction with the register-resident kernel
+    where the grid fits on the chip, else as 1.
     """
 
     def __init__(self, nx: int, ny: int, nz: int, h: Sequence[float] = (1.0, 1.0, 1.0),
                  rtol: float = 1e-6, max_iter: int = 1000, checkpoint_every: int = 0,
                  precision: str = "f32", device: Optional[int] = None,
                  stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
-                 tile_z: int = 0, profile: bool = False, cg_variant: int = 1):
+                 tile_z: int = 0, profile: bool = False, cg_variant: int = 2):
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.lib = _lib.load()

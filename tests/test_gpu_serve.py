@@ -1,0 +1,191 @@
+"""Serving path on the GPU: each job of a continuous batch against the FP64
+oracle, and the same job alone versus in a mix (bit-identical).
+
+Tolerances as for the single-problem FP32 path (global relative L2): loss
+1e-5 relative, dL/dalpha 1e-4. The oracle solves every step to 1e-13; the
+server to the job's rtol of 1e-7.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import heat as orc
+from paper_2603_11045_amd import _lib
+from paper_2603_11045_amd import workloads as wl
+from paper_2603_11045_amd.serve import Request, Server, serve_stream, sequential_stream
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-7
+
+# (nx, ny, nz, nsteps, seed): one workgroup to several, ragged x and y tiles
+JOBS = [(20, 12, 6, 8, 11), (70, 40, 24, 6, 12), (33, 17, 9, 10, 13), (96, 20, 40, 5, 14)]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    _lib.load()
+
+
+def make_job(nx, ny, nz, nsteps, seed):
+    w = wl.small_problem(nx, ny, nz, nsteps, seed, dt=2.0, sigma=0.5, precision="f32", pulse_steps=3)
+    src = orc.source_series(w.q_xy, w.q_t)
+    St, _, _ = orc.forward(w.alpha_target, src, w.dt, rtol=1e-13, keep_states=False)
+    return w, St.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def jobs():
+    out = []
+    for spec in JOBS:
+        w, target = make_job(*spec)
+        src = orc.source_series(w.q_xy, w.q_t)
+        S, T_all, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-13)
+        L, gs = orc.mse_loss_and_grad(S, target)
+        G, _, _, _ = orc.adjoint(w.alpha, T_all, gs, w.dt, rtol=1e-13)
+        out.append(dict(w=w, target=target, L=L, G=G))
+    return out
+
+
+def submit(srv, j):
+    w = j["w"]
+    return srv.submit(w.alpha, w.q_xy, w.q_t, j["target"], w.dt, 1.0, RTOL, 2000)
+
+
+def test_batched_jobs_match_oracle(jobs):
+    srv = Server(hbm_budget_bytes=8e9)
+    ids = [submit(srv, j) for j in jobs]
+    done = srv.run_until_idle()
+    assert sorted(done) == sorted(ids)
+    for jid, j in zip(ids, jobs):
+        loss, G, inf = srv.result(jid)
+        say(j["w"].name, "team", inf["team_blocks"], "iters", inf["fwd_iters"], inf["adj_iters"],
+            "loss rel", abs(loss - j["L"]) / j["L"], "G rel", rel_l2(G, j["G"]))
+        assert inf["state"] == _lib.NH_JOB_DONE and inf["status"] == 0
+        assert abs(loss - j["L"]) <= 1e-5 * j["L"]
+        assert rel_l2(G, j["G"]) <= 1e-4
+    st = srv.stats()
+    assert st["jobs_done"] == len(jobs) and st["active"] == 0 and st["used_bytes"] == 0
+    assert st["ticks"] == max(2 * j["w"].nsteps for j in jobs)
+    srv.close()
+
+
+def test_alone_equals_mixed(jobs):
+    alone = []
+    for j in jobs:
+        srv = Server(hbm_budget_bytes=8e9)
+        jid = submit(srv, j)
+        srv.run_until_idle()
+        alone.append(srv.result(jid)[:2])
+        srv.close()
+    # the mix: staggered arrivals, jobs join while others are in their
+    # forward or adjoint sweeps
+    srv = Server(hbm_budget_bytes=8e9)
+    ids = [submit(srv, jobs[0])]
+    for k in range(3):
+        srv.tick()
+    ids.append(submit(srv, jobs[1]))
+    ids.append(submit(srv, jobs[2]))
+    for k in range(9):
+        srv.tick()
+    ids.append(submit(srv, jobs[3]))
+    srv.run_until_idle()
+    for jid, (La, Ga), j in zip(ids, alone, jobs):
+        Lm, Gm, _ = srv.result(jid)
+        say(j["w"].name, "alone vs mixed max |dG|", float(np.max(np.abs(Gm - Ga))))
+        assert Lm == La
+        assert np.array_equal(Gm, Ga)
+    srv.close()
+
+
+def test_budget_limits_concurrency(jobs):
+    lib = _lib.load()
+    w0 = jobs[1]["w"]
+    t = lib.nh_serve_job_team(w0.nx, w0.ny, w0.nz, 256)
+    b1 = lib.nh_serve_job_bytes(w0.nx, w0.ny, w0.nz, w0.nsteps, t)
+    srv = Server(hbm_budget_bytes=1.5 * b1)
+    ids = [submit(srv, jobs[1]) for _ in range(3)]
+    peak_active = 0
+    while True:
+        na, nq, _ = srv.tick()
+        st = srv.stats()
+        assert st["used_bytes"] <= 1.5 * b1
+        peak_active = max(peak_active, na)
+        if na == 0 and nq == 0:
+            break
+    assert peak_active == 1
+    res = [srv.result(i) for i in ids]
+    for L, G, _ in res[1:]:
+        assert L == res[0][0] and np.array_equal(G, res[0][1])
+    srv.close()
+
+
+def test_workgroup_limit_limits_concurrency(jobs):
+    # max_blocks = 8: the 6-workgroup job cannot share the chip with the 4-workgroup one
+    srv = Server(hbm_budget_bytes=8e9, max_blocks=8)
+    ids = [submit(srv, jobs[1]), submit(srv, jobs[3]), submit(srv, jobs[0])]
+    teams = []
+    while True:
+        na, nq, _ = srv.tick()
+        st = srv.stats()
+        assert st["used_blocks"] <= 8
+        teams.append(st["used_blocks"])
+        if na == 0 and nq == 0:
+            break
+    for jid, j in zip(ids, [jobs[1], jobs[3], jobs[0]]):
+        L, G, inf = srv.result(jid)
+        assert inf["team_blocks"] <= 4
+        assert rel_l2(G, j["G"]) <= 1e-4
+    srv.close()
+
+
+def test_submit_errors(jobs):
+    srv = Server(hbm_budget_bytes=1e6)
+    w = jobs[1]["w"]
+    with pytest.raises(_lib.NHError) as e:
+        submit(srv, jobs[1])
+    assert e.value.code == _lib.NH_ENOMEM
+    srv.close()
+    srv = Server(hbm_budget_bytes=8e9)
+    bad = w.alpha.copy()
+    bad[0, 0, 0] = 0.0
+    with pytest.raises(_lib.NHError) as e:
+        srv.submit(bad, w.q_xy, w.q_t, jobs[1]["target"], w.dt)
+    assert e.value.code == _lib.NH_EINVAL
+    with pytest.raises(_lib.NHError) as e:
+        srv.submit(w.alpha, w.q_xy, w.q_t, jobs[1]["target"], -1.0)
+    assert e.value.code == _lib.NH_EINVAL
+    jid = submit(srv, jobs[0])
+    with pytest.raises(_lib.NHError) as e:
+        srv.release(jid)
+    assert e.value.code == _lib.NH_ESTATE
+    srv.run_until_idle()
+    srv.release(jid)
+    srv.close()
+
+
+def test_stream_driver_and_sequential_baseline_agree(jobs):
+    reqs = [Request(0.002 * k, j["w"].alpha, j["w"].q_xy, j["w"].q_t, j["target"], j["w"].dt, 1.0, RTOL, 2000)
+            for k, j in enumerate(jobs)]
+    a = serve_stream(reqs, hbm_budget_bytes=8e9, keep_grads=True)
+    b = sequential_stream(reqs, keep_grads=True)
+    for k, j in enumerate(jobs):
+        assert abs(a.losses[k] - j["L"]) <= 1e-5 * j["L"]
+        assert abs(b.losses[k] - j["L"]) <= 1e-5 * j["L"]
+        assert rel_l2(a.grads[k], j["G"]) <= 1e-4
+        assert rel_l2(b.grads[k], j["G"]) <= 1e-4
+    sa, sb = a.summary(), b.summary()
+    say("served", sa)
+    say("sequential", sb)
+    assert sa["jobs"] == sb["jobs"] == len(jobs)

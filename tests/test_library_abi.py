@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     with open(os.path.join(ROOT, "include", "nefty_heat.h")) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^(?:nh_status|const char \*|void)\s*(nh_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:nh_status|const char \*|void|int|size_t)\s*(nh_\w+)\s*\(", text, re.M)))
 
 
 def test_header_and_binding_agree():
@@ -24,12 +24,18 @@ def test_library_exports_every_declared_symbol():
         assert getattr(lib, name) is not None, name
 
 
-def test_stats_struct_matches_header_fields():
+def struct_fields(name):
     with open(os.path.join(ROOT, "include", "nefty_heat.h")) as f:
         text = f.read()
-    body = text[text.index("typedef struct {"):text.index("} nh_stats;")]
-    fields = re.findall(r"\b([a-z_0-9]+)\s*[;,]", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
-    assert fields == [n for n, _ in _lib.nh_stats._fields_]
+    end = text.index("} %s;" % name)
+    body = text[text.rindex("typedef struct {", 0, end):end]
+    return re.findall(r"\b([a-z_0-9]+)\s*[;,]", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+
+
+def test_structs_match_header_fields():
+    for cname, py in (("nh_stats", _lib.nh_stats), ("nh_job_info", _lib.nh_job_info),
+                      ("nh_server_stats", _lib.nh_server_stats)):
+        assert struct_fields(cname) == [n for n, _ in py._fields_], cname
 
 
 def test_null_context_calls_fail_cleanly():
@@ -38,3 +44,7 @@ def test_null_context_calls_fail_cleanly():
     assert lib.nh_last_error(None) == b"null context"
     assert lib.nh_copy_f32(None, None, 4, None) == _lib.NH_EINVAL
     lib.nh_destroy(None)
+    assert lib.nh_server_tick(None, None, None, None, 0, None) == _lib.NH_EINVAL
+    assert lib.nh_server_last_error(None) == b"null server"
+    assert lib.nh_server_create(None, 0, None, 1e9, 0) == _lib.NH_EINVAL
+    lib.nh_server_destroy(None)

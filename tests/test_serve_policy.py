@@ -1,0 +1,96 @@
+"""Host-side admission policy of the serving path (no GPU needed).
+
+The server admits queued jobs in arrival order: the longest prefix of the
+queue whose device bytes and workgroups, added to those in use, fit the HBM
+budget and the co-resident workgroup limit. These tests call the library's
+host-only helpers through the C ABI.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2603_11045_amd import _lib
+from paper_2603_11045_amd import workloads as wl
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def admit(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks):
+    n = len(bytes_)
+    b = (ctypes.c_size_t * max(n, 1))(*bytes_)
+    t = (ctypes.c_int * max(n, 1))(*teams)
+    return lib.nh_serve_admit_count(b, t, n, used_bytes, used_blocks, float(budget), max_blocks)
+
+
+def test_admit_prefix_by_budget(lib):
+    assert admit(lib, [10, 10, 10], [1, 1, 1], 0, 0, 25, 100) == 2
+    assert admit(lib, [10, 10, 10], [1, 1, 1], 0, 0, 30, 100) == 3
+    assert admit(lib, [10, 10, 10], [1, 1, 1], 6, 0, 25, 100) == 1
+    assert admit(lib, [10], [1], 20, 0, 25, 100) == 0
+
+
+def test_admit_prefix_by_workgroups(lib):
+    assert admit(lib, [1, 1, 1], [100, 100, 100], 0, 0, 1e18, 256) == 2
+    assert admit(lib, [1, 1, 1], [100, 100, 100], 0, 100, 1e18, 256) == 1
+    assert admit(lib, [1], [256], 0, 0, 1e18, 256) == 1
+    assert admit(lib, [1], [257], 0, 0, 1e18, 256) == 0
+
+
+def test_admission_is_in_arrival_order(lib):
+    # a large job at the head blocks smaller ones behind it (no overtaking)
+    assert admit(lib, [100, 1, 1], [1, 1, 1], 0, 0, 50, 100) == 0
+    assert admit(lib, [1, 100, 1], [1, 1, 1], 0, 0, 50, 100) == 1
+
+
+def test_admit_edge_cases(lib):
+    assert admit(lib, [], [], 0, 0, 10, 10) == 0
+    assert lib.nh_serve_admit_count(None, None, 3, 0, 0, 10.0, 10) == 0
+
+
+def test_job_team_sizes(lib):
+    # about one workgroup per 32768 voxels, one tile each, capped at half the limit
+    teams = {g: lib.nh_serve_job_team(*g, 256) for g in wl.SERVE_GRIDS}
+    assert teams[(32, 32, 16)] == 1
+    assert teams[(64, 64, 32)] == 4
+    assert teams[(96, 96, 32)] == 12
+    assert teams[(128, 128, 48)] == 32
+    assert teams[(192, 192, 48)] == 72
+    for g, t in teams.items():
+        ng = g[0] * g[1] * g[2]
+        assert 1 <= t <= 128
+        assert ng / t <= 2 * 32768 + 1
+    assert lib.nh_serve_job_team(192, 192, 48, 64) == 32
+    assert lib.nh_serve_job_team(0, 1, 1, 256) == 0
+    assert lib.nh_serve_job_team(4, 4, 4, 0) == 0
+
+
+def test_job_bytes(lib):
+    for (nx, ny, nz) in wl.SERVE_GRIDS:
+        for ns in wl.SERVE_STEPS:
+            team = lib.nh_serve_job_team(nx, ny, nz, 256)
+            b = lib.nh_serve_job_bytes(nx, ny, nz, ns, team)
+            ng, nxy = nx * ny * nz, nx * ny
+            floor = 4 * ng * (9 + ns) + 8 * ng + 4 * nxy * (1 + 3 * ns)
+            assert floor <= b <= floor + 64 * 1024 + 256 * 30
+    # monotone in the number of steps
+    assert lib.nh_serve_job_bytes(64, 64, 32, 300, 4) > lib.nh_serve_job_bytes(64, 64, 32, 100, 4)
+    assert lib.nh_serve_job_bytes(64, 64, 32, 0, 4) == 0
+
+
+def test_stream_fits_budget(lib):
+    # every job of the serving stream fits the 200 GB budget on its own,
+    # and the workgroup limit (not memory) bounds the concurrency
+    jobs = wl.serving_stream(n_jobs=40)
+    sizes = []
+    for j in jobs:
+        w = j.workload
+        t = lib.nh_serve_job_team(w.nx, w.ny, w.nz, 256)
+        sizes.append((lib.nh_serve_job_bytes(w.nx, w.ny, w.nz, w.nsteps, t), t))
+    assert max(b for b, _ in sizes) < 200e9
+    n = admit(lib, [b for b, _ in sizes], [t for _, t in sizes], 0, 0, 200e9, 256)
+    assert 1 <= n < len(jobs)
+    assert sum(t for _, t in sizes[:n]) <= 256 < sum(t for _, t in sizes[:n + 1])
