@@ -179,13 +179,15 @@ nh_status nh_copy_f32(const float *src, float *dst, size_t n, void *hip_stream);
  *
  * The server keeps every admitted job's state in device memory and advances
  * all admitted jobs together: each nh_server_tick() makes one cooperative
- * launch in which each job performs one implicit-Euler step (forward, or
- * adjoint once its forward is done) with its own team of workgroups and its
- * own reductions. Before the launch the tick admits queued jobs in arrival
- * order while the job's device bytes fit the HBM budget and its workgroups
- * fit the co-resident limit; after it, finished jobs are retired and their
- * memory freed. A job's team and tiling depend only on its own grid, so its
- * result is bit-identical alone and among other jobs.
+ * launch in which each job's own team of workgroups runs implicit-Euler
+ * steps (forward, or adjoint once its forward is done) with its own
+ * reductions, until its CG iterations in the launch reach the slice budget
+ * (nh_server_set_slice) or its sweep ends. Before the launch the tick admits
+ * queued jobs in arrival order while the job's device bytes fit the HBM
+ * budget and its workgroups fit the co-resident limit; after it, finished
+ * jobs are retired and their memory freed. A job's team and tiling depend
+ * only on its own grid and slices end between steps, so its result is
+ * bit-identical alone and among other jobs.
  *
  * Inputs of nh_server_submit are HOST arrays, copied at submission; results
  * come back to HOST memory. One server is driven from one host thread.
@@ -225,6 +227,9 @@ typedef struct {
     long long jobs_done;
     double voxel_steps;     /* sum over finished jobs of 2 * voxels * nsteps (forward + adjoint) */
     long long cg_iters;     /* CG iterations of finished jobs */
+    double busy_block_s;    /* sum over launches and jobs of workgroups * the job's time in the launch */
+    double span_block_s;    /* sum over launches of max_blocks * the launch's span; busy / span is the
+                               fraction of the chip's workgroup slots that did work */
 } nh_server_stats;
 
 /* Create a server on `hip_device` working on `hip_stream` (NULL = the null
@@ -233,15 +238,25 @@ typedef struct {
 nh_status nh_server_create(nh_server **out, int hip_device, void *hip_stream, double hbm_budget_bytes,
                            int max_blocks);
 
+/* Slice budget of a tick: about `iters` CG iterations of a workgroup that
+ * holds 32768 voxels (smaller tiles run proportionally more; default 128).
+ * Each job runs at least one step per tick. */
+nh_status nh_server_set_slice(nh_server *s, int iters);
+
+/* Backfilling: a queued job that does not fit holds back the jobs behind it
+ * only after it has waited `ticks` ticks; until then smaller jobs behind it
+ * that fit are admitted first (default 16; 0 = strict arrival order). */
+nh_status nh_server_set_backfill(nh_server *s, int ticks);
+
 /* Queue a job. HOST inputs: alpha [nz][ny][nx] (finite, > 0), q_xy [ny][nx],
  * q_t [nsteps] (FP64), target [nsteps][ny][nx]; uniform spacing h; CG to
- * rtol with at most max_iter iterations per solve. Writes the job id.
+ * rtol with at most max_iter (<= 30000) iterations per solve. Writes the job id.
  * NH_ENOMEM if the job alone exceeds the budget. */
 nh_status nh_server_submit(nh_server *s, int nx, int ny, int nz, double h, double dt, int nsteps, double rtol,
                            int max_iter, const float *alpha, const float *q_xy, const double *q_t,
                            const float *target, long long *job_id);
 
-/* Admit what fits, advance every admitted job by one step (one launch),
+/* Admit what fits, advance every admitted job by one slice (one launch),
  * retire finished jobs. Writes up to finished_cap ids of jobs that finished
  * in this tick to HOST finished_ids (may be NULL if finished_cap is 0) and
  * the counts; a tick with nothing admitted does nothing. Blocks until the
@@ -273,11 +288,16 @@ int nh_serve_job_team(int nx, int ny, int nz, int max_blocks);
 /* Device bytes a job holds while admitted (0 on bad arguments). */
 size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks);
 
-/* Number of queued jobs, taken from the head of the queue in order, that the
- * next tick admits: the longest prefix whose bytes and workgroups, added to
- * those already in use, stay within the budget and the workgroup limit. */
-int nh_serve_admit_count(const size_t *bytes, const int *teams, int n_queued, size_t used_bytes, int used_blocks,
-                         double budget_bytes, int max_blocks);
+/* The jobs the next tick admits, as indices into the queue (arrival order),
+ * written to selected[] (room for n_queued); returns their number. Walking
+ * the queue in order, a job is admitted when its bytes and workgroups, added
+ * to those in use and to those admitted before it, stay within the budget
+ * and the workgroup limit. A job that does not fit and has waited
+ * (waited[i] ticks) at least reserve_after ticks ends the walk: nothing
+ * behind it is admitted ahead of it. reserve_after = 0 is strict arrival
+ * order. */
+int nh_serve_admit_select(const size_t *bytes, const int *teams, const int *waited, int n_queued, size_t used_bytes,
+                          int used_blocks, double budget_bytes, int max_blocks, int reserve_after, int *selected);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,8 @@ EXPORTED = ["nh_create", "nh_set_grid", "nh_set_solver", "nh_forward", "nh_adjoi
             "nh_set_cg_variant", "nh_set_barrier_timeout", "nh_get_stats", "nh_last_error", "nh_destroy", "nh_copy_f32",
             "nh_server_create", "nh_server_submit", "nh_server_tick", "nh_server_job", "nh_server_release",
             "nh_server_get_stats", "nh_server_last_error", "nh_server_destroy", "nh_serve_job_team",
-            "nh_serve_job_bytes", "nh_serve_admit_count"]
+            "nh_serve_job_bytes", "nh_serve_admit_select", "nh_server_set_slice",
+            "nh_server_set_backfill"]
 
 NH_JOB_QUEUED, NH_JOB_FORWARD, NH_JOB_ADJOINT, NH_JOB_DONE, NH_JOB_FAILED = range(5)
 JOB_STATE_NAMES = {0: "queued", 1: "forward", 2: "adjoint", 3: "done", 4: "failed"}
@@ -99,6 +100,8 @@ class nh_server_stats(ctypes.Structure):
         ("jobs_done", ctypes.c_longlong),
         ("voxel_steps", ctypes.c_double),
         ("cg_iters", ctypes.c_longlong),
+        ("busy_block_s", ctypes.c_double),
+        ("span_block_s", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -149,6 +152,7 @@ def load():
     lib.nh_server_tick.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), llp, ip, ctypes.POINTER(ip)]
     lib.nh_server_job.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(nh_job_info), vp]
     lib.nh_server_release.argtypes = [vp, ctypes.c_longlong]
+    lib.nh_server_set_slice.argtypes = [vp, ip]
     lib.nh_server_get_stats.argtypes = [vp, ctypes.POINTER(nh_server_stats)]
     lib.nh_server_last_error.argtypes = [vp]
     lib.nh_server_last_error.restype = ctypes.c_char_p
@@ -158,13 +162,15 @@ def load():
     lib.nh_serve_job_team.restype = ip
     lib.nh_serve_job_bytes.argtypes = [ip, ip, ip, ip, ip]
     lib.nh_serve_job_bytes.restype = ctypes.c_size_t
-    lib.nh_serve_admit_count.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ip), ip,
-                                         ctypes.c_size_t, ip, dp, ip]
-    lib.nh_serve_admit_count.restype = ip
+    lib.nh_serve_admit_select.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ip),
+                                          ctypes.POINTER(ip), ip, ctypes.c_size_t, ip, dp, ip, ip,
+                                          ctypes.POINTER(ip)]
+    lib.nh_serve_admit_select.restype = ip
+    lib.nh_server_set_backfill.argtypes = [vp, ip]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name not in ("nh_last_error", "nh_destroy", "nh_server_last_error", "nh_server_destroy",
-                        "nh_serve_job_team", "nh_serve_job_bytes", "nh_serve_admit_count"):
+                        "nh_serve_job_team", "nh_serve_job_bytes", "nh_serve_admit_select"):
             f.restype = st
     _lib = lib
     return lib

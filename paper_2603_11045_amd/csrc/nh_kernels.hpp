@@ -712,10 +712,54 @@ __device__ __forceinline__ void top_cells(const Geom& g, int rank, int team, int
 // ---------------------------------------------------------------------------
 // one implicit-Euler step (forward or adjoint) for one team
 
+// What every workgroup of the team knows after a step: the iteration count
+// and the flags that follow from reduced values are the same on all of them;
+// kTimeout is set only where a wait of this workgroup timed out.
+struct StepResult {
+  int iters;
+  int status;
+  double relres;                            // ||r|| / ||b|| at exit (0 when b = 0)
+};
+
+// The fields of a step that change from step to step; run_step takes them
+// apart from the rest of StepArgs so that a caller looping over steps keeps
+// only these live (the rest can be re-read from memory that does not change).
 template <typename R>
-__device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
+struct StepVar {
+  R* x;
+  const R* xprev;
+  const R* top_src;
+  R top_scale;
+  R* surf_out;
+  R* ckpt_out;
+  const R* T_grad;
+  int* out_iters;
+  double* out_relres;
+  int* out_status;
+  unsigned long long epoch_base;
+};
+
+template <typename R>
+__device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
+  StepVar<R> V;
+  V.x = S.x;
+  V.xprev = S.xprev;
+  V.top_src = S.top_src;
+  V.top_scale = S.top_scale;
+  V.surf_out = S.surf_out;
+  V.ckpt_out = S.ckpt_out;
+  V.T_grad = S.T_grad;
+  V.out_iters = S.out_iters;
+  V.out_relres = S.out_relres;
+  V.out_status = S.out_status;
+  V.epoch_base = S.epoch_base;
+  return V;
+}
+
+template <typename R>
+__device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int rank, Smem<R>& sh) {
   const Geom& g = S.g;
-  unsigned long long red = S.epoch_base;
+  unsigned long long red = V.epoch_base;
   bool ok = true;
   int ntr = 0;
   // trace_rank >= 0: that workgroup stamps into trace[0..cap); -1: every
@@ -732,15 +776,15 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
   init.alpha = S.alpha;
   init.sx = S.sx; init.sy = S.sy; init.sz = S.sz;
   init.z = S.z;
-  init.top = S.top_src;
-  init.top_scale = S.top_scale;
+  init.top = V.top_src;
+  init.top_scale = V.top_scale;
   init.nxy = g.nxy;
   init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
   if (S.mode == kForward) {
-    init.src = S.xprev;
-    init.xw = (S.xprev == S.x) ? nullptr : S.x;
+    init.src = V.xprev;
+    init.xw = (V.xprev == V.x) ? nullptr : V.x;
   } else {
-    init.src = S.x;
+    init.src = V.x;
     init.xw = nullptr;
   }
   sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
@@ -754,7 +798,7 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
   int it = 0, status = kOk;
   if (ok && bb == 0.0) {
     // b = 0: the solution is x = 0
-    own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) { S.x[i] = R(0); });
+    own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) { V.x[i] = R(0); });
     double v0[1] = {0.0};
     ok &= team_sum<R, 1>(S, rank, red, v0, sh);
     rr = 0.0;
@@ -779,7 +823,7 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
       const double alpha_cg = rz / v1[0];
 
       UpdOp<R> B;
-      B.alpha = S.alpha; B.p = pn; B.x = S.x; B.z = S.z;
+      B.alpha = S.alpha; B.p = pn; B.x = V.x; B.z = S.z;
       B.a = (R)alpha_cg;
       B.sx = S.sx; B.sy = S.sy; B.sz = S.sz;
       B.acc[0] = B.acc[1] = 0.0;
@@ -816,7 +860,7 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
       FusedOp<R> F;
       F.alpha = S.alpha;
       F.u = ub[cur]; F.wh = wb[cur]; F.sho = sb[cur];
-      F.x = S.x; F.p = S.p0;
+      F.x = V.x; F.p = S.p0;
       F.un = ub[cur ^ 1]; F.whn = wb[cur ^ 1]; F.shn = sb[cur ^ 1];
       F.a = (R)a_cg; F.b = (R)b_cg;
       F.first = (it == 0);
@@ -842,33 +886,35 @@ __device__ void run_step(const StepArgs<R>& S, int rank, Smem<R>& sh) {
 
   // epilogue
   if (S.mode == kForward) {
-    if (S.ckpt_out) {
+    if (V.ckpt_out) {
       own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long col, int kz) {
-        const R v = S.x[i];
-        if (kz == 0 && S.surf_out) S.surf_out[col] = v;
-        S.ckpt_out[i] = v;
+        const R v = V.x[i];
+        if (kz == 0 && V.surf_out) V.surf_out[col] = v;
+        V.ckpt_out[i] = v;
       });
-    } else if (S.surf_out) {
-      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { S.surf_out[col] = S.x[col]; });
+    } else if (V.surf_out) {
+      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.x[col]; });
     }
-  } else if (S.T_grad && ok) {
+  } else if (V.T_grad && ok) {
     GradOp<R> Gop;
-    Gop.alpha = S.alpha; Gop.mu = S.x; Gop.T = S.T_grad; Gop.G = S.G;
+    Gop.alpha = S.alpha; Gop.mu = V.x; Gop.T = V.T_grad; Gop.G = S.G;
     Gop.sx = S.sx; Gop.sy = S.sy; Gop.sz = S.sz;
     sweep<R>(g, rank, S.team, S.xcd_order, Gop, sh);
   }
 
-  if (rank == 0 && threadIdx.x == 0) {
-    S.out_iters[0] = it;
-    S.out_relres[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    S.out_status[0] = status;
+  const double relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  if (V.out_iters && rank == 0 && threadIdx.x == 0) {
+    V.out_iters[0] = it;
+    V.out_relres[0] = relres;
+    V.out_status[0] = status;
   }
+  return StepResult{it, status, relres};
 }
 
 template <typename R>
 __global__ void __launch_bounds__(Cfg<R>::kBlock, 1) step_kernel(StepArgs<R> S) {
   __shared__ Smem<R> sh;
-  run_step<R>(S, blockIdx.x, sh);
+  run_step<R>(S, step_var(S), blockIdx.x, sh);
 }
 
 template <typename R>

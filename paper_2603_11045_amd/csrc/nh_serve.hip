@@ -3,15 +3,17 @@
 // A job is one reconstruction request: a diffusivity field, a source, and the
 // surface measurements it is compared with (mean squared error). The server
 // keeps every admitted job's state resident in HBM and advances all of them
-// together: each tick is ONE cooperative launch of nh::batch_step_kernel in
-// which every active job performs one implicit-Euler step (forward, or
-// adjoint after its forward has finished) with its own team of workgroups and
-// its own team reductions (the same step code as the single-problem path).
-// Between ticks the host retires finished jobs, frees their memory and admits
-// queued jobs in arrival order while both the HBM budget and the co-resident
-// workgroup budget allow -- so requests that arrive while others run join at
-// the next step boundary. A job's team size and tiling depend only on the job
-// itself, so its result is bit-identical whether it runs alone or among others.
+// together: each tick is ONE cooperative launch of nh::batch_run_kernel in
+// which every active job's team of workgroups runs implicit-Euler steps
+// (forward, or adjoint after its forward has finished) with its own team
+// reductions -- the same step code as the single-problem path -- until its
+// CG iterations in this launch reach the tick's budget. Between ticks the host
+// reads one progress record per job, retires finished jobs, frees their
+// memory and admits queued jobs in arrival order while both the HBM budget
+// and the co-resident workgroup budget allow -- so requests that arrive while
+// others run join at the next tick. A job's team size and tiling depend only
+// on the job itself and slices end only between steps, so its result is
+// bit-identical whether it runs alone or among others.
 #include "nefty_heat.h"
 #include "nh_kernels.hpp"
 
@@ -21,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -30,13 +33,101 @@
 
 namespace nh {
 
-// Workgroup b works as rank map[b].y of job map[b].x.
-template <typename R>
-__global__ void __launch_bounds__(Cfg<R>::kBlock, 1) batch_step_kernel(const StepArgs<R>* jobs, const int2* map) {
-  __shared__ Smem<R> sh;
+// One job's slice of work in a launch. `S` holds the job's buffers and
+// constants; the per-step fields are set in the kernel.
+struct JobRun {
+  StepArgs<float> S;
+  const float* qscale;        // forward: top-plane source scale of step n at [n-1]
+  float* traj;                // T^n at (n-1) * ng
+  float* surf;                // S^n at (n-1) * nxy
+  const float* gsurf;         // dL/dS^n at (n-1) * nxy
+  int* it_out;                // per-step iterations [2][nsteps]: forward, then adjoint
+  double* rel_out;            // per-step relative residuals, same layout
+  int* st_out;                // per-step status flags, same layout
+  int mode;                   // kForward or kAdjoint
+  int n0;                     // first step of the slice (the adjoint counts down to 1)
+  int nsteps;
+  long long cost;             // cost of one iteration of one workgroup (voxel units)
+  long long budget;           // the slice ends once (iterations + steps) * cost would pass this
+};
+
+// Per-job progress of a launch, written by the job's rank 0.
+struct JobProg {
+  int steps;
+  int status;
+  long long iters;
+  long long t0, t1;           // wall clock of rank 0 at the start and end of the slice
+};
+
+constexpr int kMaxSliceSteps = 255;       // steps per slice: epoch bits 16..23 of a launch
+
+// Workgroup b works as rank map[b].y of job map[b].x. The step loop and its
+// exit test depend only on reduced values, so every workgroup of a team runs
+// the same steps (a barrier timeout aside, which every member then reaches
+// within its own bounded waits).
+__global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const JobRun* jobs, const int2* map,
+                                                                          JobProg* prog) {
+  __shared__ Smem<float> sh;
   const int2 m = map[blockIdx.x];
-  const StepArgs<R> S = jobs[m.x];
-  run_step<R>(S, m.y, sh);
+  if (m.x < 0) return;
+  // The job table is not written during the launch: reading it through the
+  // constant address space makes its loads scalar and invariant, so the
+  // compiler reloads fields instead of keeping the whole table live.
+  typedef __attribute__((address_space(4))) const JobRun CJobRun;
+  const CJobRun& J = *(const CJobRun*)(jobs + m.x);
+  const long long t0 = wall_clock64();
+  const bool fwd = J.mode == kForward;
+  int n = J.n0, steps = 0, status = 0;
+  long long iters = 0;
+  const StepArgs<float>& S = (const StepArgs<float>&)J.S;
+  const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
+  while (true) {
+    StepVar<float> V;
+    V.epoch_base = J.S.epoch_base + ((unsigned long long)steps << 16);
+    V.out_iters = nullptr;                  // per-step outputs are written below
+    V.out_relres = nullptr;
+    V.out_status = nullptr;
+    V.ckpt_out = nullptr;
+    if (fwd) {
+      V.x = J.traj + (long long)(n - 1) * ng;
+      V.xprev = n == 1 ? nullptr : J.traj + (long long)(n - 2) * ng;
+      V.top_src = J.S.top_src;
+      V.top_scale = J.qscale[n - 1];
+      V.surf_out = J.surf + (long long)(n - 1) * nxy;
+      V.T_grad = nullptr;
+    } else {
+      V.x = J.S.x;
+      V.xprev = nullptr;
+      V.top_src = J.gsurf + (long long)(n - 1) * nxy;
+      V.top_scale = 1.f;
+      V.surf_out = nullptr;
+      V.T_grad = J.traj + (long long)(n - 1) * ng;
+    }
+    const StepResult r = run_step<float>(S, V, m.y, sh);
+    if (m.y == 0 && threadIdx.x == 0) {
+      const int slot = (fwd ? 0 : J.nsteps) + n - 1;
+      J.it_out[slot] = r.iters;
+      J.rel_out[slot] = r.relres;
+      J.st_out[slot] = r.status;
+    }
+    iters += r.iters;
+    status |= r.status;
+    ++steps;
+    const bool last = fwd ? n == J.nsteps : n == 1;
+    n += fwd ? 1 : -1;
+    if (last || (status & (kNonFinite | kTimeout)) || steps >= kMaxSliceSteps) break;
+    // the next step is expected to take about as many iterations as this one
+    if ((iters + steps + r.iters + 1) * J.cost > J.budget) break;
+  }
+  if (m.y == 0 && threadIdx.x == 0) {
+    JobProg p;
+    p.steps = steps;
+    p.status = status;
+    p.iters = iters;
+    p.t0 = t0;
+    p.t1 = wall_clock64();
+    prog[m.x] = p;
+  }
 }
 
 constexpr int kMseThreads = 256;
@@ -73,6 +164,8 @@ namespace {
 
 constexpr int kMseBlocks = 64;
 constexpr long long kVoxelsPerBlock = 32768;
+constexpr long long kReductionCost = 8192;   // a team reduction, in voxel units of work
+constexpr int kMaxIterLimit = 30000;          // reductions per step stay below 2^16
 constexpr int kBlock = nh::Cfg<float>::kBlock;
 
 double now_s() {
@@ -113,8 +206,10 @@ size_t job_bytes(int nx, int ny, int nz, int nsteps, int team) {
   b += align256(4 * ng * N);                                // trajectory T^1..T^N
   b += align256(8 * ng);                                    // dL/dalpha (FP64)
   b += align256(4 * nxy) + 3 * align256(4 * nxy * N);       // q_xy, target, S, dL/dS
+  b += align256(4 * N);                                     // source scale per step
+  b += 2 * align256(4 * 2 * N) + align256(8 * 2 * N);       // per-step iterations, status, residuals
   b += align256(sizeof(nh::Slot) * ((size_t)team + 1));     // team reduction slots
-  b += align256(8 * kMseBlocks) + 4 * 256;                  // MSE partials, loss, step outputs
+  b += align256(8 * kMseBlocks) + 256;                      // MSE partials, loss
   return b;
 }
 
@@ -123,19 +218,20 @@ struct SJob {
   int state = NH_JOB_QUEUED;
   int nx = 0, ny = 0, nz = 0, nsteps = 0, max_iter = 0;
   double h = 1, dt = 1, rtol = 1e-6;
-  std::vector<float> h_alpha, h_qxy, h_target;
-  std::vector<double> h_qt;
+  std::vector<float> h_alpha, h_qxy, h_target, h_qscale;
   nh::Geom g{};
   int team = 1;
+  long long cost = 0;
   size_t bytes = 0;
   void* mem = nullptr;
   float *alpha = nullptr, *qxy = nullptr, *target = nullptr, *traj = nullptr, *z = nullptr, *p0 = nullptr,
         *u1 = nullptr, *w0 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr, *mu = nullptr,
-        *surf = nullptr, *gsurf = nullptr;
+        *surf = nullptr, *gsurf = nullptr, *qscale = nullptr;
   double *G = nullptr, *partial = nullptr, *lossbuf = nullptr, *rel_out = nullptr;
   void* slots = nullptr;
   int *it_out = nullptr, *st_out = nullptr;
-  int step = 0;            // the step being computed (the adjoint counts down from N)
+  int step = 0;            // the next step to compute (the adjoint counts down from N)
+  int waited = 0;          // ticks spent in the queue
   long long fwd_iters = 0, adj_iters = 0;
   int status = 0;
   double loss = 0;
@@ -150,20 +246,26 @@ struct nh_server {
   hipStream_t stream = nullptr;
   int num_cu = 0, max_blocks = 0;
   double budget = 0;
+  int slice_iters = 128;
+  int backfill_ticks = 16;
   size_t used_bytes = 0;
   int used_blocks = 0;
   long long next_id = 1;
   unsigned long long launch_ctr = 0;
   long long wallclock_khz = 100000;
   double barrier_timeout_s = 20.0;
+  int trace = 0;          // NH_SERVE_TRACE=1: a line per launch; 2: also a line per job
   std::deque<SJob*> queue;
   std::vector<SJob*> active;
   std::map<long long, std::unique_ptr<SJob>> jobs;
-  std::vector<nh::StepArgs<float>> h_args;
-  std::vector<int2> h_map;
-  nh::StepArgs<float>* d_args = nullptr;
+  // pinned host staging and device copies of the launch tables
+  nh::JobRun* h_runs = nullptr;
+  nh::JobProg* h_prog = nullptr;
+  int2* h_map = nullptr;
+  nh::JobRun* d_runs = nullptr;
+  nh::JobProg* d_prog = nullptr;
   int2* d_map = nullptr;
-  size_t cap_args = 0, cap_map = 0;
+  size_t cap_jobs = 0;
   int* d_flag = nullptr;
   std::string err;
   nh_server_stats st{};
@@ -212,16 +314,18 @@ nh_status admit(nh_server* s, SJob* j) {
   j->target = (float*)take(4 * nxy * N);
   j->surf = (float*)take(4 * nxy * N);
   j->gsurf = (float*)take(4 * nxy * N);
+  j->qscale = (float*)take(4 * N);
+  j->it_out = (int*)take(4 * 2 * N);
+  j->st_out = (int*)take(4 * 2 * N);
+  j->rel_out = (double*)take(8 * 2 * N);
   j->slots = take(sizeof(nh::Slot) * ((size_t)j->team + 1));
   j->partial = (double*)take(8 * kMseBlocks);
   j->lossbuf = (double*)take(256);
-  j->it_out = (int*)take(256);
-  j->rel_out = (double*)take(256);
-  j->st_out = (int*)take(256);
   if ((size_t)(p - (char*)j->mem) > j->bytes) return sfail(s, NH_EINVAL, "internal: job layout exceeds its size");
   SV_HIP(s, hipMemcpyAsync(j->alpha, j->h_alpha.data(), 4 * ng, hipMemcpyHostToDevice, s->stream));
   SV_HIP(s, hipMemcpyAsync(j->qxy, j->h_qxy.data(), 4 * nxy, hipMemcpyHostToDevice, s->stream));
   SV_HIP(s, hipMemcpyAsync(j->target, j->h_target.data(), 4 * nxy * N, hipMemcpyHostToDevice, s->stream));
+  SV_HIP(s, hipMemcpyAsync(j->qscale, j->h_qscale.data(), 4 * N, hipMemcpyHostToDevice, s->stream));
   SV_HIP(s, hipMemsetAsync(j->slots, 0, sizeof(nh::Slot) * ((size_t)j->team + 1), s->stream));
   const int blocks = (int)std::min<size_t>((ng + 255) / 256, 2048);
   hipLaunchKernelGGL(nh::fill_kernel<float>, dim3(blocks), dim3(256), 0, s->stream, j->mu, (long long)ng, 0.f);
@@ -242,10 +346,10 @@ void retire(nh_server* s, SJob* j) {
   s->used_blocks -= j->team;
 }
 
-// Arguments of job j's current step.
-nh::StepArgs<float> job_args(const nh_server* s, const SJob* j, unsigned long long epoch_base) {
-  nh::StepArgs<float> S;
-  std::memset(&S, 0, sizeof(S));
+// Job j's slice of the next launch.
+void job_run(const nh_server* s, const SJob* j, unsigned long long epoch_base, nh::JobRun& J) {
+  std::memset(&J, 0, sizeof(J));
+  nh::StepArgs<float>& S = J.S;
   S.g = j->g;
   const float sd = (float)(2.0 * j->dt / (j->h * j->h));
   S.sx = S.sy = S.sz = sd;
@@ -264,39 +368,45 @@ nh::StepArgs<float> job_args(const nh_server* s, const SJob* j, unsigned long lo
   S.max_iter = j->max_iter;
   S.team = j->team;
   S.xcd_order = 0;
-  S.out_iters = j->it_out;
-  S.out_relres = j->rel_out;
-  S.out_status = j->st_out;
   S.err_flag = s->d_flag;
   S.timeout_ticks = (long long)(s->barrier_timeout_s * (double)s->wallclock_khz * 1000.0);
-  const size_t ng = (size_t)j->g.ng, nxy = (size_t)j->g.nxy;
-  const int n = j->step;
   if (j->state == NH_JOB_FORWARD) {
     S.mode = nh::kForward;
-    S.x = j->traj + (size_t)(n - 1) * ng;
-    S.xprev = n == 1 ? nullptr : j->traj + (size_t)(n - 2) * ng;
     S.top_src = j->qxy;
-    S.top_scale = (float)(j->dt * j->h_qt[n - 1]);
-    S.surf_out = j->surf + (size_t)(n - 1) * nxy;
   } else {
     S.mode = nh::kAdjoint;
     S.x = j->mu;
-    S.top_src = j->gsurf + (size_t)(n - 1) * nxy;
     S.top_scale = 1.f;
-    S.T_grad = j->traj + (size_t)(n - 1) * ng;
     S.G = j->G;
   }
-  return S;
+  J.qscale = j->qscale;
+  J.traj = j->traj;
+  J.surf = j->surf;
+  J.gsurf = j->gsurf;
+  J.it_out = j->it_out;
+  J.rel_out = j->rel_out;
+  J.st_out = j->st_out;
+  J.mode = S.mode;
+  J.n0 = j->step;
+  J.nsteps = j->nsteps;
+  J.cost = j->cost;
+  J.budget = (long long)s->slice_iters * (kVoxelsPerBlock + kReductionCost);
 }
 
-template <typename T>
-nh_status grow(nh_server* s, T*& p, size_t& cap, size_t need) {
-  if (cap >= need) return NH_OK;
-  if (p) (void)hipFree(p);
-  p = nullptr;
-  cap = 0;
-  SV_HIP(s, hipMalloc(&p, sizeof(T) * need));
-  cap = need;
+nh_status ensure_tables(nh_server* s, size_t njobs) {
+  if (s->cap_jobs >= njobs) return NH_OK;
+  const size_t cap = std::max<size_t>(64, 2 * njobs);
+  if (s->h_runs) (void)hipHostFree(s->h_runs);
+  if (s->h_prog) (void)hipHostFree(s->h_prog);
+  if (s->d_runs) (void)hipFree(s->d_runs);
+  if (s->d_prog) (void)hipFree(s->d_prog);
+  s->h_runs = nullptr; s->h_prog = nullptr; s->d_runs = nullptr; s->d_prog = nullptr;
+  s->cap_jobs = 0;
+  SV_HIP(s, hipHostMalloc((void**)&s->h_runs, sizeof(nh::JobRun) * cap, hipHostMallocDefault));
+  SV_HIP(s, hipHostMalloc((void**)&s->h_prog, sizeof(nh::JobProg) * cap, hipHostMallocDefault));
+  SV_HIP(s, hipMalloc(&s->d_runs, sizeof(nh::JobRun) * cap));
+  SV_HIP(s, hipMalloc(&s->d_prog, sizeof(nh::JobProg) * cap));
+  s->cap_jobs = cap;
   return NH_OK;
 }
 
@@ -317,16 +427,20 @@ size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks) {
   return job_bytes(nx, ny, nz, nsteps, team_blocks);
 }
 
-int nh_serve_admit_count(const size_t* bytes, const int* teams, int n_queued, size_t used_bytes, int used_blocks,
-                         double budget_bytes, int max_blocks) {
-  if (!bytes || !teams || n_queued < 1) return 0;
+int nh_serve_admit_select(const size_t* bytes, const int* teams, const int* waited, int n_queued, size_t used_bytes,
+                          int used_blocks, double budget_bytes, int max_blocks, int reserve_after, int* selected) {
+  if (!bytes || !teams || !waited || !selected || n_queued < 1) return 0;
   int n = 0;
   double b = (double)used_bytes;
   long long w = used_blocks;
-  for (; n < n_queued; ++n) {
-    if (b + (double)bytes[n] > budget_bytes || w + teams[n] > max_blocks) break;
-    b += (double)bytes[n];
-    w += teams[n];
+  for (int i = 0; i < n_queued; ++i) {
+    if (b + (double)bytes[i] <= budget_bytes && w + teams[i] <= max_blocks) {
+      b += (double)bytes[i];
+      w += teams[i];
+      selected[n++] = i;
+    } else if (waited[i] >= reserve_after) {
+      break;  // this job holds a reservation: nothing behind it overtakes it
+    }
   }
   return n;
 }
@@ -346,7 +460,7 @@ nh_status nh_server_create(nh_server** out, int hip_device, void* hip_stream, do
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return NH_EHIP;
   s->num_cu = prop.multiProcessorCount;
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)nh::batch_step_kernel<float>, kBlock, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)nh::batch_run_kernel, kBlock, 0) !=
           hipSuccess ||
       occ < 1)
     return NH_EHIP;
@@ -356,14 +470,32 @@ nh_status nh_server_create(nh_server** out, int hip_device, void* hip_stream, do
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
     s->wallclock_khz = khz;
-  if (hipMalloc(&s->d_flag, 64) != hipSuccess) return NH_ENOMEM;
-  if (hipMemset(s->d_flag, 0, 64) != hipSuccess || hipEventCreate(&s->ev0) != hipSuccess ||
-      hipEventCreate(&s->ev1) != hipSuccess) {
-    (void)hipFree(s->d_flag);
+  bool ok = hipMalloc(&s->d_flag, 64) == hipSuccess && hipMemset(s->d_flag, 0, 64) == hipSuccess &&
+            hipMalloc(&s->d_map, sizeof(int2) * s->max_blocks) == hipSuccess &&
+            hipHostMalloc((void**)&s->h_map, sizeof(int2) * s->max_blocks, hipHostMallocDefault) == hipSuccess &&
+            hipEventCreate(&s->ev0) == hipSuccess && hipEventCreate(&s->ev1) == hipSuccess;
+  s->st.max_blocks = s->max_blocks;
+  if (const char* t = std::getenv("NH_SERVE_TRACE")) s->trace = std::atoi(t);
+  nh_server* raw = s.release();
+  if (!ok || ensure_tables(raw, 64) != NH_OK) {
+    nh_server_destroy(raw);
     return NH_EHIP;
   }
-  s->st.max_blocks = s->max_blocks;
-  *out = s.release();
+  *out = raw;
+  return NH_OK;
+}
+
+nh_status nh_server_set_slice(nh_server* s, int iters) {
+  if (!s) return NH_EINVAL;
+  if (iters < 1) return sfail(s, NH_EINVAL, "slice must be >= 1 iteration");
+  s->slice_iters = iters;
+  return NH_OK;
+}
+
+nh_status nh_server_set_backfill(nh_server* s, int ticks) {
+  if (!s) return NH_EINVAL;
+  if (ticks < 0) return sfail(s, NH_EINVAL, "backfill window must be >= 0 ticks");
+  s->backfill_ticks = ticks;
   return NH_OK;
 }
 
@@ -373,7 +505,7 @@ nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, doubl
   if (!s) return NH_EINVAL;
   if (!job_id || !alpha || !q_xy || !q_t || !target) return sfail(s, NH_EINVAL, "null pointer argument");
   if (nx < 1 || ny < 1 || nz < 1 || nsteps < 1 || !(dt > 0) || !std::isfinite(dt) || !(h > 0) ||
-      !std::isfinite(h) || !(rtol > 0) || !(rtol < 1) || max_iter < 1)
+      !std::isfinite(h) || !(rtol > 0) || !(rtol < 1) || max_iter < 1 || max_iter > kMaxIterLimit)
     return sfail(s, NH_EINVAL, "bad job parameters");
   const size_t ng = (size_t)nx * ny * nz, nxy = (size_t)nx * ny, N = (size_t)nsteps;
   for (size_t i = 0; i < ng; ++i)
@@ -394,12 +526,14 @@ nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, doubl
   int team = 0;
   job_geom(nx, ny, nz, std::max(1, s->max_blocks / 2), j->g, team);
   j->team = team;
+  j->cost = ((long long)ng + team - 1) / team + (team > 1 ? kReductionCost : 0);
   j->bytes = job_bytes(nx, ny, nz, nsteps, team);
   if ((double)j->bytes > s->budget) return sfail(s, NH_ENOMEM, "job larger than the HBM budget");
   j->h_alpha.assign(alpha, alpha + ng);
   j->h_qxy.assign(q_xy, q_xy + nxy);
-  j->h_qt.assign(q_t, q_t + N);
   j->h_target.assign(target, target + nxy * N);
+  j->h_qscale.resize(N);
+  for (size_t n = 0; n < N; ++n) j->h_qscale[n] = (float)(dt * q_t[n]);   // as the single-problem path
   j->id = s->next_id++;
   j->t_submit = now_s();
   *job_id = j->id;
@@ -415,110 +549,147 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
   if (hipSetDevice(s->device) != hipSuccess) return sfail(s, NH_EHIP, "hipSetDevice failed");
   int finished = 0;
 
-  // admission, in arrival order
+  // admission: arrival order, with backfilling of later jobs that fit while
+  // the jobs ahead of them have waited fewer than backfill_ticks ticks
   {
     std::vector<size_t> qb;
-    std::vector<int> qt;
+    std::vector<int> qt, qw, sel(s->queue.size());
     for (const SJob* j : s->queue) {
       qb.push_back(j->bytes);
       qt.push_back(j->team);
+      qw.push_back(j->waited);
     }
-    const int na = nh_serve_admit_count(qb.data(), qt.data(), (int)qb.size(), s->used_bytes, s->used_blocks,
-                                        s->budget, s->max_blocks);
-    for (int k = 0; k < na; ++k) {
-      SJob* j = s->queue.front();
-      const nh_status st = admit(s, j);
-      if (st != NH_OK) return st;
-      s->queue.pop_front();
+    const int na = nh_serve_admit_select(qb.data(), qt.data(), qw.data(), (int)qb.size(), s->used_bytes,
+                                         s->used_blocks, s->budget, s->max_blocks, s->backfill_ticks, sel.data());
+    std::vector<SJob*> admitted;
+    nh_status st = NH_OK;
+    for (int k = 0; k < na && st == NH_OK; ++k) {
+      SJob* j = s->queue[sel[k]];
+      st = admit(s, j);
+      if (st != NH_OK) break;
+      admitted.push_back(j);
       s->active.push_back(j);
     }
+    std::deque<SJob*> rest;
+    for (SJob* j : s->queue)
+      if (j->state == NH_JOB_QUEUED) {
+        ++j->waited;
+        rest.push_back(j);
+      }
+    s->queue.swap(rest);
+    if (st != NH_OK) return st;
     if (na > 0) {
       // the host copies of the inputs may go once the uploads are done
       SV_HIP(s, hipStreamSynchronize(s->stream));
-      for (int k = 0; k < na; ++k) {
-        SJob* j = s->active[s->active.size() - na + k];
+      for (SJob* j : admitted) {
         std::vector<float>().swap(j->h_alpha);
         std::vector<float>().swap(j->h_target);
+        std::vector<float>().swap(j->h_qscale);
       }
     }
   }
 
   if (!s->active.empty()) {
+    const size_t na = s->active.size();
+    nh_status ts = ensure_tables(s, na);
+    if (ts != NH_OK) return ts;
     const unsigned long long base = (++s->launch_ctr) << 24;
-    s->h_args.clear();
-    s->h_map.clear();
-    for (size_t k = 0; k < s->active.size(); ++k) {
+    int nb = 0;
+    for (size_t k = 0; k < na; ++k) {
       const SJob* j = s->active[k];
-      s->h_args.push_back(job_args(s, j, base));
-      for (int r = 0; r < j->team; ++r) s->h_map.push_back(make_int2((int)k, r));
+      if (nb + j->team > s->max_blocks) return sfail(s, NH_EINVAL, "internal: workgroups exceed the limit");
+      job_run(s, j, base, s->h_runs[k]);
+      for (int r = 0; r < j->team; ++r) s->h_map[nb++] = make_int2((int)k, r);
     }
-    if ((int)s->h_map.size() > s->max_blocks) return sfail(s, NH_EINVAL, "internal: workgroups exceed the limit");
-    nh_status gs = grow(s, s->d_args, s->cap_args, std::max<size_t>(s->h_args.size(), 64));
-    if (gs != NH_OK) return gs;
-    gs = grow(s, s->d_map, s->cap_map, (size_t)s->max_blocks);
-    if (gs != NH_OK) return gs;
-    SV_HIP(s, hipMemcpyAsync(s->d_args, s->h_args.data(), sizeof(nh::StepArgs<float>) * s->h_args.size(),
-                             hipMemcpyHostToDevice, s->stream));
-    SV_HIP(s, hipMemcpyAsync(s->d_map, s->h_map.data(), sizeof(int2) * s->h_map.size(), hipMemcpyHostToDevice,
-                             s->stream));
-    void* args[] = {(void*)&s->d_args, (void*)&s->d_map};
+    SV_HIP(s, hipMemcpyAsync(s->d_runs, s->h_runs, sizeof(nh::JobRun) * na, hipMemcpyHostToDevice, s->stream));
+    SV_HIP(s, hipMemcpyAsync(s->d_map, s->h_map, sizeof(int2) * nb, hipMemcpyHostToDevice, s->stream));
+    void* args[] = {(void*)&s->d_runs, (void*)&s->d_map, (void*)&s->d_prog};
     SV_HIP(s, hipEventRecord(s->ev0, s->stream));
-    SV_HIP(s, hipLaunchCooperativeKernel((const void*)nh::batch_step_kernel<float>, dim3((unsigned)s->h_map.size()),
-                                         dim3(kBlock), args, 0, s->stream));
+    SV_HIP(s, hipLaunchCooperativeKernel((const void*)nh::batch_run_kernel, dim3((unsigned)nb), dim3(kBlock), args,
+                                         0, s->stream));
     SV_HIP(s, hipEventRecord(s->ev1, s->stream));
-    // after a job's last forward step: loss and dL/dS of the mean squared error
-    for (const SJob* j : s->active) {
-      if (j->state == NH_JOB_FORWARD && j->step == j->nsteps) {
-        const long long m = j->g.nxy * (long long)j->nsteps;
-        hipLaunchKernelGGL(nh::mse_grad_kernel, dim3(kMseBlocks), dim3(nh::kMseThreads), 0, s->stream, j->surf,
-                           j->target, j->gsurf, m, 2.0 / (double)m, j->partial);
-        hipLaunchKernelGGL(nh::mse_finish_kernel, dim3(1), dim3(64), 0, s->stream, j->partial, kMseBlocks,
-                           1.0 / (double)m, j->lossbuf);
-        SV_HIP(s, hipGetLastError());
-      }
-    }
-    std::vector<int> its(s->active.size()), sts(s->active.size());
-    for (size_t k = 0; k < s->active.size(); ++k) {
-      SV_HIP(s, hipMemcpyAsync(&its[k], s->active[k]->it_out, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-      SV_HIP(s, hipMemcpyAsync(&sts[k], s->active[k]->st_out, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    }
+    SV_HIP(s, hipMemcpyAsync(s->h_prog, s->d_prog, sizeof(nh::JobProg) * na, hipMemcpyDeviceToHost, s->stream));
     SV_HIP(s, hipStreamSynchronize(s->stream));
     float ms = 0.f;
     SV_HIP(s, hipEventElapsedTime(&ms, s->ev0, s->ev1));
     s->st.kernel_s += 1e-3 * ms;
     ++s->st.ticks;
 
+    // busy time of each team against the launch's span (load balance)
+    {
+      long long lo = s->h_prog[0].t0, hi = s->h_prog[0].t1;
+      double busy = 0.0;
+      for (size_t k = 0; k < na; ++k) {
+        lo = std::min(lo, s->h_prog[k].t0);
+        hi = std::max(hi, s->h_prog[k].t1);
+        busy += (double)s->active[k]->team * (double)(s->h_prog[k].t1 - s->h_prog[k].t0);
+      }
+      const double tick_s = 1.0 / ((double)s->wallclock_khz * 1000.0);
+      s->st.busy_block_s += busy * tick_s;
+      s->st.span_block_s += (double)s->max_blocks * (double)(hi - lo) * tick_s;
+      if (s->trace > 1)
+        for (size_t k = 0; k < na; ++k) {
+          const SJob* j = s->active[k];
+          const nh::JobProg& q = s->h_prog[k];
+          std::fprintf(stderr, "[nh_server]   job %lld %dx%dx%d team %d %s steps %d iters %lld busy %.3f ms\n", j->id,
+                       j->nx, j->ny, j->nz, j->team, j->state == NH_JOB_FORWARD ? "fwd" : "adj", q.steps, q.iters,
+                       (double)(q.t1 - q.t0) * tick_s * 1e3);
+        }
+      if (s->trace)
+        std::fprintf(stderr, "[nh_server] tick %lld: %zu jobs, %d workgroups, launch %.3f ms, span %.3f ms, busy %.1f%%\n",
+                     s->st.ticks, na, nb, (double)ms, (double)(hi - lo) * tick_s * 1e3,
+                     100.0 * busy / ((double)s->max_blocks * (double)std::max(1LL, hi - lo)));
+    }
     std::vector<SJob*> still;
-    still.reserve(s->active.size());
-    for (size_t k = 0; k < s->active.size(); ++k) {
+    still.reserve(na);
+    for (size_t k = 0; k < na; ++k) {
       SJob* j = s->active[k];
-      j->status |= sts[k];
+      const nh::JobProg pr = s->h_prog[k];
+      j->status |= pr.status;
+      const bool failed = (pr.status & (nh::kNonFinite | nh::kTimeout)) != 0;
       if (j->state == NH_JOB_FORWARD) {
-        j->fwd_iters += its[k];
-        if (j->step == j->nsteps)
-          j->state = NH_JOB_ADJOINT;  // the adjoint starts at step N
-        else
-          ++j->step;
-        still.push_back(j);
-        continue;
+        j->fwd_iters += pr.iters;
+        j->step += pr.steps;
+        if (j->step > j->nsteps && !failed) {
+          // forward done: loss and dL/dS of the mean squared error, ahead of
+          // the next launch on the same stream; the adjoint starts at step N
+          const long long m = j->g.nxy * (long long)j->nsteps;
+          hipLaunchKernelGGL(nh::mse_grad_kernel, dim3(kMseBlocks), dim3(nh::kMseThreads), 0, s->stream, j->surf,
+                             j->target, j->gsurf, m, 2.0 / (double)m, j->partial);
+          hipLaunchKernelGGL(nh::mse_finish_kernel, dim3(1), dim3(64), 0, s->stream, j->partial, kMseBlocks,
+                             1.0 / (double)m, j->lossbuf);
+          SV_HIP(s, hipGetLastError());
+          j->state = NH_JOB_ADJOINT;
+          j->step = j->nsteps;
+        }
+        if (!failed) {
+          still.push_back(j);
+          continue;
+        }
+      } else {
+        j->adj_iters += pr.iters;
+        j->step -= pr.steps;
+        if (j->step >= 1 && !failed) {
+          still.push_back(j);
+          continue;
+        }
       }
-      j->adj_iters += its[k];
-      if (j->step > 1) {
-        --j->step;
-        still.push_back(j);
-        continue;
-      }
+      // finished (or failed): results to the host, memory back to the pool
       const size_t ng = (size_t)j->g.ng;
-      j->h_G.resize(ng);
-      SV_HIP(s, hipMemcpyAsync(j->h_G.data(), j->G, 8 * ng, hipMemcpyDeviceToHost, s->stream));
-      SV_HIP(s, hipMemcpyAsync(&j->loss, j->lossbuf, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      if (!failed) {
+        j->h_G.resize(ng);
+        SV_HIP(s, hipMemcpyAsync(j->h_G.data(), j->G, 8 * ng, hipMemcpyDeviceToHost, s->stream));
+        SV_HIP(s, hipMemcpyAsync(&j->loss, j->lossbuf, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      }
       SV_HIP(s, hipStreamSynchronize(s->stream));
-      j->state = (j->status & (nh::kNonFinite | nh::kTimeout)) ? NH_JOB_FAILED : NH_JOB_DONE;
+      j->state = failed ? NH_JOB_FAILED : NH_JOB_DONE;
       j->t_done = now_s();
       retire(s, j);
-      s->st.jobs_done += 1;
-      s->st.voxel_steps += 2.0 * (double)ng * j->nsteps;
-      s->st.cg_iters += j->fwd_iters + j->adj_iters;
+      if (!failed) {
+        s->st.jobs_done += 1;
+        s->st.voxel_steps += 2.0 * (double)ng * j->nsteps;
+        s->st.cg_iters += j->fwd_iters + j->adj_iters;
+      }
       if (finished < finished_cap) finished_ids[finished] = j->id;
       ++finished;
     }
@@ -580,7 +751,11 @@ void nh_server_destroy(nh_server* s) {
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
   for (SJob* j : s->active) retire(s, j);
-  if (s->d_args) (void)hipFree(s->d_args);
+  if (s->h_runs) (void)hipHostFree(s->h_runs);
+  if (s->h_prog) (void)hipHostFree(s->h_prog);
+  if (s->h_map) (void)hipHostFree(s->h_map);
+  if (s->d_runs) (void)hipFree(s->d_runs);
+  if (s->d_prog) (void)hipFree(s->d_prog);
   if (s->d_map) (void)hipFree(s->d_map);
   if (s->d_flag) (void)hipFree(s->d_flag);
   if (s->ev0) (void)hipEventDestroy(s->ev0);

@@ -41,12 +41,14 @@ class Server:
     """Continuous-batching server on one GPU.
 
     ``submit`` queues a job; each ``tick`` admits what fits (HBM budget and
-    co-resident workgroups, arrival order), advances every admitted job by
-    one implicit-Euler step in a single launch, and retires finished jobs.
+    co-resident workgroups, arrival order), advances every admitted job by a
+    slice of implicit-Euler steps in a single launch, and retires finished
+    jobs.
     """
 
     def __init__(self, hbm_budget_bytes: float = 200e9, max_blocks: int = 0,
-                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None):
+                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None,
+                 slice_iters: int = 0, backfill_ticks: Optional[int] = None):
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -56,6 +58,19 @@ class Server:
                                          int(max_blocks)), None, "nh_server_create", self.lib)
         self._shapes: Dict[int, tuple] = {}
         self._done = (ctypes.c_longlong * 256)()
+        if slice_iters:
+            self.set_slice(slice_iters)
+        if backfill_ticks is not None:
+            self.set_backfill(backfill_ticks)
+
+    def set_backfill(self, ticks: int):
+        """Ticks a job that does not fit may be overtaken by later jobs (0 = strict order)."""
+        _check(self.lib.nh_server_set_backfill(self._srv, int(ticks)), self._srv, "nh_server_set_backfill",
+               self.lib)
+
+    def set_slice(self, iters: int):
+        """CG iterations per tick of a 32768-voxel workgroup (see the header)."""
+        _check(self.lib.nh_server_set_slice(self._srv, int(iters)), self._srv, "nh_server_set_slice", self.lib)
 
     def submit(self, alpha, q_xy, q_t, target, dt: float, h: float = 1.0, rtol: float = 1e-6,
                max_iter: int = 1000) -> int:
@@ -79,7 +94,7 @@ class Server:
         return jid.value
 
     def tick(self):
-        """One batched step. Returns ``(n_active, n_queued, finished_ids)``."""
+        """One batched launch. Returns ``(n_active, n_queued, finished_ids)``."""
         na, nq, nf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(self.lib.nh_server_tick(self._srv, ctypes.byref(na), ctypes.byref(nq), self._done,
                                        len(self._done), ctypes.byref(nf)), self._srv, "nh_server_tick", self.lib)
@@ -207,10 +222,11 @@ def target_series(specs, rtol: float = 1e-6) -> List[np.ndarray]:
 
 
 def serve_stream(reqs: Sequence[Request], hbm_budget_bytes: float = 200e9, max_blocks: int = 0,
-                 keep_grads: bool = False) -> StreamResult:
+                 keep_grads: bool = False, log=None, slice_iters: int = 0,
+                 backfill_ticks: Optional[int] = None) -> StreamResult:
     """Feed ``reqs`` to a ``Server`` at their arrival times (wall clock from
     the call) and tick until all are done. Latency = completion - arrival."""
-    srv = Server(hbm_budget_bytes, max_blocks)
+    srv = Server(hbm_budget_bytes, max_blocks, slice_iters=slice_iters, backfill_ticks=backfill_ticks)
     order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival_s)
     pending = deque(order)
     id2req: Dict[int, int] = {}
@@ -238,6 +254,8 @@ def serve_stream(reqs: Sequence[Request], hbm_budget_bytes: float = 200e9, max_b
                 grads[i] = G
             srv.release(jid)
             ndone += 1
+            if log and ndone % 10 == 0:
+                log(f"served {ndone}/{len(reqs)} jobs at {tf:.2f} s")
         if na == 0 and nq == 0 and pending:
             wait = reqs[pending[0]].arrival_s - (time.perf_counter() - t0)
             if wait > 0:
@@ -247,12 +265,13 @@ def serve_stream(reqs: Sequence[Request], hbm_budget_bytes: float = 200e9, max_b
     srv.close()
     lat = [done_t[i] - reqs[i].arrival_s for i in range(len(reqs))]
     res = StreamResult(lat, makespan, losses, st["voxel_steps"], st["cg_iters"],
-                       {"ticks": st["ticks"], "kernel_s": st["kernel_s"], "max_blocks": st["max_blocks"]})
+                       {"ticks": st["ticks"], "kernel_s": st["kernel_s"], "max_blocks": st["max_blocks"],
+                        "workgroup_busy_frac": st["busy_block_s"] / max(st["span_block_s"], 1e-30)})
     res.grads = grads
     return res
 
 
-def sequential_stream(reqs: Sequence[Request], keep_grads: bool = False) -> StreamResult:
+def sequential_stream(reqs: Sequence[Request], keep_grads: bool = False, log=None) -> StreamResult:
     """Baseline: the same requests solved one at a time in arrival order with
     a single-problem ``Solver`` (all of the GPU per job), inputs uploaded and
     results downloaded per job as the server does."""
@@ -290,6 +309,8 @@ def sequential_stream(reqs: Sequence[Request], keep_grads: bool = False) -> Stre
         st = sv.stats()
         vs += 2.0 * nx * ny * nz * len(r.q_t)
         iters += st["fwd_iters"] + st["adj_iters"]
+        if log and (order.index(i) + 1) % 10 == 0:
+            log(f"sequential {order.index(i) + 1}/{len(reqs)} jobs at {done_t[i]:.2f} s")
     makespan = max(done_t) - min(r.arrival_s for r in reqs)
     for sv in solvers.values():
         sv.close()
@@ -297,3 +318,61 @@ def sequential_stream(reqs: Sequence[Request], keep_grads: bool = False) -> Stre
     res = StreamResult(lat, makespan, losses, vs, iters)
     res.grads = grads
     return res
+
+
+def benchmark(n_jobs: int = 40, rate: float = 20.0, seed: int = 5, hbm_budget_bytes: float = 200e9,
+              sequential: bool = True, log=None, slice_iters: int = 0,
+              backfill_ticks: Optional[int] = None) -> dict:
+    """Serve the first ``n_jobs`` of the Poisson stream of mixed grids, then
+    (optionally) the same requests sequentially; returns both summaries and
+    the speedup of the served stream (throughput and latency)."""
+    from . import workloads as wl
+
+    def say(*a):
+        if log:
+            log(" ".join(str(x) for x in a))
+
+    t = time.perf_counter()
+    specs = wl.serving_stream(n_jobs=n_jobs, rate=rate, seed=seed)
+    targets = target_series(specs)
+    reqs = requests_from_specs(specs, targets)
+    torch.cuda.synchronize()
+    say(f"serve: {n_jobs} jobs generated with targets in {time.perf_counter() - t:.1f} s")
+    a = serve_stream(reqs, hbm_budget_bytes, log=log, slice_iters=slice_iters, backfill_ticks=backfill_ticks)
+    out = {"rate_jobs_per_s": rate, "seed": seed, "hbm_budget_gb": hbm_budget_bytes / 1e9,
+           "batched": a.summary()}
+    say("serve: batched", out["batched"])
+    if sequential:
+        b = sequential_stream(reqs, log=log)
+        out["sequential"] = b.summary()
+        say("serve: sequential", out["sequential"])
+        out["speedup_throughput"] = out["batched"]["jobs_per_s"] / out["sequential"]["jobs_per_s"]
+        out["speedup_p50"] = out["sequential"]["p50_ms"] / out["batched"]["p50_ms"]
+        out["speedup_p99"] = out["sequential"]["p99_ms"] / out["batched"]["p99_ms"]
+        dl = max(abs(x - y) / abs(y) for x, y in zip(a.losses, b.losses))
+        out["max_rel_loss_diff_vs_sequential"] = dl
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+
+    p = argparse.ArgumentParser(description="Serve a Poisson stream of mixed-grid inversion jobs on one GPU")
+    p.add_argument("--jobs", type=int, default=40)
+    p.add_argument("--rate", type=float, default=20.0)
+    p.add_argument("--seed", type=int, default=5)
+    p.add_argument("--budget-gb", type=float, default=200.0)
+    p.add_argument("--no-sequential", action="store_true")
+    p.add_argument("--slice", type=int, default=0, help="CG iterations per tick (0 = library default)")
+    p.add_argument("--backfill", type=int, default=None, help="backfill window in ticks (0 = strict order)")
+    args = p.parse_args(argv)
+    res = benchmark(args.jobs, args.rate, args.seed, args.budget_gb * 1e9, not args.no_sequential,
+                    log=lambda s: print(s, file=sys.stderr, flush=True), slice_iters=args.slice,
+                    backfill_ticks=args.backfill)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,7 +77,8 @@ def test_batched_jobs_match_oracle(jobs):
         assert rel_l2(G, j["G"]) <= 1e-4
     st = srv.stats()
     assert st["jobs_done"] == len(jobs) and st["active"] == 0 and st["used_bytes"] == 0
-    assert st["ticks"] == max(2 * j["w"].nsteps for j in jobs)
+    # the forward and the adjoint of a job never share a launch
+    assert 2 <= st["ticks"] <= max(2 * j["w"].nsteps for j in jobs)
     srv.close()
 
 
@@ -90,8 +91,9 @@ def test_alone_equals_mixed(jobs):
         alone.append(srv.result(jid)[:2])
         srv.close()
     # the mix: staggered arrivals, jobs join while others are in their
-    # forward or adjoint sweeps
-    srv = Server(hbm_budget_bytes=8e9)
+    # forward or adjoint sweeps; one-iteration slices (one step per job and
+    # tick) against the default slices of the runs alone
+    srv = Server(hbm_budget_bytes=8e9, slice_iters=1)
     ids = [submit(srv, jobs[0])]
     for k in range(3):
         srv.tick()

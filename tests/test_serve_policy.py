@@ -19,11 +19,22 @@ def lib():
     return _lib.load()
 
 
-def admit(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks):
+def select(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks, waited=None, reserve_after=0):
     n = len(bytes_)
+    waited = [0] * n if waited is None else waited
     b = (ctypes.c_size_t * max(n, 1))(*bytes_)
     t = (ctypes.c_int * max(n, 1))(*teams)
-    return lib.nh_serve_admit_count(b, t, n, used_bytes, used_blocks, float(budget), max_blocks)
+    w = (ctypes.c_int * max(n, 1))(*waited)
+    sel = (ctypes.c_int * max(n, 1))()
+    k = lib.nh_serve_admit_select(b, t, w, n, used_bytes, used_blocks, float(budget), max_blocks, reserve_after, sel)
+    return [sel[i] for i in range(k)]
+
+
+def admit(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks):
+    """Strict arrival order: the number of jobs admitted from the head."""
+    sel = select(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks)
+    assert sel == list(range(len(sel)))
+    return len(sel)
 
 
 def test_admit_prefix_by_budget(lib):
@@ -40,15 +51,31 @@ def test_admit_prefix_by_workgroups(lib):
     assert admit(lib, [1], [257], 0, 0, 1e18, 256) == 0
 
 
-def test_admission_is_in_arrival_order(lib):
-    # a large job at the head blocks smaller ones behind it (no overtaking)
+def test_strict_order_blocks_behind_the_head(lib):
+    # reserve_after = 0: a large job at the head holds back smaller ones
     assert admit(lib, [100, 1, 1], [1, 1, 1], 0, 0, 50, 100) == 0
     assert admit(lib, [1, 100, 1], [1, 1, 1], 0, 0, 50, 100) == 1
 
 
+def test_backfill_until_the_head_is_reserved(lib):
+    # the 72-workgroup head does not fit in 60 free workgroups
+    teams = [72, 4, 1, 32, 1]
+    bytes_ = [1] * 5
+    # young head: jobs behind it that fit are admitted, in order
+    assert select(lib, bytes_, teams, 0, 196, 1e18, 256, waited=[3, 2, 1, 0, 0], reserve_after=16) == [1, 2, 3, 4]
+    # the head has waited long enough: it holds its place, nothing overtakes
+    assert select(lib, bytes_, teams, 0, 196, 1e18, 256, waited=[16, 2, 1, 0, 0], reserve_after=16) == []
+    # a younger job that does not fit stops only itself
+    assert select(lib, [1, 1, 1], [8, 300, 8], 0, 0, 1e18, 256, waited=[0, 5, 0], reserve_after=16) == [0, 2]
+    # a reserved job in the middle stops the walk there
+    assert select(lib, [1, 1, 1], [8, 300, 8], 0, 0, 1e18, 256, waited=[0, 20, 0], reserve_after=16) == [0]
+    # the budget applies to what was admitted before in the same walk
+    assert select(lib, [30, 30, 10], [1, 1, 1], 0, 0, 45, 256, waited=[0, 0, 0], reserve_after=16) == [0, 2]
+
+
 def test_admit_edge_cases(lib):
     assert admit(lib, [], [], 0, 0, 10, 10) == 0
-    assert lib.nh_serve_admit_count(None, None, 3, 0, 0, 10.0, 10) == 0
+    assert lib.nh_serve_admit_select(None, None, None, 3, 0, 0, 10.0, 10, 0, None) == 0
 
 
 def test_job_team_sizes(lib):
