@@ -245,7 +245,7 @@ nh_status nh_server_set_slice(nh_server *s, int iters);
 
 /* Backfilling: a queued job that does not fit holds back the jobs behind it
  * only after it has waited `ticks` ticks; until then smaller jobs behind it
- * that fit are admitted first (default 16; 0 = strict arrival order). */
+ * that fit are admitted first (default 64; 0 = strict arrival order). */
 nh_status nh_server_set_backfill(nh_server *s, int ticks);
 
 /* Queue a job. HOST inputs: alpha [nz][ny][nx] (finite, > 0), q_xy [ny][nx],

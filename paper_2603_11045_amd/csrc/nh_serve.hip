@@ -247,7 +247,7 @@ struct nh_server {
   int num_cu = 0, max_blocks = 0;
   double budget = 0;
   int slice_iters = 128;
-  int backfill_ticks = 16;
+  int backfill_ticks = 64;
   size_t used_bytes = 0;
   int used_blocks = 0;
   long long next_id = 1;
