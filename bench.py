@@ -8,7 +8,15 @@ Default workload: 256x256x64 voxels, 1000 steps, dt = 10, lognormal alpha
 FP32 vectors with FP64 reductions and gradient.
 
 Prints one JSON line. ``value`` is fwd+adjoint voxel-steps/s
-(voxels * steps / time of one forward plus one adjoint).
+(voxels * steps / time of one forward plus one adjoint). ``roofline`` prices
+the dominant kernel against the HBM peak with algorithmic bytes: 48 bytes per
+voxel and CG iteration plus 24 (forward) or 52 (adjoint) bytes per voxel and
+step, the traffic of textbook two-pass Jacobi-PCG with its vectors in HBM,
+over the kernel's HIP-event time; ``traffic`` is the counter-measured HBM
+bytes per launch when a record taken on the same kernel sources is stored
+under profiles/. ``serve`` runs the first jobs of the Poisson serving stream
+through the batching server and, as the baseline, one by one through the
+single-problem path.
 """
 from __future__ import annotations
 
@@ -74,6 +82,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=16)
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
+    ap.add_argument("--serve-jobs", type=int, default=40,
+                    help="jobs of the Poisson serving stream to serve (0 = skip the serving run)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (nh_copy_f32) three times, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -159,14 +169,28 @@ def main():
     iters = it_f + it_a + it_r
     st = solver.stats()
     roof = None
+    if st["resident"]:
+        kname = "nh::resident_step_kernel<64>"
+    else:
+        kname = "nh::step_kernel<float>" if w.precision == "f32" else "nh::step_kernel<double>"
     if not args.no_profile and (tk_f + tk_a) > 0:
+        from paper_2603_11045_amd import profiling
+
         achieved = (bytes_f + bytes_a) / (tk_f + tk_a) / 1e9
+        alg_per_launch = (bytes_f + bytes_a) / max(launches, 1)
+        tr_path = os.path.join(ROOT, "profiles", f"traffic_{kname.split('::')[1].split('<')[0]}_{w.name}.json")
+        tr = profiling.load_traffic(tr_path, kname)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "nh::step_kernel<float>" if w.precision == "f32" else "nh::step_kernel<double>",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+                "kernel": kname,
                 "avg_launch_us": round((tk_f + tk_a) / max(launches, 1) * 1e6, 2),
-                "alg_bytes_per_launch": (bytes_f + bytes_a) / max(launches, 1),
+                "alg_bytes_per_launch": alg_per_launch,
+                "alg_bytes_model": "48 B/voxel/CG iteration + 24 (fwd) or 52 (adj) B/voxel/step",
                 "kernel_time_frac": round((tk_f + tk_a) / elapsed, 4)}
+        if tr:
+            roof["traffic_over_alg"] = round(tr["traffic_bytes_per_launch"] / alg_per_launch, 4)
+            roof["traffic_source"] = os.path.relpath(tr_path, ROOT)
     rec = {
         "metric": "fwd+adjoint voxel-steps/s",
         "value": value,
@@ -191,6 +215,23 @@ def main():
         "roofline": roof,
         "peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
     }
+    del solver, alpha, q_xy, target
+    torch.cuda.empty_cache()
+    if args.serve_jobs > 0:
+        from paper_2603_11045_amd import serve
+
+        print(f"[bench] serving: first {args.serve_jobs} jobs of the Poisson stream (20 jobs/s, seed 5)",
+              file=sys.stderr, flush=True)
+        sv = serve.benchmark(args.serve_jobs, log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
+        b, q = sv["batched"], sv["sequential"]
+        rec["serve"] = {
+            "jobs": b["jobs"], "rate_jobs_per_s": sv["rate_jobs_per_s"], "hbm_budget_gb": sv["hbm_budget_gb"],
+            "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"], "jobs_per_s": b["jobs_per_s"],
+            "voxel_steps_per_s": b["voxel_steps_per_s"], "workgroup_busy_frac": b["workgroup_busy_frac"],
+            "sequential": {"p50_ms": q["p50_ms"], "p99_ms": q["p99_ms"], "jobs_per_s": q["jobs_per_s"]},
+            "speedup": {"throughput": sv["speedup_throughput"], "p50": sv["speedup_p50"],
+                        "p99": sv["speedup_p99"]},
+        }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         cb = cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps))

@@ -67,8 +67,10 @@ typedef struct {
     int fwd_steps, adj_steps, recompute_steps;
     int max_step_iters;         /* largest per-step iteration count of the last forward/adjoint */
     double worst_rel_res;       /* largest final ||r||/||b|| over those solves */
-    double bytes_alg_fwd;       /* algorithmic HBM bytes of the step kernels, last forward */
-    double bytes_alg_adj;       /* same for the last adjoint (recomputation included) */
+    double bytes_alg_fwd;       /* algorithmic bytes of the last forward: 12R per voxel and CG iteration, 6R
+                                   per voxel and step (textbook two-pass Jacobi-PCG, vectors in HBM) */
+    double bytes_alg_adj;       /* same for the last adjoint, 10R + 16 per voxel and step for the state load
+                                   and the FP64 gradient (recomputed forward steps counted as forward) */
     double t_fwd_s, t_adj_s;    /* host wall time of the last forward / adjoint call */
     double t_kernel_fwd_s;      /* summed HIP-event durations of the forward step kernels
                                    (only when profiling is enabled, else 0) */

@@ -369,38 +369,18 @@ nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
   return h ? NH_EINVAL : NH_OK;
 }
 
-// Per-voxel algorithmic bytes of one step kernel (R = vector element size).
-double step_bytes(const Geom& g, int R, int variant, int mode, int iters, bool first_step, bool surf, bool ckpt,
-                  bool resident = false) {
-  const double ng = (double)g.ng, nxy = (double)g.nxy;
-  double b = 0;
-  if (resident) {
-    // alpha and the previous state in, the state out; per iteration only the
-    // tile faces move: 3 vectors written once and read by the neighbour
-    const double faces = (double)g.ntiles * (2.0 * g.TX * g.TY + 2.0 * (g.TX + g.TY) * g.TZ);
-    b += (first_step && mode == nh::kForward ? 2.0 : 3.0) * R * ng + R * nxy;
-    if (surf) b += 2.0 * R * nxy;
-    if (ckpt) b += R * ng;
-    if (mode == nh::kAdjoint) b += (R + 16.0) * ng + R * ng;   // T^n, G read+write, mu faces re-read
-    b += (iters + 1) * 6.0 * R * faces;
-    return b;
-  }
-  if (mode == nh::kForward) {
-    b += (first_step ? 3.0 : 4.0) * R * ng;        // read x0 (halo), alpha; write x, z
-    if (surf) b += 2.0 * R * nxy;
-    if (ckpt) b += 2.0 * R * ng;
-    b += R * nxy;                                 // top source map
-  } else {
-    b += 3.0 * R * ng + R * nxy;                  // read x, alpha, g^n; write z
-    b += (3.0 * R + 16.0) * ng;                   // gradient: read mu, T, alpha; G read+write
-  }
-  if (iters > 0) {
-    if (variant == 0)
-      b += (10.0 * iters - 1.0) * R * ng;   // 4R + 6R per iteration, no p_old on the first
-    else
-      b += (11.0 * iters + 1.0) * R * ng;   // set-up 3R, first iteration 9R, then 11R each
-  }
-  return b;
+// Algorithmic bytes of one step, R bytes per vector element: the traffic of
+// the textbook two-pass Jacobi-PCG with every vector in HBM, whatever the
+// kernel actually keeps on chip. Per iteration and voxel the operator pass
+// reads r, p, alpha and writes p, q (5R) and the update pass reads x, p, r,
+// q, 1/D and writes x, r (7R): 12R. Per step the residual set-up reads the
+// previous state, alpha and the source and writes r, z (5R) and the state is
+// stored (R); an adjoint step also loads T^n (R) and accumulates the gradient
+// (T, mu, alpha read: 3R; the FP64 accumulator read and written: 16 bytes).
+// FP32: 48 bytes per voxel-iteration, 24 per forward step, 52 per adjoint step.
+double step_bytes(const Geom& g, int R, int mode, int iters) {
+  const double per_voxel = 12.0 * R * iters + (mode == nh::kForward ? 6.0 * R : 10.0 * R + 16.0);
+  return per_voxel * (double)g.ng;
 }
 
 template <typename R>
@@ -582,8 +562,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     NH_HIP(c, hipStreamSynchronize(c->stream));
     double bytes = 0;
     for (int n = 1; n <= nsteps; ++n)
-      bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, it[n - 1], n == 1, true,
-                          k > 0 && n % k == 0 && n < nsteps, sizeof(R) == 4 && c->resident);
+      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1]);
     c->st.bytes_alg_fwd = bytes;
   }
   c->saved_prec = sizeof(R);
@@ -683,8 +662,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
   NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 1, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   for (int n = 1; n <= N; ++n)
-    bytes += step_bytes(g, sizeof(R), c->variant, nh::kAdjoint, it[n - 1], false, false, false,
-                        sizeof(R) == 4 && c->resident);
+    bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1]);
   c->st.recompute_iters = 0;
   if (k > 0) {
     long long rsum = 0;
@@ -697,8 +675,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     NH_HIP(c, hipMemcpyAsync(ir.data(), step_out(c, 2, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
     NH_HIP(c, hipStreamSynchronize(c->stream));
     for (int n = 1; n <= N; ++n)
-      bytes += step_bytes(g, sizeof(R), c->variant, nh::kForward, ir[n - 1], n == 1, false, false,
-                          sizeof(R) == 4 && c->resident);
+      bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1]);
   }
   c->st.bytes_alg_adj = bytes;
   c->st.workspace_bytes = c->ws_bytes;
