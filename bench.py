@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=16)
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
+    ap.add_argument("--ckpt-overhead", action="store_true",
+                    help="with checkpointing on: also time the same passes with full trajectory storage "
+                         "and report peak device memory of both")
     ap.add_argument("--serve-jobs", type=int, default=40,
                     help="jobs of the Poisson serving stream to serve (0 = skip the serving run)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -215,6 +218,35 @@ def main():
         "roofline": roof,
         "peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
     }
+    rec["memory"] = {"library_peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
+                     "torch_peak_allocated_gb": torch.cuda.max_memory_allocated(dev) / 1e9,
+                     "device_used_gb": (torch.cuda.mem_get_info(dev)[1] - torch.cuda.mem_get_info(dev)[0]) / 1e9}
+    if args.ckpt_overhead and ck > 0:
+        # the same passes with every state stored: the cost of recomputation
+        solver.close()
+        torch.cuda.empty_cache()
+        full = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=w.rtol, max_iter=2000, checkpoint_every=0,
+                      precision=w.precision, device=0, team_blocks_max=args.team, tile_z=args.tile_z)
+        print("[bench] full-storage comparison ...", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            S = full.forward(alpha, q_xy, w.q_t, w.dt, w.nsteps)
+            full.adjoint((2.0 / m) * (S - target))
+            print(f"[bench] full-storage step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el_full = time.perf_counter() - t1
+        sf = full.stats()
+        rec["checkpointing"] = {
+            "checkpoint_every": ck,
+            "ms_per_step": elapsed / K * 1e3,
+            "peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
+            "recompute_iters_per_step": it_r / K,
+            "full_storage": {"ms_per_step": el_full / K * 1e3, "peak_workspace_gb": sf["peak_workspace_bytes"] / 1e9},
+            "time_overhead": elapsed / el_full - 1.0,
+            "memory_saving": 1.0 - st["peak_workspace_bytes"] / sf["peak_workspace_bytes"],
+        }
+        full.close()
     del solver, alpha, q_xy, target
     torch.cuda.empty_cache()
     if args.serve_jobs > 0:

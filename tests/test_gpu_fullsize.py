@@ -1,0 +1,136 @@
+"""Full-size checks on the 256x256x64 workload, in the launch configuration
+the benchmark times (the register-resident kernel for FP32).
+
+- A short horizon (3 steps) against the FP64 oracle: surface temperature and
+  dL/dalpha, same tolerances as the small parity cases.
+- Over a 20-step horizon, properties that hold at any size, with the FP64
+  path at rtol 1e-13: central finite differences of the MSE loss in single
+  voxels (32 uniform over the grid, seed 33, plus 16 in the top four layers
+  where the gradient is large), the homogeneity identity
+  sum_p alpha_p dL/dalpha_p = dL(c alpha)/dc at c = 1, and one random
+  direction <dL/dalpha, v> against the difference quotient along v. Gate per
+  voxel: |g_fd - g| <= 1e-4 * max(|g_fd|, 1e-3 * max|g|).
+- The FP32 path's gradient against the FP64 path's, 1e-4 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import heat as orc
+from paper_2603_11045_amd import _lib
+from paper_2603_11045_amd import workloads as wl
+from paper_2603_11045_amd.solver import Solver
+
+pytestmark = pytest.mark.gpu
+
+NSTEPS_FD = 20
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    _lib.load()
+
+
+def test_full_size_short_horizon_matches_oracle():
+    w = wl.stiff_256x256x64(nsteps=3)
+    src = orc.source_series(w.q_xy, w.q_t)
+    S_o, T_all, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-13)
+    St, _, _ = orc.forward(w.alpha_target, src, w.dt, rtol=1e-13, keep_states=False)
+    L_o, gs = orc.mse_loss_and_grad(S_o, St)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_all, gs, w.dt, rtol=1e-13)
+    s = Solver(w.nx, w.ny, w.nz, rtol=w.rtol, max_iter=2000)
+    S = s.forward(dev(w.alpha, torch.float32), dev(w.q_xy, torch.float32), w.q_t, w.dt, w.nsteps)
+    st = s.stats()
+    G = s.adjoint(dev(gs, torch.float32)).cpu().numpy()
+    eS, eG = rel_l2(S.cpu().numpy(), S_o), rel_l2(G, G_o)
+    say("256x256x64, 3 steps: resident", st["resident"], "team", st["team_blocks"], "tile",
+        (st["tile_x"], st["tile_y"], st["tile_z"]), "S rel", eS, "G rel", eG)
+    assert st["resident"] == 1 and st["team_blocks"] == 256
+    assert eS <= 1e-5
+    assert eG <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def fd_setup():
+    w = wl.stiff_256x256x64(nsteps=NSTEPS_FD)
+    s = Solver(w.nx, w.ny, w.nz, rtol=1e-13, max_iter=5000, precision="f64")
+    q = dev(w.q_xy, torch.float64)
+    target = s.forward(dev(w.alpha_target, torch.float64), q, w.q_t, w.dt, w.nsteps).clone()
+    m = target.numel()
+
+    def loss(a_np):
+        S = s.forward(dev(a_np, torch.float64), q, w.q_t, w.dt, w.nsteps)
+        d = S - target
+        return float((d * d).sum() / m)
+
+    a = w.alpha.astype(np.float64)
+    S = s.forward(dev(a, torch.float64), q, w.q_t, w.dt, w.nsteps)
+    L0 = float(((S - target) ** 2).sum() / m)
+    gs = (2.0 / m) * (S - target)
+    G = s.adjoint(gs).cpu().numpy()
+    return dict(w=w, s=s, loss=loss, a=a, G=G, L0=L0, gs=gs.clone(), m=m)
+
+
+def test_fd_single_voxels(fd_setup):
+    a, G, loss = fd_setup["a"], fd_setup["G"], fd_setup["loss"]
+    nz, ny, nx = a.shape
+    rng = np.random.default_rng(33)
+    vox = [(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(32)]
+    vox += [(int(rng.integers(4)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(16)]
+    gmax = float(np.abs(G).max())
+    eps = 1e-3
+    worst = 0.0
+    for p in vox:
+        ap, am = a.copy(), a.copy()
+        hp = eps * a[p]
+        ap[p] += hp
+        am[p] -= hp
+        g_fd = (loss(ap) - loss(am)) / (2 * hp)
+        tol = 1e-4 * max(abs(g_fd), 1e-3 * gmax)
+        worst = max(worst, abs(g_fd - G[p]) / tol)
+        assert abs(g_fd - G[p]) <= tol, (p, g_fd, G[p], tol)
+    say(f"FD over {len(vox)} voxels: worst |g_fd - g| / tol = {worst:.3f}, max|g| = {gmax:.3e}")
+
+
+def test_homogeneity_and_random_direction(fd_setup):
+    a, G, loss = fd_setup["a"], fd_setup["G"], fd_setup["loss"]
+    # sum_p alpha_p dL/dalpha_p = d/dc L(c alpha) at c = 1
+    c = 1e-4
+    d_c = (loss(a * (1 + c)) - loss(a * (1 - c))) / (2 * c)
+    lhs = float(np.sum(a * G))
+    say("homogeneity: sum alpha*g", lhs, "dL/dc", d_c)
+    assert abs(lhs - d_c) <= 1e-5 * abs(d_c)
+    # one random direction, scaled by alpha so that alpha stays positive
+    v = np.random.default_rng(34).standard_normal(a.shape) * a
+    e = 1e-4
+    d_v = (loss(a + e * v) - loss(a - e * v)) / (2 * e)
+    gv = float(np.sum(G * v))
+    say("direction: <g, v>", gv, "FD", d_v)
+    assert abs(gv - d_v) <= 1e-5 * max(abs(d_v), 1e-3 * float(np.abs(G).max()) * float(np.abs(v).sum()))
+
+
+def test_fp32_gradient_matches_fp64_at_full_size(fd_setup):
+    # the same dL/dS drives both adjoints; the FP32 path keeps its own trajectory
+    w, G64, gs = fd_setup["w"], fd_setup["G"], fd_setup["gs"]
+    s = Solver(w.nx, w.ny, w.nz, rtol=w.rtol, max_iter=2000)
+    s.forward(dev(w.alpha, torch.float32), dev(w.q_xy, torch.float32), w.q_t, w.dt, w.nsteps)
+    G = s.adjoint(gs.float().contiguous()).cpu().numpy()
+    e = rel_l2(G, G64)
+    say("FP32 (rtol 1e-6) vs FP64 (rtol 1e-13) gradient at 256x256x64,", NSTEPS_FD, "steps:", e)
+    assert s.stats()["resident"] == 1
+    assert e <= 1e-4
