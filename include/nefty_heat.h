@@ -150,6 +150,16 @@ nh_status nh_set_launch(nh_ctx *ctx, int team_blocks_max, int tile_z, int profil
  * |r|^2 are reduced together once per iteration. Frees the saved forward. */
 nh_status nh_set_cg_variant(nh_ctx *ctx, int variant);
 
+/* CG initial guess of every solve: 1 (default) extrapolates the states of
+ * the preceding time levels -- 2 h1 - h2 with two of them, 3 h1 - 3 h2 + h3
+ * with three (h1 = T^{n-1}, h2 = T^{n-2}, ... forward; mu^{n+1}, mu^{n+2},
+ * ... adjoint); 0 starts from the previous state h1 alone. Both converge to
+ * the same tolerance; the extrapolation needs fewer iterations on smooth
+ * trajectories. With checkpointing the three states below each checkpoint
+ * are kept, so recomputed segments repeat the forward bit for bit. Drops any
+ * saved forward. */
+nh_status nh_set_initial_guess(nh_ctx *ctx, int mode);
+
 /* Time limit of the device-side team barrier in seconds (default 20). A
  * barrier that waits longer makes its kernel exit and the call return
  * NH_ETIMEOUT; the context stays usable. */

@@ -61,7 +61,10 @@ struct nh_ctx {
   std::vector<double> saved_qt;
 
   // workspaces
-  Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, mu, w0, w1, traj, seg, slots, steps, flag;
+  Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
+  Buf mu[4];                                 // adjoint states, mu^n in mu[n & 3]
+  Buf w[4];                                  // checkpointed forward: T^n in w[n & 3]
+  int guess = 1;                             // initial guess: 0 previous state, 1 extrapolated
   int variant = 2;                           // 0 two reductions per iteration, 1 one, 2 one + register-resident
   bool resident = false;                     // the current plan uses nh::resident_step_kernel
   unsigned long long launch_ctr = 0;         // makes every launch's reduction epochs unique
@@ -132,8 +135,7 @@ void drop_forward(nh_ctx* c) {
   c->saved_nsteps = 0;
   release(c, c->traj);
   release(c, c->seg);
-  release(c, c->w0);
-  release(c, c->w1);
+  for (Buf& b : c->w) release(c, b);
 }
 
 template <typename T>
@@ -417,16 +419,37 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   return NH_OK;
 }
 
-// One forward step n (1-based) into x from xprev; region selects where its
-// iteration count goes (0 forward, 2 recompute).
+// The previous state h1 and the CG initial guess. With the extrapolating
+// guess and two (three) earlier states available, x0 is the linear
+// (quadratic) extrapolation 2 h1 - h2 (3 h1 - 3 h2 + h3) of the states at the
+// three preceding time levels; else x0 = h1. Null states are zero.
 template <typename R>
-nh_status forward_step(nh_ctx* c, int n, const R* xprev, R* x, const R* q_xy, double dt, double qt,
+void set_guess(const nh_ctx* c, StepArgs<R>& S, const R* const (&h)[3]) {
+  S.xprev = h[0];
+  S.xprev2 = S.xprev3 = nullptr;
+  S.ex1 = R(1);
+  S.ex2 = S.ex3 = R(0);
+  if (!c->guess || !h[0] || !h[1]) return;
+  S.xprev2 = h[1];
+  if (h[2]) {
+    S.xprev3 = h[2];
+    S.ex1 = R(3); S.ex2 = R(-3); S.ex3 = R(1);
+  } else {
+    S.ex1 = R(2); S.ex2 = R(-1);
+  }
+}
+
+// One forward step n (1-based) into x from the previous states h = T^{n-1},
+// T^{n-2}, T^{n-3}; region selects where its iteration count goes (0 forward,
+// 2 recompute).
+template <typename R>
+nh_status forward_step(nh_ctx* c, int n, const R* const (&h)[3], R* x, const R* q_xy, double dt, double qt,
                        R* surf, R* ckpt, int region, int ev_slot) {
   StepArgs<R> S;
   base_args<R>(c, S, dt);
   S.mode = nh::kForward;
   S.x = x;
-  S.xprev = xprev;
+  set_guess<R>(c, S, h);
   S.top_src = q_xy;
   S.top_scale = (R)(dt * qt);
   S.surf_out = surf;
@@ -510,10 +533,11 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     NH_TRY(ensure(c, c->traj, vb * (size_t)nsteps));
     traj = (R*)c->traj.p;
   } else {
-    const int nck = (nsteps - 1) / k;               // T^k, T^2k, ... below T^N
-    if (nck > 0) NH_TRY(ensure(c, c->traj, vb * (size_t)nck));
-    NH_TRY(ensure(c, c->w0, vb));
-    NH_TRY(ensure(c, c->w1, vb));
+    // checkpoint j holds T^{jk}, T^{jk-1}, T^{jk-2} (the states the initial
+    // guess of step jk+1 uses), for jk below N
+    const int nck = (nsteps - 1) / k;
+    if (nck > 0) NH_TRY(ensure(c, c->traj, 3 * vb * (size_t)nck));
+    for (Buf& b : c->w) NH_TRY(ensure(c, b, vb));
   }
 
   c->st.fwd_iters = 0;
@@ -522,21 +546,22 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
   c->st.t_kernel_fwd_s = 0;
   double tk = 0;
   int used = 0;
+  R* const w[4] = {(R*)c->w[0].p, (R*)c->w[1].p, (R*)c->w[2].p, (R*)c->w[3].p};
+  auto state = [&](int m) -> R* {   // T^m, null for T^0 = 0
+    if (m < 1) return nullptr;
+    return k == 0 ? traj + (size_t)(m - 1) * g.ng : w[m & 3];
+  };
   for (int n = 1; n <= nsteps; ++n) {
-    const R* xprev;
-    R* x;
+    const R* const h[3] = {state(n - 1), state(n - 2), state(n - 3)};
+    R* x = state(n);
     R* ck = nullptr;
-    if (k == 0) {
-      xprev = n == 1 ? nullptr : traj + (size_t)(n - 2) * g.ng;
-      x = traj + (size_t)(n - 1) * g.ng;
-    } else {
-      R* w[2] = {(R*)c->w0.p, (R*)c->w1.p};
-      xprev = n == 1 ? nullptr : w[(n - 1) & 1];
-      x = w[n & 1];
-      if (n % k == 0 && n < nsteps) ck = (R*)c->traj.p + (size_t)(n / k - 1) * g.ng;
-    }
-    NH_TRY(forward_step<R>(c, n, xprev, x, qsrc, dt, q_t[n - 1], T_surf + (size_t)(n - 1) * g.nxy,
+    const bool ckpt = k > 0 && n % k == 0 && n < nsteps;
+    if (ckpt) ck = (R*)c->traj.p + (size_t)(n / k - 1) * 3 * g.ng;
+    NH_TRY(forward_step<R>(c, n, h, x, qsrc, dt, q_t[n - 1], T_surf + (size_t)(n - 1) * g.nxy,
                            ck, 0, used));
+    if (ckpt)
+      for (int d = 1; d <= 2 && n - d >= 1; ++d)
+        NH_HIP(c, hipMemcpyAsync(ck + (size_t)d * g.ng, state(n - d), vb, hipMemcpyDeviceToDevice, c->stream));
     ++c->st.launches_fwd;
     if (c->profile && ++used == kEvPairs) {
       NH_TRY(collect_events(c, used, &tk));
@@ -585,8 +610,9 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
   const int N = c->saved_nsteps, k = c->ckpt_every;
   const double dt = c->saved_dt;
   const size_t vb = sizeof(R) * (size_t)g.ng;
-  NH_TRY(ensure(c, c->mu, vb));
-  NH_TRY(fill<R>(c, (R*)c->mu.p, g.ng, R(0)));
+  for (Buf& b : c->mu) NH_TRY(ensure(c, b, vb));
+  R* const M[4] = {(R*)c->mu[0].p, (R*)c->mu[1].p, (R*)c->mu[2].p, (R*)c->mu[3].p};
+  auto mu_state = [&](int m) -> const R* { return m > N ? nullptr : M[m & 3]; };   // mu^{N+1} = 0
   NH_TRY(fill<double>(c, G, g.ng, 0.0));
   NH_TRY(ensure_events(c));
 
@@ -602,8 +628,9 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     StepArgs<R> S;
     base_args<R>(c, S, dt);
     S.mode = nh::kAdjoint;
-    S.x = (R*)c->mu.p;
-    S.xprev = nullptr;
+    S.x = M[n & 3];
+    const R* const h[3] = {mu_state(n + 1), mu_state(n + 2), mu_state(n + 3)};
+    set_guess<R>(c, S, h);
     S.top_src = gsurf + (size_t)(n - 1) * g.nxy;
     S.top_scale = R(1);
     S.T_grad = Tn;
@@ -631,10 +658,15 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     const R* qxy = (const R*)c->qxy.p;
     for (int s_idx = nseg - 1; s_idx >= 0; --s_idx) {
       const int s = s_idx * k, e = std::min(s + k, N);
-      const R* start = s == 0 ? nullptr : (const R*)c->traj.p + (size_t)(s_idx - 1) * g.ng;
+      // T^m of this segment: recomputed into seg above s, from the checkpoint at and below s
+      auto state = [&](int m) -> const R* {
+        if (m < 1) return nullptr;
+        if (m > s) return seg + (size_t)(m - s - 1) * g.ng;
+        return (const R*)c->traj.p + ((size_t)(s_idx - 1) * 3 + (size_t)(s - m)) * g.ng;
+      };
       for (int n = s + 1; n <= e; ++n) {
-        const R* xprev = n == s + 1 ? start : seg + (size_t)(n - s - 2) * g.ng;
-        NH_TRY(forward_step<R>(c, n, xprev, seg + (size_t)(n - s - 1) * g.ng, qxy, dt,
+        const R* const h[3] = {state(n - 1), state(n - 2), state(n - 3)};
+        NH_TRY(forward_step<R>(c, n, h, seg + (size_t)(n - s - 1) * g.ng, qxy, dt,
                                c->saved_qt[n - 1], nullptr, nullptr, 2, used));
         ++c->st.launches_adj;
         ++c->st.recompute_steps;
@@ -748,7 +780,7 @@ nh_status nh_set_grid(nh_ctx* c, int nx, int ny, int nz, double hx, double hy, d
   NH_TRY(release(c, c->z));
   NH_TRY(release(c, c->p0));
   NH_TRY(release(c, c->p1));
-  NH_TRY(release(c, c->mu));
+  for (Buf& b : c->mu) NH_TRY(release(c, b));
   plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
   return NH_OK;
 }
@@ -793,9 +825,9 @@ nh_status nh_get_state(nh_ctx* c, int n, void* out) {
   if (c->ckpt_every == 0) {
     src = (const char*)c->traj.p + (size_t)(n - 1) * vb;
   } else if (n % c->ckpt_every == 0 && n < c->saved_nsteps) {
-    src = (const char*)c->traj.p + (size_t)(n / c->ckpt_every - 1) * vb;
+    src = (const char*)c->traj.p + (size_t)(n / c->ckpt_every - 1) * 3 * vb;
   } else if (n == c->saved_nsteps) {
-    src = (n & 1) ? c->w1.p : c->w0.p;
+    src = c->w[n & 3].p;
   } else {
     return fail(c, NH_ESTATE, "state not held (checkpointing keeps every k-th state and the last)");
   }
@@ -840,6 +872,14 @@ nh_status nh_set_cg_variant(nh_ctx* c, int variant) {
   return NH_OK;
 }
 
+nh_status nh_set_initial_guess(nh_ctx* c, int mode) {
+  if (!c) return NH_EINVAL;
+  if (mode < 0 || mode > 1) return fail(c, NH_EINVAL, "initial guess mode must be 0 or 1");
+  drop_forward(c);
+  c->guess = mode;
+  return NH_OK;
+}
+
 nh_status nh_set_barrier_timeout(nh_ctx* c, double seconds) {
   if (!c) return NH_EINVAL;
   if (!(seconds >= 0) || !std::isfinite(seconds)) return fail(c, NH_EINVAL, "timeout must be finite and >= 0");
@@ -865,9 +905,10 @@ void nh_destroy(nh_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
-                 &c->vs0, &c->vs1, &c->mu, &c->w0, &c->w1, &c->traj,
-                 &c->seg, &c->slots, &c->steps, &c->flag};
+                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag};
   for (Buf* b : bufs) release(c, *b);
+  for (Buf& b : c->mu) release(c, b);
+  for (Buf& b : c->w) release(c, b);
   for (auto e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

@@ -60,7 +60,10 @@ struct StepArgs {
   R sx, sy, sz;                             // 2 dt / h_d^2 per axis
   const R* alpha;
   R* x;                                     // the unknown, solved in place
-  const R* xprev;                           // forward: T^{n-1} (null = zero state); adjoint: null
+  const R* xprev;                           // the previous state h1: T^{n-1} or mu^{n+1} (null = zero)
+  const R* xprev2;                          // h2, h3: the two states before it, for the initial guess
+  const R* xprev3;                          //   x0 = ex1 h1 + ex2 h2 + ex3 h3 (null: x0 = h1)
+  R ex1, ex2, ex3;
   R* z;                                     // preconditioned residual
   R* p0;                                    // search direction, ping-pong pair
   R* p1;
@@ -474,7 +477,10 @@ struct InitOp {
   static constexpr int NO = 1;
   using OT = R;
   const R* alpha;
-  const R* src;                             // staged x0 (null = zero state)
+  const R* src;                             // the previous state h1 (null = zero state)
+  const R* h2;                              // with h2 (and h3) the staged x0 extrapolates:
+  const R* h3;                              //   x0 = e1 h1 + e2 h2 + e3 h3; else x0 = h1
+  R e1, e2, e3;
   R* xw;                                    // x to initialise with x0 (null = already there)
   R* z;
   const R* top;
@@ -482,12 +488,19 @@ struct InitOp {
   R sx, sy, sz;
   long long nxy;
   double acc[3];                            // |b|^2, r.z, |r|^2
-  __device__ R load(int, long long i) const { return src ? src[i] : R(0); }
-  __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
+  __device__ R load(int, long long i) const {
+    if (!src) return R(0);
+    if (!h2) return src[i];
+    R v = e2 * h2[i];
+    if (h3) v = fma(e3, h3[i], v);
+    return fma(e1, src[i], v);
+  }
+  // the right-hand side's previous state, when the staged value is an extrapolation
+  __device__ R own(int, long long i) const { return h2 ? src[i] : R(0); }
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[1], long long i, int kz) {
     R Av, D;
     stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
-    R b = P.v[0][0];
+    R b = h2 ? o[0] : P.v[0][0];
     if (kz == 0) b += top_scale * top[i];
     const R r = b - Av;
     const R zz = r * rcp<R>(D);
@@ -728,6 +741,9 @@ template <typename R>
 struct StepVar {
   R* x;
   const R* xprev;
+  const R* xprev2;
+  const R* xprev3;
+  R ex1, ex2, ex3;
   const R* top_src;
   R top_scale;
   R* surf_out;
@@ -744,6 +760,11 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   StepVar<R> V;
   V.x = S.x;
   V.xprev = S.xprev;
+  V.xprev2 = S.xprev2;
+  V.xprev3 = S.xprev3;
+  V.ex1 = S.ex1;
+  V.ex2 = S.ex2;
+  V.ex3 = S.ex3;
   V.top_src = S.top_src;
   V.top_scale = S.top_scale;
   V.surf_out = S.surf_out;
@@ -780,13 +801,11 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
   init.top_scale = V.top_scale;
   init.nxy = g.nxy;
   init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
-  if (S.mode == kForward) {
-    init.src = V.xprev;
-    init.xw = (V.xprev == V.x) ? nullptr : V.x;
-  } else {
-    init.src = V.x;
-    init.xw = nullptr;
-  }
+  init.src = V.xprev;
+  init.h2 = V.xprev ? V.xprev2 : nullptr;
+  init.h3 = init.h2 ? V.xprev3 : nullptr;
+  init.e1 = V.ex1; init.e2 = V.ex2; init.e3 = V.ex3;
+  init.xw = (V.xprev == V.x) ? nullptr : V.x;
   sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
   stamp();
   double v3[3] = {init.acc[0], init.acc[1], init.acc[2]};

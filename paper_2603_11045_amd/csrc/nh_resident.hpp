@@ -314,11 +314,20 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
   float (&xr)[TZ] = pr;                     // x0 lives in the p registers during the set-up
 
   // ---------------- set-up: x0, b, r = b - A x0, u = r / D; x = x0 in memory
-  const float* x0src = S.mode == kForward ? S.xprev : S.x;
+  // x0 = h1 (the previous state), or its extrapolation ex1 h1 + ex2 h2 + ex3 h3
+  const float* x0src = S.xprev;
+  const float* h2 = x0src ? S.xprev2 : nullptr;
+  const float* h3 = h2 ? S.xprev3 : nullptr;
+  auto x0_at = [&](int i) -> float {
+    if (!h2) return x0src[i];
+    float v = S.ex2 * h2[i];
+    if (h3) v = fmaf(S.ex3, h3[i], v);
+    return fmaf(S.ex1, x0src[i], v);
+  };
   if (q.own && x0src) {
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
-      if (z < q.tzn) xr[z] = x0src[q.col + (T.z0 + z) * nxy];
+      if (z < q.tzn) xr[z] = x0_at(q.col + (T.z0 + z) * nxy);
   }
   if (q.own && x0src != S.x) {
 #pragma unroll
@@ -327,9 +336,9 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
   }
   float zlo[2] = {0.f, 0.f}, zhi[2] = {0.f, 0.f};
   if (x0src) {
-    if (q.own && q.bot_z) zlo[0] = x0src[q.col + (T.z0 - 1) * nxy];
-    if (q.own && q.top_z) zhi[0] = x0src[q.col + T.z1 * nxy];
-    fill_ring<G>(g, q, lring, [&](int i) { return x0src[i]; });
+    if (q.own && q.bot_z) zlo[0] = x0_at(q.col + (T.z0 - 1) * nxy);
+    if (q.own && q.top_z) zhi[0] = x0_at(q.col + T.z1 * nxy);
+    fill_ring<G>(g, q, lring, [&](int i) { return x0_at(i); });
   } else {
     fill_ring<G>(g, q, lring, [&](int) { return 0.f; });
   }
@@ -339,7 +348,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
                  [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                    const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                    const float Av = apply_at(n, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
-                   float b = xr[z];
+                   float b = h2 ? x0src[q.col + (T.z0 + z) * nxy] : xr[z];
                    if (T.z0 + z == 0) b += S.top_scale * S.top_src[q.col];
                    const float r = b - Av;
                    const float u = r * rcp<float>(n.D);

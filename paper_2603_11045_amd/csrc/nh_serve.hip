@@ -44,6 +44,7 @@ struct JobRun {
   int* it_out;                // per-step iterations [2][nsteps]: forward, then adjoint
   double* rel_out;            // per-step relative residuals, same layout
   int* st_out;                // per-step status flags, same layout
+  float* mu[4];               // adjoint states, mu^n in mu[n & 3]
   int mode;                   // kForward or kAdjoint
   int n0;                     // first step of the slice (the adjoint counts down to 1)
   int nsteps;
@@ -88,21 +89,30 @@ __global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const 
     V.out_relres = nullptr;
     V.out_status = nullptr;
     V.ckpt_out = nullptr;
+    // the previous states h1..h3 (T^{n-1..n-3} forward, mu^{n+1..n+3} adjoint; null = zero)
+    const float* h[3];
     if (fwd) {
       V.x = J.traj + (long long)(n - 1) * ng;
-      V.xprev = n == 1 ? nullptr : J.traj + (long long)(n - 2) * ng;
+      for (int d = 1; d <= 3; ++d) h[d - 1] = n - d >= 1 ? J.traj + (long long)(n - d - 1) * ng : nullptr;
       V.top_src = J.S.top_src;
       V.top_scale = J.qscale[n - 1];
       V.surf_out = J.surf + (long long)(n - 1) * nxy;
       V.T_grad = nullptr;
     } else {
-      V.x = J.S.x;
-      V.xprev = nullptr;
+      V.x = J.mu[n & 3];
+      for (int d = 1; d <= 3; ++d) h[d - 1] = n + d <= J.nsteps ? J.mu[(n + d) & 3] : nullptr;
       V.top_src = J.gsurf + (long long)(n - 1) * nxy;
       V.top_scale = 1.f;
       V.surf_out = nullptr;
       V.T_grad = J.traj + (long long)(n - 1) * ng;
     }
+    // initial guess: quadratic (linear) extrapolation with three (two) previous states
+    V.xprev = h[0];
+    V.xprev2 = h[0] ? h[1] : nullptr;
+    V.xprev3 = V.xprev2 ? h[2] : nullptr;
+    V.ex1 = V.xprev3 ? 3.f : (V.xprev2 ? 2.f : 1.f);
+    V.ex2 = V.xprev3 ? -3.f : (V.xprev2 ? -1.f : 0.f);
+    V.ex3 = V.xprev3 ? 1.f : 0.f;
     const StepResult r = run_step<float>(S, V, m.y, sh);
     if (m.y == 0 && threadIdx.x == 0) {
       const int slot = (fwd ? 0 : J.nsteps) + n - 1;
@@ -202,7 +212,7 @@ void job_geom(int nx, int ny, int nz, int cap, nh::Geom& g, int& team) {
 size_t job_bytes(int nx, int ny, int nz, int nsteps, int team) {
   const size_t ng = (size_t)nx * ny * nz, nxy = (size_t)nx * ny, N = (size_t)nsteps;
   size_t b = 0;
-  b += align256(4 * ng) * 9;                                // alpha, z, p, u1, w0, w1, s0, s1, mu
+  b += align256(4 * ng) * 12;                               // alpha, z, p, u1, w0, w1, s0, s1, mu[4]
   b += align256(4 * ng * N);                                // trajectory T^1..T^N
   b += align256(8 * ng);                                    // dL/dalpha (FP64)
   b += align256(4 * nxy) + 3 * align256(4 * nxy * N);       // q_xy, target, S, dL/dS
@@ -225,7 +235,7 @@ struct SJob {
   size_t bytes = 0;
   void* mem = nullptr;
   float *alpha = nullptr, *qxy = nullptr, *target = nullptr, *traj = nullptr, *z = nullptr, *p0 = nullptr,
-        *u1 = nullptr, *w0 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr, *mu = nullptr,
+        *u1 = nullptr, *w0 = nullptr, *w1 = nullptr, *s0 = nullptr, *s1 = nullptr, *mu[4] = {},
         *surf = nullptr, *gsurf = nullptr, *qscale = nullptr;
   double *G = nullptr, *partial = nullptr, *lossbuf = nullptr, *rel_out = nullptr;
   void* slots = nullptr;
@@ -307,7 +317,7 @@ nh_status admit(nh_server* s, SJob* j) {
   j->w1 = (float*)take(4 * ng);
   j->s0 = (float*)take(4 * ng);
   j->s1 = (float*)take(4 * ng);
-  j->mu = (float*)take(4 * ng);
+  for (float*& m : j->mu) m = (float*)take(4 * ng);
   j->traj = (float*)take(4 * ng * N);
   j->G = (double*)take(8 * ng);
   j->qxy = (float*)take(4 * nxy);
@@ -328,7 +338,6 @@ nh_status admit(nh_server* s, SJob* j) {
   SV_HIP(s, hipMemcpyAsync(j->qscale, j->h_qscale.data(), 4 * N, hipMemcpyHostToDevice, s->stream));
   SV_HIP(s, hipMemsetAsync(j->slots, 0, sizeof(nh::Slot) * ((size_t)j->team + 1), s->stream));
   const int blocks = (int)std::min<size_t>((ng + 255) / 256, 2048);
-  hipLaunchKernelGGL(nh::fill_kernel<float>, dim3(blocks), dim3(256), 0, s->stream, j->mu, (long long)ng, 0.f);
   hipLaunchKernelGGL(nh::fill_kernel<double>, dim3(blocks), dim3(256), 0, s->stream, j->G, (long long)ng, 0.0);
   SV_HIP(s, hipGetLastError());
   j->state = NH_JOB_FORWARD;
@@ -375,10 +384,10 @@ void job_run(const nh_server* s, const SJob* j, unsigned long long epoch_base, n
     S.top_src = j->qxy;
   } else {
     S.mode = nh::kAdjoint;
-    S.x = j->mu;
     S.top_scale = 1.f;
     S.G = j->G;
   }
+  for (int k = 0; k < 4; ++k) J.mu[k] = j->mu[k];
   J.qscale = j->qscale;
   J.traj = j->traj;
   J.surf = j->surf;

@@ -45,14 +45,17 @@ class Solver:
     recomputes segments in the adjoint; 0 keeps all states. ``cg_variant``
     selects the CG form: 0 two reductions per iteration, 1 one reduction
     (streaming kernel), 2 one reduction with the register-resident kernel
-    where the grid fits on the chip, else as 1.
+    where the grid fits on the chip, else as 1. ``initial_guess`` is the CG
+    starting point of each solve: ``"extrapolate"`` from the last three
+    states, or ``"previous"`` state alone.
     """
 
     def __init__(self, nx: int, ny: int, nz: int, h: Sequence[float] = (1.0, 1.0, 1.0),
                  rtol: float = 1e-6, max_iter: int = 1000, checkpoint_every: int = 0,
                  precision: str = "f32", device: Optional[int] = None,
                  stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
-                 tile_z: int = 0, profile: bool = False, cg_variant: int = 2):
+                 tile_z: int = 0, profile: bool = False, cg_variant: int = 2,
+                 initial_guess: str = "extrapolate"):
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.lib = _lib.load()
@@ -68,6 +71,7 @@ class Solver:
         _check(self.lib.nh_set_grid(self._ctx, self.nx, self.ny, self.nz, *self.h), self._ctx,
                "nh_set_grid")
         self.set_cg_variant(cg_variant)
+        self.set_initial_guess(initial_guess)
         self.set_solver(rtol, max_iter, checkpoint_every)
         if team_blocks_max or tile_z or profile:
             self.set_launch(team_blocks_max, tile_z, profile)
@@ -88,6 +92,14 @@ class Solver:
     def set_cg_variant(self, variant: int):
         _check(self.lib.nh_set_cg_variant(self._ctx, int(variant)), self._ctx, "nh_set_cg_variant")
         self.cg_variant = int(variant)
+
+    def set_initial_guess(self, mode: str):
+        """``"extrapolate"`` (from the last three states) or ``"previous"`` (the last state)."""
+        modes = {"previous": 0, "extrapolate": 1}
+        if mode not in modes:
+            raise ValueError(f"initial_guess must be one of {sorted(modes)}")
+        _check(self.lib.nh_set_initial_guess(self._ctx, modes[mode]), self._ctx, "nh_set_initial_guess")
+        self.initial_guess = mode
 
     def set_barrier_timeout(self, seconds: float):
         _check(self.lib.nh_set_barrier_timeout(self._ctx, float(seconds)), self._ctx,

@@ -39,13 +39,14 @@ def to_dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
-def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=2):
+def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=2,
+            guess="extrapolate"):
     """Forward (and adjoint when gs is given) of workload w on the GPU."""
     prec = precision or w.precision
     dt_t = torch.float32 if prec == "f32" else torch.float64
     s = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=rtol or w.rtol, max_iter=5000,
                checkpoint_every=checkpoint_every, precision=prec, team_blocks_max=team, tile_z=tile_z,
-               cg_variant=variant)
+               cg_variant=variant, initial_guess=guess)
     S = s.forward(to_dev(w.alpha, dt_t), to_dev(w.q_xy, dt_t), w.q_t, w.dt, w.nsteps)
     out = dict(S=S.cpu().numpy().astype(np.float64), stats_fwd=s.stats(), solver=s)
     if gs is not None:
@@ -146,6 +147,23 @@ def test_mixed_64x64x32_forward_and_adjoint(mixed_ref, variant):
     assert eg <= 1e-4
 
 
+@pytest.mark.timeout(600)
+def test_initial_guess_modes(mixed_ref):
+    """Both CG starting points reach the tolerance; the extrapolated one in
+    fewer iterations on this smooth trajectory."""
+    w, ref = mixed_ref
+    its = {}
+    for guess in ("previous", "extrapolate"):
+        out = run_gpu(w, gs=ref["gs"].astype(np.float32), guess=guess)
+        es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
+        its[guess] = (out["stats_fwd"]["fwd_iters"], out["stats_adj"]["adj_iters"])
+        say("  guess", guess, "rel-L2 S", es, "G", eg, "iters", its[guess])
+        assert es <= 1e-5
+        assert eg <= 1e-4
+    assert its["extrapolate"][0] < its["previous"][0]
+    assert its["extrapolate"][1] < its["previous"][1]
+
+
 # ------------------------------------------------------------------ checkpointing, determinism
 @pytest.mark.parametrize("variant", [2, 1, 0])
 def test_checkpoint_recompute_is_bitwise(variant):
@@ -154,7 +172,7 @@ def test_checkpoint_recompute_is_bitwise(variant):
     say("checkpoint full")
     team, tz = (0, 0) if variant == 2 else (4, 3)
     full = run_gpu(w, gs=gs, team=team, tile_z=tz, variant=variant)
-    for k in (1, 7, 64):
+    for k in (1, 2, 3, 7, 64):
         say("checkpoint k", k)
         ck = run_gpu(w, gs=gs, checkpoint_every=k, team=team, tile_z=tz, variant=variant)
         assert np.array_equal(ck["S"], full["S"])

@@ -101,7 +101,7 @@ def test_job_bytes(lib):
             team = lib.nh_serve_job_team(nx, ny, nz, 256)
             b = lib.nh_serve_job_bytes(nx, ny, nz, ns, team)
             ng, nxy = nx * ny * nz, nx * ny
-            floor = 4 * ng * (9 + ns) + 8 * ng + 4 * nxy * (1 + 3 * ns)
+            floor = 4 * ng * (12 + ns) + 8 * ng + 4 * nxy * (1 + 3 * ns)
             assert floor <= b <= floor + 64 * 1024 + 256 * 30
     # monotone in the number of steps
     assert lib.nh_serve_job_bytes(64, 64, 32, 300, 4) > lib.nh_serve_job_bytes(64, 64, 32, 100, 4)
