@@ -167,6 +167,12 @@ nh_status nh_set_barrier_timeout(nh_ctx *ctx, double seconds);
 
 nh_status nh_get_stats(const nh_ctx *ctx, nh_stats *out);
 
+/* CG iterations of every step of the last sweep of one kind, to HOST
+ * iters[nsteps] (entry n-1 = step n): sweep 0 forward, 1 adjoint, 2 forward
+ * steps recomputed from checkpoints (zeros without checkpointing). Entries of
+ * a sweep not yet run since the last forward are stale. */
+nh_status nh_get_step_iters(const nh_ctx *ctx, int sweep, int *iters);
+
 /* Text of the last error of this context (never NULL). */
 const char *nh_last_error(const nh_ctx *ctx);
 

@@ -872,6 +872,19 @@ nh_status nh_set_cg_variant(nh_ctx* c, int variant) {
   return NH_OK;
 }
 
+nh_status nh_get_step_iters(const nh_ctx* c, int sweep, int* iters) {
+  if (!c) return NH_EINVAL;
+  nh_ctx* m = const_cast<nh_ctx*>(c);
+  if (!iters) return fail(m, NH_EINVAL, "null pointer argument");
+  if (sweep < 0 || sweep > 2) return fail(m, NH_EINVAL, "sweep must be 0, 1 or 2");
+  if (!c->saved_prec || !c->steps.p) return fail(m, NH_ESTATE, "no saved forward");
+  const int N = c->saved_nsteps;
+  NH_HIP(m, hipMemcpyAsync(iters, step_out(m, sweep, 0).iters, sizeof(int) * (size_t)N, hipMemcpyDeviceToHost,
+                           c->stream));
+  NH_HIP(m, hipStreamSynchronize(c->stream));
+  return NH_OK;
+}
+
 nh_status nh_set_initial_guess(nh_ctx* c, int mode) {
   if (!c) return NH_EINVAL;
   if (mode < 0 || mode > 1) return fail(c, NH_EINVAL, "initial guess mode must be 0 or 1");

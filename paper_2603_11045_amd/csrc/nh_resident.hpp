@@ -32,6 +32,7 @@ __device__ __forceinline__ void st_dev(float* p, float v) {
 __device__ __forceinline__ float ld_dev(const float* p) {
   return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+constexpr int kCpolSc1 = 16;                // cache policy of a device-coherent load (sc1), as ld_dev
 
 struct ResRed {
   double red[kMaxWaves][kNumRed];
@@ -42,7 +43,7 @@ struct ResRed {
 // LDS layout of the resident kernel (bytes).
 constexpr size_t kResAlphaFloats = (size_t)(kResTZ + 2) * kResPlane;   // alpha tile + halos
 constexpr size_t kResPlaneFloats = 4 * (size_t)kResPlane;              // [2 vectors][2 buffers]
-constexpr size_t kResRingFloats = 2 * (size_t)kResTZ * kRing;          // [2 vectors][TZ][ring]
+constexpr size_t kResRingFloats = 3 * (size_t)kResTZ * kRing;          // [3 vectors][TZ][ring]
 constexpr size_t kResLdsBytes =
     (kResAlphaFloats + kResPlaneFloats + kResRingFloats) * sizeof(float) + sizeof(ResRed) + 64;
 
@@ -218,9 +219,9 @@ __device__ __forceinline__ float apply_at(const Nb& n, float v, const float* pl,
 // Plane-by-plane sweep over the tile for NV staged vectors. own(k, z) gives
 // the thread's own value of vector k at plane z, ring[k] the LDS ring buffers,
 // zlo/zhi the values below and above the tile; cell(z, plane pointers) does the work.
-template <class G, int NV, typename OwnF, typename CellF>
-__device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, float* lp, const float* ring,
-                                            OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
+template <class G, int NV, typename OwnF, typename RingF, typename CellF>
+__device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, float* lp, RingF ringv,
+                                              OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
   // ring cells handled by this thread for the plane copy
   const int h = threadIdx.x;
   bool hin = false;
@@ -236,7 +237,7 @@ __device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, floa
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         pl[k][q.oslot] = q.own ? own(k, z) : 0.f;
-        if (hslot >= 0) pl[k][hslot] = ring[(size_t)k * kResTZ * kRing + z * kRing + h];
+        if (hslot >= 0) pl[k][hslot] = ringv(k, z * kRing + h);
       }
       __syncthreads();
       if (q.own) {
@@ -251,6 +252,40 @@ __device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, floa
     }
   }
   __syncthreads();
+}
+
+// Plane sweep whose halo ring values are stored in LDS, [NV][TZ][kRing].
+template <class G, int NV, typename OwnF, typename CellF>
+__device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, float* lp, const float* ring,
+                                            OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
+  plane_sweep_r<G, NV>(g, q, lp, [&](int k, int o) { return ring[(size_t)k * kResTZ * kRing + o]; }, own, zlo,
+                       zhi, cell);
+}
+
+// Start copying src's values at the tile's ring cells into an LDS ring
+// ([TZ][kRing]) with direct global-to-LDS loads (device-coherent), without
+// waiting: each wave writes 64 consecutive ring slots per load, so ring slot
+// = element index, which holds when the ring has exactly kRing cells. Ring
+// cells outside the grid are not loaded and must hold zeros already.
+template <class G>
+__device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* ring, const float* src, int tid,
+                                         int nxy) {
+  static_assert(G::RING == kRing, "ring slots must equal ring cells");
+  constexpr int kMaxPer = (G::RING * kResTZ + kResBlock - 1) / kResBlock;
+  const int n = G::RING * q.tzn;
+#pragma unroll
+  for (int k = 0; k < kMaxPer; ++k) {
+    const int e = tid + k * kResBlock;
+    if (e < n) {
+      const int z = e / G::RING, h = e - z * G::RING;
+      bool in;
+      int hcol, hslot;
+      ring_cell<G>(g, q, h, in, hcol, hslot);
+      if (in)
+        __builtin_amdgcn_global_load_lds(src + hcol + (q.z0 + z) * nxy,
+                                         ring + (tid & ~63) + k * kResBlock, 4, 0, kCpolSc1);
+    }
+  }
 }
 
 template <int TXC>
@@ -307,6 +342,10 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
       la[e] = a;
     }
   }
+
+  // rings 1 and 2 receive only in-grid values by direct loads: their other
+  // slots stay zero (ring 0 is fully rewritten by the set-up's fill)
+  for (int e = threadIdx.x; e < 2 * kResTZ * kRing; e += kResBlock) lring[kResTZ * kRing + e] = 0.f;
 
   float pr[TZ], ur[TZ], wr[TZ], sr[TZ];
 #pragma unroll
@@ -416,6 +455,30 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
       asm volatile("" : "+v"(col_l));
       const float a = (float)a_cg, b = (float)b_cg;
       const bool first = it == 0;
+      // the neighbours' published u, w/D, s/D on the tile's ring start
+      // streaming into LDS now and land while the registers are updated
+      const float* uo = ub[cur];
+      const float* wo = wb[cur];
+      const float* so = sb[cur];
+      float* ring_u = lring;
+      float* ring_w = lring + kResTZ * kRing;
+      float* ring_s = lring + 2 * kResTZ * kRing;
+      // (the thread index is laundered so that the ring addressing is
+      // recomputed here rather than hoisted out of the loop into registers)
+      int tid_l = threadIdx.x;
+      asm volatile("" : "+v"(tid_l));
+      ring_dma<G>(g, q, ring_u, uo, tid_l, nxy_l);
+      ring_dma<G>(g, q, ring_w, wo, tid_l, nxy_l);
+      if (!first) ring_dma<G>(g, q, ring_s, so, tid_l, nxy_l);
+      float zl[3] = {0.f, 0.f, 0.f}, zh[3] = {0.f, 0.f, 0.f};
+      if (q.own && q.bot_z) {
+        const int i = col_l + (T.z0 - 1) * nxy_l;
+        zl[0] = ld_dev(uo + i); zl[1] = ld_dev(wo + i); zl[2] = first ? 0.f : ld_dev(so + i);
+      }
+      if (q.own && q.top_z) {
+        const int i = col_l + T.z1 * nxy_l;
+        zh[0] = ld_dev(uo + i); zh[1] = ld_dev(wo + i); zh[2] = first ? 0.f : ld_dev(so + i);
+      }
       // elementwise updates: s = w + b s, p = u + b p, u -= a s in registers.
       // x (in memory) is advanced every second iteration by both pending
       // steps, x += a_prev p_prev + a p, which halves its traffic.
@@ -434,21 +497,18 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
       }
       a_prev = a;
       // halo values of the new u from the neighbours' published u, w/D, s/D
-      const float* uo = ub[cur];
-      const float* wo = wb[cur];
-      const float* so = sb[cur];
-      auto unew = [&](int i) {
-        const float s_ = first ? ld_dev(wo + i) : fmaf(b, ld_dev(so + i), ld_dev(wo + i));
-        return fmaf(-a, s_, ld_dev(uo + i));
-      };
-      if (q.own && q.bot_z) zlo[0] = unew(col_l + (T.z0 - 1) * nxy_l);
-      if (q.own && q.top_z) zhi[0] = unew(col_l + T.z1 * nxy_l);
+      auto unew = [&](float u_, float w_, float s_) { return fmaf(-a, first ? w_ : fmaf(b, s_, w_), u_); };
+      zlo[0] = unew(zl[0], zl[1], zl[2]);
+      zhi[0] = unew(zh[0], zh[1], zh[2]);
       if (S.trace_detail) stamp();
-      fill_ring<G>(g, q, lring, unew);
+      __builtin_amdgcn_s_waitcnt(0);        // the ring loads have reached LDS
+      __syncthreads();
+      // the ring's new u, in place
+      for (int e = tid_l; e < G::RING * q.tzn; e += kResBlock) ring_u[e] = unew(ring_u[e], ring_w[e], ring_s[e]);
       __syncthreads();
       if (S.trace_detail) stamp();
       double acc[3] = {0.0, 0.0, 0.0};
-      plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
+      plane_sweep<G, 1>(g, q, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
                      [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                        const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                        const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);

@@ -164,6 +164,15 @@ class Solver:
         _check(self.lib.nh_get_stats(self._ctx, ctypes.byref(s)), self._ctx, "nh_get_stats")
         return s.as_dict()
 
+    def step_iters(self, sweep: str = "forward") -> np.ndarray:
+        """CG iterations per step of the last ``"forward"``, ``"adjoint"`` or
+        ``"recompute"`` sweep (entry n-1 = step n)."""
+        kinds = {"forward": 0, "adjoint": 1, "recompute": 2}
+        out = np.zeros(self.nsteps, dtype=np.int32)
+        _check(self.lib.nh_get_step_iters(self._ctx, kinds[sweep], out.ctypes.data), self._ctx,
+               "nh_get_step_iters")
+        return out
+
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self.lib.nh_destroy(self._ctx)
