@@ -252,9 +252,13 @@ typedef struct {
 
 /* Create a server on `hip_device` working on `hip_stream` (NULL = the null
  * stream). hbm_budget_bytes bounds the device bytes of admitted jobs;
- * max_blocks > 0 lowers the workgroup limit (0 = all that fit co-resident). */
+ * max_blocks > 0 lowers the workgroup limit (0 = all that fit co-resident).
+ * resident = 1 runs the jobs with the register-resident step (one 512-thread
+ * workgroup per tile of 64 x 8 x <= 32 cells, so a job holds about one CU
+ * per 16384 cells, at most all of them); resident = 0 with the streaming
+ * step (1024-thread workgroups, about 32768 cells each). */
 nh_status nh_server_create(nh_server **out, int hip_device, void *hip_stream, double hbm_budget_bytes,
-                           int max_blocks);
+                           int max_blocks, int resident);
 
 /* Slice budget of a tick: about `iters` CG iterations of a workgroup that
  * holds 32768 voxels (smaller tiles run proportionally more; default 128).
@@ -299,9 +303,11 @@ void nh_server_destroy(nh_server *s);
 
 /* Host-only helpers of the admission policy (no device needed). */
 
-/* Workgroups of a job's team: one tile of at most about 32768 voxels per
- * workgroup, at most max_blocks / 2 workgroups (0 on bad arguments). */
-int nh_serve_job_team(int nx, int ny, int nz, int max_blocks);
+/* Workgroups of a job's team. resident = 1: one per 64 x 8 x (<= 32) tile
+ * (0 if that exceeds max_blocks); resident = 0: one tile of at most about
+ * 32768 voxels per workgroup, at most max_blocks / 2 workgroups. 0 on bad
+ * arguments. */
+int nh_serve_job_team(int nx, int ny, int nz, int max_blocks, int resident);
 
 /* Device bytes a job holds while admitted (0 on bad arguments). */
 size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks);

@@ -149,7 +149,7 @@ def load():
     lib.nh_destroy.restype = None
     lib.nh_copy_f32.argtypes = [vp, vp, ctypes.c_size_t, vp]
     llp = ctypes.POINTER(ctypes.c_longlong)
-    lib.nh_server_create.argtypes = [ctypes.POINTER(vp), ip, vp, dp, ip]
+    lib.nh_server_create.argtypes = [ctypes.POINTER(vp), ip, vp, dp, ip, ip]
     lib.nh_server_submit.argtypes = [vp, ip, ip, ip, dp, dp, ip, dp, ip, vp, vp, vp, vp, llp]
     lib.nh_server_tick.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), llp, ip, ctypes.POINTER(ip)]
     lib.nh_server_job.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(nh_job_info), vp]
@@ -160,7 +160,7 @@ def load():
     lib.nh_server_last_error.restype = ctypes.c_char_p
     lib.nh_server_destroy.argtypes = [vp]
     lib.nh_server_destroy.restype = None
-    lib.nh_serve_job_team.argtypes = [ip, ip, ip, ip]
+    lib.nh_serve_job_team.argtypes = [ip, ip, ip, ip, ip]
     lib.nh_serve_job_team.restype = ip
     lib.nh_serve_job_bytes.argtypes = [ip, ip, ip, ip, ip]
     lib.nh_serve_job_bytes.restype = ctypes.c_size_t

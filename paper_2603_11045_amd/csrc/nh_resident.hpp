@@ -130,6 +130,7 @@ struct RG {
 
 // Where one thread of the resident workgroup sits in its tile.
 struct ResPos {
+  int tid;                                  // thread index (laundered by the caller)
   int tx, ty;
   int x0, y0, z0, tzn;
   int gx, gy;
@@ -165,7 +166,7 @@ __device__ __forceinline__ void fill_ring(const Geom& g, const ResPos& q, float*
   int slot[kMaxPer];
 #pragma unroll
   for (int k = 0; k < kMaxPer; ++k) {
-    const int e = threadIdx.x + k * kResBlock;
+    const int e = q.tid + k * kResBlock;
     v[k] = 0.f;
     slot[k] = -1;
     if (e < n) {
@@ -223,7 +224,7 @@ template <class G, int NV, typename OwnF, typename RingF, typename CellF>
 __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, float* lp, RingF ringv,
                                               OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
   // ring cells handled by this thread for the plane copy
-  const int h = threadIdx.x;
+  const int h = q.tid;
   bool hin = false;
   int hcol = 0;
   int hslot = -1;
@@ -288,24 +289,31 @@ __device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* 
   }
 }
 
+// One implicit-Euler step of one team with the tile's CG state in registers
+// (dsm: the dynamic LDS of kResLdsBytes). Per-step fields come from V.
 template <int TXC>
-__global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<float> S) {
+__device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, const StepVar<float>& V, int rank,
+                                    unsigned char* dsm) {
   using G = RG<TXC>;
   constexpr int TZ = kResTZ;
-  extern __shared__ __align__(16) unsigned char dsm[];
   float* la = (float*)dsm;
   float* lp = la + kResAlphaFloats;
   float* lring = lp + kResPlaneFloats;
   ResRed* rs = (ResRed*)(lring + kResRingFloats);
 
   const Geom& g = S.g;
-  const int rank = blockIdx.x;
-  const int tile = first_tile(rank, S.team, S.xcd_order);
+  // a caller that loops over steps must not keep the tile geometry of one
+  // step live into the next: the laundered indices make it per-step values
+  int rank_l = rank, tid0 = threadIdx.x;
+  asm volatile("" : "+s"(rank_l));
+  asm volatile("" : "+v"(tid0));
+  const int tile = first_tile(rank_l, S.team, S.xcd_order);
   const Tile T = tile_of(g, tile);
 
   ResPos q;
-  q.tx = threadIdx.x % G::TX;
-  q.ty = threadIdx.x / G::TX;
+  q.tid = tid0;
+  q.tx = tid0 % G::TX;
+  q.ty = tid0 / G::TX;
   q.x0 = T.x0; q.y0 = T.y0; q.z0 = T.z0;
   q.tzn = T.z1 - T.z0;
   q.gx = T.x0 + q.tx;
@@ -319,7 +327,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
   const float sx = S.sx, sy = S.sy, sz = S.sz;
   const int nxy = (int)g.nxy;
 
-  unsigned long long red = S.epoch_base;
+  unsigned long long red = V.epoch_base;
   bool ok = true;
   int ntr = 0;
   const bool tr = S.trace && (rank == S.trace_rank || S.trace_rank < 0) && threadIdx.x == 0;
@@ -332,7 +340,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
   // alpha tile with halos: planes z0-1 .. z0+tzn, each (TX+2) x (TY+2)
   {
     const int n = (q.tzn + 2) * G::PL;
-    for (int e = threadIdx.x; e < n; e += kResBlock) {
+    for (int e = tid0; e < n; e += kResBlock) {
       const int lz = e / G::PL, rem = e - lz * G::PL;
       const int ly = rem / G::PW, lx = rem - ly * G::PW;
       const int gz = T.z0 - 1 + lz, gxx = T.x0 - 1 + lx, gyy = T.y0 - 1 + ly;
@@ -345,7 +353,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
 
   // rings 1 and 2 receive only in-grid values by direct loads: their other
   // slots stay zero (ring 0 is fully rewritten by the set-up's fill)
-  for (int e = threadIdx.x; e < 2 * kResTZ * kRing; e += kResBlock) lring[kResTZ * kRing + e] = 0.f;
+  for (int e = tid0; e < 2 * kResTZ * kRing; e += kResBlock) lring[kResTZ * kRing + e] = 0.f;
 
   float pr[TZ], ur[TZ], wr[TZ], sr[TZ];
 #pragma unroll
@@ -354,24 +362,24 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
 
   // ---------------- set-up: x0, b, r = b - A x0, u = r / D; x = x0 in memory
   // x0 = h1 (the previous state), or its extrapolation ex1 h1 + ex2 h2 + ex3 h3
-  const float* x0src = S.xprev;
-  const float* h2 = x0src ? S.xprev2 : nullptr;
-  const float* h3 = h2 ? S.xprev3 : nullptr;
+  const float* x0src = V.xprev;
+  const float* h2 = x0src ? V.xprev2 : nullptr;
+  const float* h3 = h2 ? V.xprev3 : nullptr;
   auto x0_at = [&](int i) -> float {
     if (!h2) return x0src[i];
-    float v = S.ex2 * h2[i];
-    if (h3) v = fmaf(S.ex3, h3[i], v);
-    return fmaf(S.ex1, x0src[i], v);
+    float v = V.ex2 * h2[i];
+    if (h3) v = fmaf(V.ex3, h3[i], v);
+    return fmaf(V.ex1, x0src[i], v);
   };
   if (q.own && x0src) {
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
       if (z < q.tzn) xr[z] = x0_at(q.col + (T.z0 + z) * nxy);
   }
-  if (q.own && x0src != S.x) {
+  if (q.own && x0src != V.x) {
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
-      if (z < q.tzn) S.x[q.col + (T.z0 + z) * nxy] = xr[z];
+      if (z < q.tzn) V.x[q.col + (T.z0 + z) * nxy] = xr[z];
   }
   float zlo[2] = {0.f, 0.f}, zhi[2] = {0.f, 0.f};
   if (x0src) {
@@ -388,7 +396,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
                    const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                    const float Av = apply_at(n, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                    float b = h2 ? x0src[q.col + (T.z0 + z) * nxy] : xr[z];
-                   if (T.z0 + z == 0) b += S.top_scale * S.top_src[q.col];
+                   if (T.z0 + z == 0) b += V.top_scale * V.top_src[q.col];
                    const float r = b - Av;
                    const float u = r * rcp<float>(n.D);
                    ur[z] = u;
@@ -417,7 +425,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
     if (q.own) {
 #pragma unroll
       for (int z = 0; z < TZ; ++z)
-        if (z < q.tzn) S.x[q.col + (T.z0 + z) * nxy] = 0.f;
+        if (z < q.tzn) V.x[q.col + (T.z0 + z) * nxy] = 0.f;
     }
     rr = 0.0;
   } else if (ok && rr > S.rtol2 * bb) {
@@ -488,7 +496,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
         const float s_ = first ? wr[z] : fmaf(b, sr[z], wr[z]);
         const float p_ = first ? ur[z] : fmaf(b, pr[z], ur[z]);
         if (xstep && q.own && z < q.tzn) {
-          float* xp = S.x + col_l + (T.z0 + z) * nxy_l;
+          float* xp = V.x + col_l + (T.z0 + z) * nxy_l;
           *xp = fmaf(a, p_, fmaf(a_prev, pr[z], *xp));
         }
         pr[z] = p_;
@@ -548,7 +556,7 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
 #pragma unroll
       for (int z = 0; z < TZ; ++z) {
         if (z < q.tzn) {
-          float* xp = S.x + q.col + (T.z0 + z) * nxy;
+          float* xp = V.x + q.col + (T.z0 + z) * nxy;
           *xp = fmaf(a_prev, pr[z], *xp);
         }
       }
@@ -560,15 +568,15 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
   // ---------------- epilogue: surface frame, checkpoint copy; for the gradient
   // the final x on the tile's faces is republished with device-scope stores
   if (q.own) {
-    if (S.mode == kForward && S.surf_out && T.z0 == 0) S.surf_out[q.col] = S.x[q.col];
-    if (S.ckpt_out) {
+    if (S.mode == kForward && V.surf_out && T.z0 == 0) V.surf_out[q.col] = V.x[q.col];
+    if (V.ckpt_out) {
       for (int z = 0; z < q.tzn; ++z) {
         const int i = q.col + (T.z0 + z) * nxy;
-        S.ckpt_out[i] = S.x[i];
+        V.ckpt_out[i] = V.x[i];
       }
     }
   }
-  if (S.mode == kAdjoint && S.T_grad && ok) {
+  if (S.mode == kAdjoint && V.T_grad && ok) {
     // gradient: G_p -= sum_f s_f (a_q/(a_p+a_q))^2 (T_p-T_q)(mu_p-mu_q)
     float (&mcol)[TZ] = ur;                 // the solve is over: mu and T columns reuse u and p
     float (&tcol)[TZ] = pr;
@@ -576,24 +584,24 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
     for (int z = 0; z < TZ; ++z) {
       const bool in = q.own && z < q.tzn;
       const int i = q.col + (T.z0 + z) * nxy;
-      mcol[z] = in ? S.x[i] : 0.f;
-      tcol[z] = in ? S.T_grad[i] : 0.f;
-      if (in && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(S.x + i, mcol[z]);
+      mcol[z] = in ? V.x[i] : 0.f;
+      tcol[z] = in ? V.T_grad[i] : 0.f;
+      if (in && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(V.x + i, mcol[z]);
     }
     double dummy[1] = {0.0};
     ok &= team_sum_dev<1>(S, rank, red, dummy, rs);
     float* ring_mu = lring;
     float* ring_T = lring + (size_t)kResTZ * kRing;
-    fill_ring<G>(g, q, ring_mu, [&](int i) { return ld_dev(S.x + i); });
-    fill_ring<G>(g, q, ring_T, [&](int i) { return S.T_grad[i]; });
+    fill_ring<G>(g, q, ring_mu, [&](int i) { return ld_dev(V.x + i); });
+    fill_ring<G>(g, q, ring_T, [&](int i) { return V.T_grad[i]; });
     float glo[2] = {0.f, 0.f}, ghi[2] = {0.f, 0.f};
     if (q.own && q.bot_z) {
-      glo[0] = ld_dev(S.x + q.col + (T.z0 - 1) * nxy);
-      glo[1] = S.T_grad[q.col + (T.z0 - 1) * nxy];
+      glo[0] = ld_dev(V.x + q.col + (T.z0 - 1) * nxy);
+      glo[1] = V.T_grad[q.col + (T.z0 - 1) * nxy];
     }
     if (q.own && q.top_z) {
-      ghi[0] = ld_dev(S.x + q.col + T.z1 * nxy);
-      ghi[1] = S.T_grad[q.col + T.z1 * nxy];
+      ghi[0] = ld_dev(V.x + q.col + T.z1 * nxy);
+      ghi[1] = V.T_grad[q.col + T.z1 * nxy];
     }
     __syncthreads();
     plane_sweep<G, 2>(g, q, lp, lring, [&](int k, int z) { return k == 0 ? mcol[z] : tcol[z]; }, glo, ghi,
@@ -623,11 +631,19 @@ __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<fl
                    });
   }
 
-  if (rank == 0 && threadIdx.x == 0) {
-    S.out_iters[0] = it;
-    S.out_relres[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    S.out_status[0] = status;
+  const double relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  if (V.out_iters && rank == 0 && threadIdx.x == 0) {
+    V.out_iters[0] = it;
+    V.out_relres[0] = relres;
+    V.out_status[0] = status;
   }
+  return StepResult{it, status, relres};
+}
+
+template <int TXC>
+__global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<float> S) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  resident_step<TXC>(S, step_var(S), blockIdx.x, dsm);
 }
 
 }  // namespace nh

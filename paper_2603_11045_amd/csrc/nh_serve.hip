@@ -3,8 +3,9 @@
 // A job is one reconstruction request: a diffusivity field, a source, and the
 // surface measurements it is compared with (mean squared error). The server
 // keeps every admitted job's state resident in HBM and advances all of them
-// together: each tick is ONE cooperative launch of nh::batch_run_kernel in
-// which every active job's team of workgroups runs implicit-Euler steps
+// together: each tick is ONE cooperative launch (nh::batch_resident_kernel,
+// or nh::batch_run_kernel with the streaming step code) in which every
+// active job's team of workgroups runs implicit-Euler steps
 // (forward, or adjoint after its forward has finished) with its own team
 // reductions -- the same step code as the single-problem path -- until its
 // CG iterations in this launch reach the tick's budget. Between ticks the host
@@ -16,6 +17,7 @@
 // bit-identical whether it runs alone or among others.
 #include "nefty_heat.h"
 #include "nh_kernels.hpp"
+#include "nh_resident.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -62,20 +64,15 @@ struct JobProg {
 
 constexpr int kMaxSliceSteps = 255;       // steps per slice: epoch bits 16..23 of a launch
 
-// Workgroup b works as rank map[b].y of job map[b].x. The step loop and its
-// exit test depend only on reduced values, so every workgroup of a team runs
-// the same steps (a barrier timeout aside, which every member then reaches
-// within its own bounded waits).
-__global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const JobRun* jobs, const int2* map,
-                                                                          JobProg* prog) {
-  __shared__ Smem<float> sh;
-  const int2 m = map[blockIdx.x];
-  if (m.x < 0) return;
-  // The job table is not written during the launch: reading it through the
-  // constant address space makes its loads scalar and invariant, so the
-  // compiler reloads fields instead of keeping the whole table live.
-  typedef __attribute__((address_space(4))) const JobRun CJobRun;
-  const CJobRun& J = *(const CJobRun*)(jobs + m.x);
+// The slice of one job for one workgroup: steps of the job until its
+// iterations in this launch reach the budget. `step(S, V)` runs one step of
+// the team. The loop and its exit test depend only on reduced values, so
+// every workgroup of a team runs the same steps (a barrier timeout aside,
+// which every member then reaches within its own bounded waits).
+typedef __attribute__((address_space(4))) const JobRun CJobRun;
+
+template <typename StepF>
+__device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* prog, StepF step) {
   const long long t0 = wall_clock64();
   const bool fwd = J.mode == kForward;
   int n = J.n0, steps = 0, status = 0;
@@ -113,7 +110,7 @@ __global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const 
     V.ex1 = V.xprev3 ? 3.f : (V.xprev2 ? 2.f : 1.f);
     V.ex2 = V.xprev3 ? -3.f : (V.xprev2 ? -1.f : 0.f);
     V.ex3 = V.xprev3 ? 1.f : 0.f;
-    const StepResult r = run_step<float>(S, V, m.y, sh);
+    const StepResult r = step(S, V);
     if (m.y == 0 && threadIdx.x == 0) {
       const int slot = (fwd ? 0 : J.nsteps) + n - 1;
       J.it_out[slot] = r.iters;
@@ -138,6 +135,34 @@ __global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const 
     p.t1 = wall_clock64();
     prog[m.x] = p;
   }
+}
+
+// Workgroup b works as rank map[b].y of job map[b].x (streaming step kernel
+// code: 1024-thread workgroups, tiles of 64 x 16 columns or narrower).
+__global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const JobRun* jobs, const int2* map,
+                                                                          JobProg* prog) {
+  __shared__ Smem<float> sh;
+  const int2 m = map[blockIdx.x];
+  if (m.x < 0) return;
+  // The job table is not written during the launch: reading it through the
+  // constant address space makes its loads scalar and invariant.
+  const CJobRun& J = *(const CJobRun*)(jobs + m.x);
+  run_slice(J, m, prog, [&](const StepArgs<float>& S, const StepVar<float>& V) {
+    return run_step<float>(S, V, m.y, sh);
+  });
+}
+
+// The same with the register-resident step: 512-thread workgroups, one tile
+// of 64 x 8 x (<= 32) cells each, the tile's CG state in registers.
+__global__ void __launch_bounds__(kResBlock, 1) batch_resident_kernel(const JobRun* jobs, const int2* map,
+                                                                       JobProg* prog) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int2 m = map[blockIdx.x];
+  if (m.x < 0) return;
+  const CJobRun& J = *(const CJobRun*)(jobs + m.x);
+  run_slice(J, m, prog, [&](const StepArgs<float>& S, const StepVar<float>& V) {
+    return resident_step<64>(S, V, m.y, dsm);
+  });
 }
 
 constexpr int kMseThreads = 256;
@@ -175,6 +200,8 @@ namespace {
 constexpr int kMseBlocks = 64;
 constexpr long long kVoxelsPerBlock = 32768;
 constexpr long long kReductionCost = 8192;   // a team reduction, in voxel units of work
+constexpr long long kResCells = 16384;        // cells of a full resident tile
+constexpr long long kResFixedCost = 24576;    // per resident iteration: reduction and face exchange
 constexpr int kMaxIterLimit = 30000;          // reductions per step stay below 2^16
 constexpr int kBlock = nh::Cfg<float>::kBlock;
 
@@ -207,6 +234,24 @@ void job_geom(int nx, int ny, int nz, int cap, nh::Geom& g, int& team) {
   g.ntz = (nz + tz - 1) / tz;
   g.ntiles = (int)(xy * g.ntz);
   team = std::max(1, std::min(g.ntiles, cap));
+}
+
+// Tiling of one job for the register-resident kernel: tiles of 64 x 8
+// columns and at most 32 cells in z, one workgroup per tile.
+void job_geom_res(int nx, int ny, int nz, nh::Geom& g, int& team) {
+  g = nh::Geom{};
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.nxy = (long long)nx * ny;
+  g.ng = g.nxy * nz;
+  g.TX = 64;
+  g.TY = nh::kResBlock / 64;
+  g.txs = 6;
+  g.ntx = (nx + g.TX - 1) / g.TX;
+  g.nty = (ny + g.TY - 1) / g.TY;
+  g.ntz = (nz + nh::kResTZ - 1) / nh::kResTZ;
+  g.TZ = (nz + g.ntz - 1) / g.ntz;
+  g.ntiles = (int)((long long)g.ntx * g.nty * g.ntz);
+  team = g.ntiles;
 }
 
 size_t job_bytes(int nx, int ny, int nz, int nsteps, int team) {
@@ -256,6 +301,7 @@ struct nh_server {
   hipStream_t stream = nullptr;
   int num_cu = 0, max_blocks = 0;
   double budget = 0;
+  int resident = 1;        // 1: nh::batch_resident_kernel, 0: nh::batch_run_kernel
   int slice_iters = 128;
   int backfill_ticks = 64;
   size_t used_bytes = 0;
@@ -399,7 +445,7 @@ void job_run(const nh_server* s, const SJob* j, unsigned long long epoch_base, n
   J.n0 = j->step;
   J.nsteps = j->nsteps;
   J.cost = j->cost;
-  J.budget = (long long)s->slice_iters * (kVoxelsPerBlock + kReductionCost);
+  J.budget = (long long)s->slice_iters * (s->resident ? kResCells + kResFixedCost : kVoxelsPerBlock + kReductionCost);
 }
 
 nh_status ensure_tables(nh_server* s, size_t njobs) {
@@ -423,10 +469,14 @@ nh_status ensure_tables(nh_server* s, size_t njobs) {
 
 extern "C" {
 
-int nh_serve_job_team(int nx, int ny, int nz, int max_blocks) {
+int nh_serve_job_team(int nx, int ny, int nz, int max_blocks, int resident) {
   if (nx < 1 || ny < 1 || nz < 1 || max_blocks < 1) return 0;
   nh::Geom g;
   int team = 0;
+  if (resident) {
+    job_geom_res(nx, ny, nz, g, team);
+    return team <= max_blocks ? team : 0;
+  }
   job_geom(nx, ny, nz, std::max(1, max_blocks / 2), g, team);
   return team;
 }
@@ -455,10 +505,10 @@ int nh_serve_admit_select(const size_t* bytes, const int* teams, const int* wait
 }
 
 nh_status nh_server_create(nh_server** out, int hip_device, void* hip_stream, double hbm_budget_bytes,
-                           int max_blocks) {
+                           int max_blocks, int resident) {
   if (!out) return NH_EINVAL;
   *out = nullptr;
-  if (!(hbm_budget_bytes > 0) || max_blocks < 0) return NH_EINVAL;
+  if (!(hbm_budget_bytes > 0) || max_blocks < 0 || resident < 0 || resident > 1) return NH_EINVAL;
   now_s();
   std::unique_ptr<nh_server> s(new (std::nothrow) nh_server());
   if (!s) return NH_ENOMEM;
@@ -468,11 +518,20 @@ nh_status nh_server_create(nh_server** out, int hip_device, void* hip_stream, do
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return NH_EHIP;
   s->num_cu = prop.multiProcessorCount;
+  s->resident = resident;
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)nh::batch_run_kernel, kBlock, 0) !=
-          hipSuccess ||
-      occ < 1)
+  if (resident) {
+    if (hipFuncSetAttribute((const void*)nh::batch_resident_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)nh::kResLdsBytes) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)nh::batch_resident_kernel, nh::kResBlock,
+                                                     nh::kResLdsBytes) != hipSuccess ||
+        occ < 1)
+      return NH_EHIP;
+  } else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)nh::batch_run_kernel, kBlock, 0) !=
+                 hipSuccess ||
+             occ < 1) {
     return NH_EHIP;
+  }
   s->max_blocks = occ * s->num_cu;
   if (max_blocks > 0) s->max_blocks = std::min(s->max_blocks, max_blocks);
   s->budget = hbm_budget_bytes;
@@ -533,9 +592,15 @@ nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, doubl
   j->rtol = rtol;
   j->max_iter = max_iter;
   int team = 0;
-  job_geom(nx, ny, nz, std::max(1, s->max_blocks / 2), j->g, team);
+  if (s->resident) {
+    job_geom_res(nx, ny, nz, j->g, team);
+    if (team > s->max_blocks) return sfail(s, NH_EINVAL, "job needs more tiles than fit on the device");
+    j->cost = ((long long)ng + team - 1) / team + kResFixedCost;
+  } else {
+    job_geom(nx, ny, nz, std::max(1, s->max_blocks / 2), j->g, team);
+    j->cost = ((long long)ng + team - 1) / team + (team > 1 ? kReductionCost : 0);
+  }
   j->team = team;
-  j->cost = ((long long)ng + team - 1) / team + (team > 1 ? kReductionCost : 0);
   j->bytes = job_bytes(nx, ny, nz, nsteps, team);
   if ((double)j->bytes > s->budget) return sfail(s, NH_ENOMEM, "job larger than the HBM budget");
   j->h_alpha.assign(alpha, alpha + ng);
@@ -614,8 +679,12 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
     SV_HIP(s, hipMemcpyAsync(s->d_map, s->h_map, sizeof(int2) * nb, hipMemcpyHostToDevice, s->stream));
     void* args[] = {(void*)&s->d_runs, (void*)&s->d_map, (void*)&s->d_prog};
     SV_HIP(s, hipEventRecord(s->ev0, s->stream));
-    SV_HIP(s, hipLaunchCooperativeKernel((const void*)nh::batch_run_kernel, dim3((unsigned)nb), dim3(kBlock), args,
-                                         0, s->stream));
+    if (s->resident)
+      SV_HIP(s, hipLaunchCooperativeKernel((const void*)nh::batch_resident_kernel, dim3((unsigned)nb),
+                                           dim3(nh::kResBlock), args, (unsigned)nh::kResLdsBytes, s->stream));
+    else
+      SV_HIP(s, hipLaunchCooperativeKernel((const void*)nh::batch_run_kernel, dim3((unsigned)nb), dim3(kBlock),
+                                           args, 0, s->stream));
     SV_HIP(s, hipEventRecord(s->ev1, s->stream));
     SV_HIP(s, hipMemcpyAsync(s->h_prog, s->d_prog, sizeof(nh::JobProg) * na, hipMemcpyDeviceToHost, s->stream));
     SV_HIP(s, hipStreamSynchronize(s->stream));

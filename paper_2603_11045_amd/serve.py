@@ -48,14 +48,18 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: float = 200e9, max_blocks: int = 0,
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None,
-                 slice_iters: int = 0, backfill_ticks: Optional[int] = None):
+                 slice_iters: int = 0, backfill_ticks: Optional[int] = None, kernel: str = "resident"):
+        if kernel not in ("resident", "streaming"):
+            raise ValueError("kernel must be 'resident' or 'streaming'")
+        self.kernel = kernel
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._srv = ctypes.c_void_p()
         _check(self.lib.nh_server_create(ctypes.byref(self._srv), self.device.index,
                                          ctypes.c_void_p(self.stream.cuda_stream), float(hbm_budget_bytes),
-                                         int(max_blocks)), None, "nh_server_create", self.lib)
+                                         int(max_blocks), int(kernel == "resident")), None, "nh_server_create",
+               self.lib)
         self._shapes: Dict[int, tuple] = {}
         self._done = (ctypes.c_longlong * 256)()
         if slice_iters:
@@ -223,10 +227,11 @@ def target_series(specs, rtol: float = 1e-6) -> List[np.ndarray]:
 
 def serve_stream(reqs: Sequence[Request], hbm_budget_bytes: float = 200e9, max_blocks: int = 0,
                  keep_grads: bool = False, log=None, slice_iters: int = 0,
-                 backfill_ticks: Optional[int] = None) -> StreamResult:
+                 backfill_ticks: Optional[int] = None, kernel: str = "resident") -> StreamResult:
     """Feed ``reqs`` to a ``Server`` at their arrival times (wall clock from
     the call) and tick until all are done. Latency = completion - arrival."""
-    srv = Server(hbm_budget_bytes, max_blocks, slice_iters=slice_iters, backfill_ticks=backfill_ticks)
+    srv = Server(hbm_budget_bytes, max_blocks, slice_iters=slice_iters, backfill_ticks=backfill_ticks,
+                 kernel=kernel)
     order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival_s)
     pending = deque(order)
     id2req: Dict[int, int] = {}
@@ -322,7 +327,7 @@ def sequential_stream(reqs: Sequence[Request], keep_grads: bool = False, log=Non
 
 def benchmark(n_jobs: int = 40, rate: float = 20.0, seed: int = 5, hbm_budget_bytes: float = 200e9,
               sequential: bool = True, log=None, slice_iters: int = 0,
-              backfill_ticks: Optional[int] = None) -> dict:
+              backfill_ticks: Optional[int] = None, kernel: str = "resident") -> dict:
     """Serve the first ``n_jobs`` of the Poisson stream of mixed grids, then
     (optionally) the same requests sequentially; returns both summaries and
     the speedup of the served stream (throughput and latency)."""
@@ -338,8 +343,9 @@ def benchmark(n_jobs: int = 40, rate: float = 20.0, seed: int = 5, hbm_budget_by
     reqs = requests_from_specs(specs, targets)
     torch.cuda.synchronize()
     say(f"serve: {n_jobs} jobs generated with targets in {time.perf_counter() - t:.1f} s")
-    a = serve_stream(reqs, hbm_budget_bytes, log=log, slice_iters=slice_iters, backfill_ticks=backfill_ticks)
-    out = {"rate_jobs_per_s": rate, "seed": seed, "hbm_budget_gb": hbm_budget_bytes / 1e9,
+    a = serve_stream(reqs, hbm_budget_bytes, log=log, slice_iters=slice_iters, backfill_ticks=backfill_ticks,
+                     kernel=kernel)
+    out = {"rate_jobs_per_s": rate, "seed": seed, "hbm_budget_gb": hbm_budget_bytes / 1e9, "kernel": kernel,
            "batched": a.summary()}
     say("serve: batched", out["batched"])
     if sequential:
@@ -367,10 +373,11 @@ def main(argv=None):
     p.add_argument("--no-sequential", action="store_true")
     p.add_argument("--slice", type=int, default=0, help="CG iterations per tick (0 = library default)")
     p.add_argument("--backfill", type=int, default=None, help="backfill window in ticks (0 = strict order)")
+    p.add_argument("--kernel", default="resident", choices=["resident", "streaming"])
     args = p.parse_args(argv)
     res = benchmark(args.jobs, args.rate, args.seed, args.budget_gb * 1e9, not args.no_sequential,
                     log=lambda s: print(s, file=sys.stderr, flush=True), slice_iters=args.slice,
-                    backfill_ticks=args.backfill)
+                    backfill_ticks=args.backfill, kernel=args.kernel)
     print(json.dumps(res), flush=True)
 
 

@@ -58,13 +58,17 @@ def jobs():
     return out
 
 
+KERNELS = ["resident", "streaming"]
+
+
 def submit(srv, j):
     w = j["w"]
     return srv.submit(w.alpha, w.q_xy, w.q_t, j["target"], w.dt, 1.0, RTOL, 2000)
 
 
-def test_batched_jobs_match_oracle(jobs):
-    srv = Server(hbm_budget_bytes=8e9)
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_batched_jobs_match_oracle(jobs, kernel):
+    srv = Server(hbm_budget_bytes=8e9, kernel=kernel)
     ids = [submit(srv, j) for j in jobs]
     done = srv.run_until_idle()
     assert sorted(done) == sorted(ids)
@@ -82,10 +86,11 @@ def test_batched_jobs_match_oracle(jobs):
     srv.close()
 
 
-def test_alone_equals_mixed(jobs):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_alone_equals_mixed(jobs, kernel):
     alone = []
     for j in jobs:
-        srv = Server(hbm_budget_bytes=8e9)
+        srv = Server(hbm_budget_bytes=8e9, kernel=kernel)
         jid = submit(srv, j)
         srv.run_until_idle()
         alone.append(srv.result(jid)[:2])
@@ -93,7 +98,7 @@ def test_alone_equals_mixed(jobs):
     # the mix: staggered arrivals, jobs join while others are in their
     # forward or adjoint sweeps; one-iteration slices (one step per job and
     # tick) against the default slices of the runs alone
-    srv = Server(hbm_budget_bytes=8e9, slice_iters=1)
+    srv = Server(hbm_budget_bytes=8e9, slice_iters=1, kernel=kernel)
     ids = [submit(srv, jobs[0])]
     for k in range(3):
         srv.tick()
@@ -114,7 +119,7 @@ def test_alone_equals_mixed(jobs):
 def test_budget_limits_concurrency(jobs):
     lib = _lib.load()
     w0 = jobs[1]["w"]
-    t = lib.nh_serve_job_team(w0.nx, w0.ny, w0.nz, 256)
+    t = lib.nh_serve_job_team(w0.nx, w0.ny, w0.nz, 256, 1)
     b1 = lib.nh_serve_job_bytes(w0.nx, w0.ny, w0.nz, w0.nsteps, t)
     srv = Server(hbm_budget_bytes=1.5 * b1)
     ids = [submit(srv, jobs[1]) for _ in range(3)]
@@ -133,21 +138,23 @@ def test_budget_limits_concurrency(jobs):
     srv.close()
 
 
-def test_workgroup_limit_limits_concurrency(jobs):
-    # max_blocks = 8: the 6-workgroup job cannot share the chip with the 4-workgroup one
-    srv = Server(hbm_budget_bytes=8e9, max_blocks=8)
+@pytest.mark.parametrize("kernel,limit", [("resident", 16), ("streaming", 8)])
+def test_workgroup_limit_limits_concurrency(jobs, kernel, limit):
+    # a limit below the three jobs' total: they cannot all share the chip
+    srv = Server(hbm_budget_bytes=8e9, max_blocks=limit, kernel=kernel)
     ids = [submit(srv, jobs[1]), submit(srv, jobs[3]), submit(srv, jobs[0])]
-    teams = []
+    peak = 0
     while True:
         na, nq, _ = srv.tick()
         st = srv.stats()
-        assert st["used_blocks"] <= 8
-        teams.append(st["used_blocks"])
+        assert st["used_blocks"] <= limit
+        peak = max(peak, na)
         if na == 0 and nq == 0:
             break
+    assert peak < 3
     for jid, j in zip(ids, [jobs[1], jobs[3], jobs[0]]):
         L, G, inf = srv.result(jid)
-        assert inf["team_blocks"] <= 4
+        assert inf["team_blocks"] <= limit
         assert rel_l2(G, j["G"]) <= 1e-4
     srv.close()
 

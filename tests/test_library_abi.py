@@ -46,5 +46,5 @@ def test_null_context_calls_fail_cleanly():
     lib.nh_destroy(None)
     assert lib.nh_server_tick(None, None, None, None, 0, None) == _lib.NH_EINVAL
     assert lib.nh_server_last_error(None) == b"null server"
-    assert lib.nh_server_create(None, 0, None, 1e9, 0) == _lib.NH_EINVAL
+    assert lib.nh_server_create(None, 0, None, 1e9, 0, 1) == _lib.NH_EINVAL
     lib.nh_server_destroy(None)

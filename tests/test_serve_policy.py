@@ -78,9 +78,9 @@ def test_admit_edge_cases(lib):
     assert lib.nh_serve_admit_select(None, None, None, 3, 0, 0, 10.0, 10, 0, None) == 0
 
 
-def test_job_team_sizes(lib):
+def test_job_team_sizes_streaming(lib):
     # about one workgroup per 32768 voxels, one tile each, capped at half the limit
-    teams = {g: lib.nh_serve_job_team(*g, 256) for g in wl.SERVE_GRIDS}
+    teams = {g: lib.nh_serve_job_team(*g, 256, 0) for g in wl.SERVE_GRIDS}
     assert teams[(32, 32, 16)] == 1
     assert teams[(64, 64, 32)] == 4
     assert teams[(96, 96, 32)] == 12
@@ -90,15 +90,27 @@ def test_job_team_sizes(lib):
         ng = g[0] * g[1] * g[2]
         assert 1 <= t <= 128
         assert ng / t <= 2 * 32768 + 1
-    assert lib.nh_serve_job_team(192, 192, 48, 64) == 32
-    assert lib.nh_serve_job_team(0, 1, 1, 256) == 0
-    assert lib.nh_serve_job_team(4, 4, 4, 0) == 0
+    assert lib.nh_serve_job_team(192, 192, 48, 64, 0) == 32
+    assert lib.nh_serve_job_team(0, 1, 1, 256, 0) == 0
+    assert lib.nh_serve_job_team(4, 4, 4, 0, 0) == 0
+
+
+def test_job_team_sizes_resident(lib):
+    # one workgroup per tile of 64 x 8 columns and <= 32 cells in z
+    teams = {g: lib.nh_serve_job_team(*g, 256, 1) for g in wl.SERVE_GRIDS}
+    assert teams == {(32, 32, 16): 4, (64, 64, 32): 8, (96, 96, 32): 24, (128, 128, 48): 64, (192, 192, 48): 144}
+    assert lib.nh_serve_job_team(70, 40, 24, 256, 1) == 10
+    assert lib.nh_serve_job_team(96, 20, 40, 256, 1) == 12
+    assert lib.nh_serve_job_team(256, 256, 64, 256, 1) == 256
+    # larger than the device: not servable in this mode
+    assert lib.nh_serve_job_team(256, 256, 65, 256, 1) == 0
+    assert lib.nh_serve_job_team(192, 192, 48, 100, 1) == 0
 
 
 def test_job_bytes(lib):
     for (nx, ny, nz) in wl.SERVE_GRIDS:
         for ns in wl.SERVE_STEPS:
-            team = lib.nh_serve_job_team(nx, ny, nz, 256)
+            team = lib.nh_serve_job_team(nx, ny, nz, 256, 1)
             b = lib.nh_serve_job_bytes(nx, ny, nz, ns, team)
             ng, nxy = nx * ny * nz, nx * ny
             floor = 4 * ng * (12 + ns) + 8 * ng + 4 * nxy * (1 + 3 * ns)
@@ -115,7 +127,7 @@ def test_stream_fits_budget(lib):
     sizes = []
     for j in jobs:
         w = j.workload
-        t = lib.nh_serve_job_team(w.nx, w.ny, w.nz, 256)
+        t = lib.nh_serve_job_team(w.nx, w.ny, w.nz, 256, 1)
         sizes.append((lib.nh_serve_job_bytes(w.nx, w.ny, w.nz, w.nsteps, t), t))
     assert max(b for b, _ in sizes) < 200e9
     n = admit(lib, [b for b, _ in sizes], [t for _, t in sizes], 0, 0, 200e9, 256)
