@@ -291,9 +291,11 @@ __device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* 
 
 // One implicit-Euler step of one team with the tile's CG state in registers
 // (dsm: the dynamic LDS of kResLdsBytes). Per-step fields come from V.
+// publish: end with a fenced team barrier, for callers that run further steps
+// in the same launch.
 template <int TXC>
 __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, const StepVar<float>& V, int rank,
-                                    unsigned char* dsm) {
+                                                    unsigned char* dsm, bool publish) {
   using G = RG<TXC>;
   constexpr int TZ = kResTZ;
   float* la = (float*)dsm;
@@ -631,6 +633,17 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                    });
   }
 
+  if (publish) {
+    // The solution was stored with ordinary stores (the last part after the
+    // final reduction): make it visible to the whole team before a following
+    // step in the same launch reads its neighbours' cells. The barrier takes
+    // the last epoch of this step's range.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned long long e = V.epoch_base + 0xFFFEull;
+    double none[1] = {0.0};
+    if (!team_sum_dev<1>(S, rank, e, none, rs)) status |= kTimeout;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   const double relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
   if (V.out_iters && rank == 0 && threadIdx.x == 0) {
     V.out_iters[0] = it;
@@ -643,7 +656,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
 template <int TXC>
 __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<float> S) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  resident_step<TXC>(S, step_var(S), blockIdx.x, dsm);
+  resident_step<TXC>(S, step_var(S), blockIdx.x, dsm, false);
 }
 
 }  // namespace nh
