@@ -150,14 +150,18 @@ nh_status nh_set_launch(nh_ctx *ctx, int team_blocks_max, int tile_z, int profil
  * |r|^2 are reduced together once per iteration. Frees the saved forward. */
 nh_status nh_set_cg_variant(nh_ctx *ctx, int variant);
 
-/* CG initial guess of every solve: 1 (default) extrapolates the states of
- * the preceding time levels -- 2 h1 - h2 with two of them, 3 h1 - 3 h2 + h3
- * with three (h1 = T^{n-1}, h2 = T^{n-2}, ... forward; mu^{n+1}, mu^{n+2},
- * ... adjoint); 0 starts from the previous state h1 alone. Both converge to
- * the same tolerance; the extrapolation needs fewer iterations on smooth
- * trajectories. With checkpointing the three states below each checkpoint
- * are kept, so recomputed segments repeat the forward bit for bit. Drops any
- * saved forward. */
+/* CG initial guess of every solve. The states of the preceding time levels
+ * are h1 = T^{n-1}, h2 = T^{n-2}, h3 = T^{n-3} (forward) or mu^{n+1},
+ * mu^{n+2}, mu^{n+3} (adjoint); their extrapolation is 2 h1 - h2 with two of
+ * them and 3 h1 - 3 h2 + h3 with three. mode 0 starts from h1; mode 1 from
+ * the extrapolation; mode 2 (default) adaptively: in each period of 32 steps
+ * of a sweep the first step starts from h1 and the second from the
+ * extrapolation, and the rest from whichever of the two took fewer CG
+ * iterations (the choice is made on the device, so nothing synchronises).
+ * All modes converge to the same tolerance. With checkpointing the three
+ * states below each checkpoint are kept and recomputed steps repeat the
+ * forward's choices, so recomputation stays bit for bit. Drops any saved
+ * forward. */
 nh_status nh_set_initial_guess(nh_ctx *ctx, int mode);
 
 /* Time limit of the device-side team barrier in seconds (default 20). A

@@ -64,7 +64,7 @@ struct nh_ctx {
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
   Buf mu[4];                                 // adjoint states, mu^n in mu[n & 3]
   Buf w[4];                                  // checkpointed forward: T^n in w[n & 3]
-  int guess = 1;                             // initial guess: 0 previous state, 1 extrapolated
+  int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive
   int variant = 2;                           // 0 two reductions per iteration, 1 one, 2 one + register-resident
   bool resident = false;                     // the current plan uses nh::resident_step_kernel
   unsigned long long launch_ctr = 0;         // makes every launch's reduction epochs unique
@@ -419,16 +419,28 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   return NH_OK;
 }
 
-// The previous state h1 and the CG initial guess. With the extrapolating
-// guess and two (three) earlier states available, x0 is the linear
-// (quadratic) extrapolation 2 h1 - h2 (3 h1 - 3 h2 + h3) of the states at the
-// three preceding time levels; else x0 = h1. Null states are zero.
-template <typename R>
-void set_guess(const nh_ctx* c, StepArgs<R>& S, const R* const (&h)[3]) {
+// The previous state h1 and the CG initial guess. With two (three) earlier
+// states available the extrapolated guess is the linear (quadratic)
+// extrapolation 2 h1 - h2 (3 h1 - 3 h2 + h3) of the states at the preceding
+// time levels; otherwise, or when the policy says so, x0 = h1. Null states are
+// zero. Policy (c->guess): 0 always h1; 1 always the extrapolation; 2
+// adaptive: the steps of a sweep are taken in periods of kGuessPeriod; the
+// first step of a period starts from h1, the second from the extrapolation,
+// and the others from whichever of the two needed fewer iterations (the
+// kernel compares the counts in gi, written by the earlier launches).
+// j is the step's position in its sweep, step(j) the step number at
+// position j; gi is indexed by step number - 1.
+constexpr int kGuessPeriod = 32;
+
+template <typename R, typename StepOf>
+void set_guess(const nh_ctx* c, StepArgs<R>& S, const R* const (&h)[3], int j, const int* gi, StepOf step) {
   S.xprev = h[0];
   S.xprev2 = S.xprev3 = nullptr;
   S.ex1 = R(1);
   S.ex2 = S.ex3 = R(0);
+  S.gmode = 0;
+  S.gi = nullptr;
+  S.gpw = S.gpe = -1;
   if (!c->guess || !h[0] || !h[1]) return;
   S.xprev2 = h[1];
   if (h[2]) {
@@ -436,6 +448,17 @@ void set_guess(const nh_ctx* c, StepArgs<R>& S, const R* const (&h)[3]) {
     S.ex1 = R(3); S.ex2 = R(-3); S.ex3 = R(1);
   } else {
     S.ex1 = R(2); S.ex2 = R(-1);
+  }
+  if (c->guess == 1) {
+    S.gmode = 1;
+    return;
+  }
+  const int k = j % kGuessPeriod;
+  S.gmode = k == 0 ? 0 : (k == 1 ? 1 : 2);
+  if (k >= 2) {
+    S.gi = gi;
+    S.gpw = step(j - k) - 1;
+    S.gpe = step(j - k + 1) - 1;
   }
 }
 
@@ -449,7 +472,8 @@ nh_status forward_step(nh_ctx* c, int n, const R* const (&h)[3], R* x, const R* 
   base_args<R>(c, S, dt);
   S.mode = nh::kForward;
   S.x = x;
-  set_guess<R>(c, S, h);
+  // a recomputed step repeats the original forward's choices: same counts
+  set_guess<R>(c, S, h, n - 1, step_out(c, 0, 0).iters, [](int jj) { return jj + 1; });
   S.top_src = q_xy;
   S.top_scale = (R)(dt * qt);
   S.surf_out = surf;
@@ -630,7 +654,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     S.mode = nh::kAdjoint;
     S.x = M[n & 3];
     const R* const h[3] = {mu_state(n + 1), mu_state(n + 2), mu_state(n + 3)};
-    set_guess<R>(c, S, h);
+    set_guess<R>(c, S, h, N - n, step_out(c, 1, 0).iters, [N](int jj) { return N - jj; });
     S.top_src = gsurf + (size_t)(n - 1) * g.nxy;
     S.top_scale = R(1);
     S.T_grad = Tn;
@@ -887,7 +911,7 @@ nh_status nh_get_step_iters(const nh_ctx* c, int sweep, int* iters) {
 
 nh_status nh_set_initial_guess(nh_ctx* c, int mode) {
   if (!c) return NH_EINVAL;
-  if (mode < 0 || mode > 1) return fail(c, NH_EINVAL, "initial guess mode must be 0 or 1");
+  if (mode < 0 || mode > 2) return fail(c, NH_EINVAL, "initial guess mode must be 0, 1 or 2");
   drop_forward(c);
   c->guess = mode;
   return NH_OK;

@@ -64,6 +64,9 @@ struct StepArgs {
   const R* xprev2;                          // h2, h3: the two states before it, for the initial guess
   const R* xprev3;                          //   x0 = ex1 h1 + ex2 h2 + ex3 h3 (null: x0 = h1)
   R ex1, ex2, ex3;
+  int gmode;                                // 0: x0 = h1; 1: the extrapolation; 2: the extrapolation
+  const int* gi;                            //   iff the step gi[gpe] took no more iterations than the
+  int gpw, gpe;                             //   step gi[gpw] (earlier steps of the same sweep)
   R* z;                                     // preconditioned residual
   R* p0;                                    // search direction, ping-pong pair
   R* p1;
@@ -744,6 +747,9 @@ struct StepVar {
   const R* xprev2;
   const R* xprev3;
   R ex1, ex2, ex3;
+  int gmode;
+  const int* gi;
+  int gpw, gpe;
   const R* top_src;
   R top_scale;
   R* surf_out;
@@ -755,6 +761,16 @@ struct StepVar {
   unsigned long long epoch_base;
 };
 
+// Whether this step starts from the extrapolated initial guess. In mode 2
+// every workgroup reads the same two iteration counts, written by earlier
+// launches, so the choice is uniform over the team.
+template <typename R>
+__device__ __forceinline__ bool use_extrapolation(const StepVar<R>& V) {
+  if (V.gmode == 0) return false;
+  if (V.gmode == 1 || !V.gi || V.gpw < 0 || V.gpe < 0) return true;
+  return V.gi[V.gpe] <= V.gi[V.gpw];
+}
+
 template <typename R>
 __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   StepVar<R> V;
@@ -765,6 +781,10 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   V.ex1 = S.ex1;
   V.ex2 = S.ex2;
   V.ex3 = S.ex3;
+  V.gmode = S.gmode;
+  V.gi = S.gi;
+  V.gpw = S.gpw;
+  V.gpe = S.gpe;
   V.top_src = S.top_src;
   V.top_scale = S.top_scale;
   V.surf_out = S.surf_out;
@@ -802,7 +822,7 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
   init.nxy = g.nxy;
   init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
   init.src = V.xprev;
-  init.h2 = V.xprev ? V.xprev2 : nullptr;
+  init.h2 = (V.xprev && use_extrapolation(V)) ? V.xprev2 : nullptr;
   init.h3 = init.h2 ? V.xprev3 : nullptr;
   init.e1 = V.ex1; init.e2 = V.ex2; init.e3 = V.ex3;
   init.xw = (V.xprev == V.x) ? nullptr : V.x;

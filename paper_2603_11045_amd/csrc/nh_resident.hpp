@@ -365,7 +365,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   // ---------------- set-up: x0, b, r = b - A x0, u = r / D; x = x0 in memory
   // x0 = h1 (the previous state), or its extrapolation ex1 h1 + ex2 h2 + ex3 h3
   const float* x0src = V.xprev;
-  const float* h2 = x0src ? V.xprev2 : nullptr;
+  const float* h2 = (x0src && use_extrapolation(V)) ? V.xprev2 : nullptr;
   const float* h3 = h2 ? V.xprev3 : nullptr;
   auto x0_at = [&](int i) -> float {
     if (!h2) return x0src[i];

@@ -71,12 +71,27 @@ constexpr int kMaxSliceSteps = 255;       // steps per slice: epoch bits 16..23 
 // which every member then reaches within its own bounded waits).
 typedef __attribute__((address_space(4))) const JobRun CJobRun;
 
+constexpr int kGuessPeriod = 32;
+
 template <typename StepF>
 __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* prog, StepF step) {
   const long long t0 = wall_clock64();
   const bool fwd = J.mode == kForward;
   int n = J.n0, steps = 0, status = 0;
   long long iters = 0;
+  // Adaptive initial guess: in each period of kGuessPeriod steps of a sweep
+  // the first step starts from the previous state, the second from the
+  // extrapolation, the rest from whichever needed fewer iterations. j is a
+  // step's position in its sweep; counts of probes run by earlier launches
+  // come from the per-step record, later ones from this loop.
+  auto pos = [&](int nn) { return fwd ? nn - 1 : J.nsteps - nn; };
+  auto slot_of = [&](int jj) { return fwd ? jj : 2 * J.nsteps - 1 - jj; };
+  int pw = -1, pe = -1;
+  {
+    const int j0 = pos(n), base = j0 - j0 % kGuessPeriod;
+    if (base < j0) pw = J.it_out[slot_of(base)];
+    if (base + 1 < j0) pe = J.it_out[slot_of(base + 1)];
+  }
   const StepArgs<float>& S = (const StepArgs<float>&)J.S;
   const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
   while (true) {
@@ -103,14 +118,21 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
       V.surf_out = nullptr;
       V.T_grad = J.traj + (long long)(n - 1) * ng;
     }
-    // initial guess: quadratic (linear) extrapolation with three (two) previous states
+    // extrapolation: quadratic (linear) with three (two) previous states
+    const int k = pos(n) % kGuessPeriod;
+    if (k == 0) pw = pe = -1;
     V.xprev = h[0];
     V.xprev2 = h[0] ? h[1] : nullptr;
     V.xprev3 = V.xprev2 ? h[2] : nullptr;
     V.ex1 = V.xprev3 ? 3.f : (V.xprev2 ? 2.f : 1.f);
     V.ex2 = V.xprev3 ? -3.f : (V.xprev2 ? -1.f : 0.f);
     V.ex3 = V.xprev3 ? 1.f : 0.f;
+    V.gmode = k == 0 ? 0 : (k == 1 || pw < 0 || pe < 0 || pe <= pw ? 1 : 0);
+    V.gi = nullptr;
+    V.gpw = V.gpe = -1;
     const StepResult r = step(S, V);
+    if (k == 0) pw = r.iters;
+    if (k == 1) pe = r.iters;
     if (m.y == 0 && threadIdx.x == 0) {
       const int slot = (fwd ? 0 : J.nsteps) + n - 1;
       J.it_out[slot] = r.iters;

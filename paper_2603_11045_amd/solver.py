@@ -46,8 +46,8 @@ class Solver:
     selects the CG form: 0 two reductions per iteration, 1 one reduction
     (streaming kernel), 2 one reduction with the register-resident kernel
     where the grid fits on the chip, else as 1. ``initial_guess`` is the CG
-    starting point of each solve: ``"extrapolate"`` from the last three
-    states, or ``"previous"`` state alone.
+    starting point of each solve: ``"adaptive"`` (default), ``"extrapolate"``
+    from the last three states, or ``"previous"`` state alone.
     """
 
     def __init__(self, nx: int, ny: int, nz: int, h: Sequence[float] = (1.0, 1.0, 1.0),
@@ -55,7 +55,7 @@ class Solver:
                  precision: str = "f32", device: Optional[int] = None,
                  stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
                  tile_z: int = 0, profile: bool = False, cg_variant: int = 2,
-                 initial_guess: str = "extrapolate"):
+                 initial_guess: str = "adaptive"):
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.lib = _lib.load()
@@ -94,8 +94,10 @@ class Solver:
         self.cg_variant = int(variant)
 
     def set_initial_guess(self, mode: str):
-        """``"extrapolate"`` (from the last three states) or ``"previous"`` (the last state)."""
-        modes = {"previous": 0, "extrapolate": 1}
+        """``"previous"`` (the last state), ``"extrapolate"`` (from the last
+        three states) or ``"adaptive"`` (per period of steps, whichever of the
+        two needed fewer iterations)."""
+        modes = {"previous": 0, "extrapolate": 1, "adaptive": 2}
         if mode not in modes:
             raise ValueError(f"initial_guess must be one of {sorted(modes)}")
         _check(self.lib.nh_set_initial_guess(self._ctx, modes[mode]), self._ctx, "nh_set_initial_guess")

@@ -40,7 +40,7 @@ def to_dev(a, dtype):
 
 
 def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=2,
-            guess="extrapolate"):
+            guess="adaptive"):
     """Forward (and adjoint when gs is given) of workload w on the GPU."""
     prec = precision or w.precision
     dt_t = torch.float32 if prec == "f32" else torch.float64
@@ -149,11 +149,11 @@ def test_mixed_64x64x32_forward_and_adjoint(mixed_ref, variant):
 
 @pytest.mark.timeout(600)
 def test_initial_guess_modes(mixed_ref):
-    """Both CG starting points reach the tolerance; the extrapolated one in
-    fewer iterations on this smooth trajectory."""
+    """Every CG starting point reaches the tolerance; the extrapolated one in
+    fewer iterations on this smooth trajectory, the adaptive choice too."""
     w, ref = mixed_ref
     its = {}
-    for guess in ("previous", "extrapolate"):
+    for guess in ("previous", "extrapolate", "adaptive"):
         out = run_gpu(w, gs=ref["gs"].astype(np.float32), guess=guess)
         es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
         its[guess] = (out["stats_fwd"]["fwd_iters"], out["stats_adj"]["adj_iters"])
@@ -162,6 +162,7 @@ def test_initial_guess_modes(mixed_ref):
         assert eg <= 1e-4
     assert its["extrapolate"][0] < its["previous"][0]
     assert its["extrapolate"][1] < its["previous"][1]
+    assert sum(its["adaptive"]) < sum(its["previous"])
 
 
 # ------------------------------------------------------------------ checkpointing, determinism
