@@ -514,6 +514,10 @@ nh_status forward_step(nh_ctx* c, int n, const R* const (&h)[3], R* x, const R* 
       std::fprintf(stderr, "[nh trace] step %d rank %d variant %d: set-up %.2f us, %d iterations, mean us per phase:",
                    n, nranks > 1 ? r : S.trace_rank, c->variant, m >= head ? (t[head - 1] - t[0]) * us : 0.0, its);
       for (int j = 0; j < per; ++j) std::fprintf(stderr, " %.2f", its ? acc[j] / its : 0.0);
+      std::fprintf(stderr, " | set-up phases:");
+      for (int j = 1; j < head && j < m; ++j) std::fprintf(stderr, " %.2f", (t[j] - t[j - 1]) * us);
+      const int last = head + per * its - 1;
+      if (m - 1 > last && last >= 0) std::fprintf(stderr, " | after the loop %.2f", (t[m - 1] - t[last]) * us);
       std::fprintf(stderr, "\n");
     }
   }

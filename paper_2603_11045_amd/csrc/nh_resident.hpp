@@ -339,17 +339,22 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   };
   stamp();
 
-  // alpha tile with halos: planes z0-1 .. z0+tzn, each (TX+2) x (TY+2)
+  // alpha tile with halos: planes z0-1 .. z0+tzn, each (TX+2) x (TY+2),
+  // streamed straight into LDS (slot e of the tile <- lane e % 64 of a wave's
+  // load); cells outside the grid are stored as zero
   {
     const int n = (q.tzn + 2) * G::PL;
-    for (int e = tid0; e < n; e += kResBlock) {
-      const int lz = e / G::PL, rem = e - lz * G::PL;
-      const int ly = rem / G::PW, lx = rem - ly * G::PW;
-      const int gz = T.z0 - 1 + lz, gxx = T.x0 - 1 + lx, gyy = T.y0 - 1 + ly;
-      float a = 0.f;
-      if (gz >= 0 && gz < g.nz && gxx >= 0 && gxx < g.nx && gyy >= 0 && gyy < g.ny)
-        a = S.alpha[gxx + g.nx * gyy + gz * nxy];
-      la[e] = a;
+    for (int e0 = 0; e0 < n; e0 += kResBlock) {
+      const int e = e0 + tid0;
+      if (e < n) {
+        const int lz = e / G::PL, rem = e - lz * G::PL;
+        const int ly = rem / G::PW, lx = rem - ly * G::PW;
+        const int gz = T.z0 - 1 + lz, gxx = T.x0 - 1 + lx, gyy = T.y0 - 1 + ly;
+        if (gz >= 0 && gz < g.nz && gxx >= 0 && gxx < g.nx && gyy >= 0 && gyy < g.ny)
+          __builtin_amdgcn_global_load_lds(S.alpha + gxx + g.nx * gyy + gz * nxy, la + e0 + (tid0 & ~63), 4, 0, 0);
+        else
+          la[e] = 0.f;
+      }
     }
   }
 
@@ -383,6 +388,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     for (int z = 0; z < TZ; ++z)
       if (z < q.tzn) V.x[q.col + (T.z0 + z) * nxy] = xr[z];
   }
+  float xtop = xr[0];                       // the latest x of the column's first cell (surface frame)
   float zlo[2] = {0.f, 0.f}, zhi[2] = {0.f, 0.f};
   if (x0src) {
     if (q.own && q.bot_z) zlo[0] = x0_at(q.col + (T.z0 - 1) * nxy);
@@ -391,6 +397,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   } else {
     fill_ring<G>(g, q, lring, [&](int) { return 0.f; });
   }
+  __builtin_amdgcn_s_waitcnt(0);            // the alpha tile has reached LDS
   __syncthreads();
   double acc3[3] = {0.0, 0.0, 0.0};
   plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return xr[z]; }, zlo, zhi,
@@ -429,6 +436,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       for (int z = 0; z < TZ; ++z)
         if (z < q.tzn) V.x[q.col + (T.z0 + z) * nxy] = 0.f;
     }
+    xtop = 0.f;
     rr = 0.0;
   } else if (ok && rr > S.rtol2 * bb) {
     // ---------------- w0 = A u0
@@ -499,7 +507,9 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
         const float p_ = first ? ur[z] : fmaf(b, pr[z], ur[z]);
         if (xstep && q.own && z < q.tzn) {
           float* xp = V.x + col_l + (T.z0 + z) * nxy_l;
-          *xp = fmaf(a, p_, fmaf(a_prev, pr[z], *xp));
+          const float xn = fmaf(a, p_, fmaf(a_prev, pr[z], *xp));
+          *xp = xn;
+          if (z == 0) xtop = xn;
         }
         pr[z] = p_;
         sr[z] = s_;
@@ -559,7 +569,9 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       for (int z = 0; z < TZ; ++z) {
         if (z < q.tzn) {
           float* xp = V.x + q.col + (T.z0 + z) * nxy;
-          *xp = fmaf(a_prev, pr[z], *xp);
+          const float xn = fmaf(a_prev, pr[z], *xp);
+          *xp = xn;
+          if (z == 0) xtop = xn;
         }
       }
     }
@@ -570,7 +582,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   // ---------------- epilogue: surface frame, checkpoint copy; for the gradient
   // the final x on the tile's faces is republished with device-scope stores
   if (q.own) {
-    if (S.mode == kForward && V.surf_out && T.z0 == 0) V.surf_out[q.col] = V.x[q.col];
+    if (S.mode == kForward && V.surf_out && T.z0 == 0) V.surf_out[q.col] = xtop;
     if (V.ckpt_out) {
       for (int z = 0; z < q.tzn; ++z) {
         const int i = q.col + (T.z0 + z) * nxy;
@@ -633,6 +645,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                    });
   }
 
+  stamp();
   if (publish) {
     // The solution was stored with ordinary stores (the last part after the
     // final reduction): make it visible to the whole team before a following
