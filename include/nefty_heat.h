@@ -269,10 +269,12 @@ nh_status nh_server_create(nh_server **out, int hip_device, void *hip_stream, do
  * Each job runs at least one step per tick. */
 nh_status nh_server_set_slice(nh_server *s, int iters);
 
-/* Backfilling: a queued job that does not fit holds back the jobs behind it
- * only after it has waited `ticks` ticks; until then smaller jobs behind it
- * that fit are admitted first (default 64; 0 = strict arrival order). */
-nh_status nh_server_set_backfill(nh_server *s, int ticks);
+/* Admission order: 1 (default) EASY backfilling -- the first queued job that
+ * does not fit holds a reservation, and a later job is admitted ahead of it
+ * only if it fits now and, by run-time estimates from the measured step
+ * times, either ends before the reserved job could start or leaves it room;
+ * 0 strict arrival order. */
+nh_status nh_server_set_backfill(nh_server *s, int mode);
 
 /* Queue a job. HOST inputs: alpha [nz][ny][nx] (finite, > 0), q_xy [ny][nx],
  * q_t [nsteps] (FP64), target [nsteps][ny][nx]; uniform spacing h; CG to
@@ -317,15 +319,20 @@ int nh_serve_job_team(int nx, int ny, int nz, int max_blocks, int resident);
 size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks);
 
 /* The jobs the next tick admits, as indices into the queue (arrival order),
- * written to selected[] (room for n_queued); returns their number. Walking
- * the queue in order, a job is admitted when its bytes and workgroups, added
- * to those in use and to those admitted before it, stay within the budget
- * and the workgroup limit. A job that does not fit and has waited
- * (waited[i] ticks) at least reserve_after ticks ends the walk: nothing
- * behind it is admitted ahead of it. reserve_after = 0 is strict arrival
- * order. */
-int nh_serve_admit_select(const size_t *bytes, const int *teams, const int *waited, int n_queued, size_t used_bytes,
-                          int used_blocks, double budget_bytes, int max_blocks, int reserve_after, int *selected);
+ * written to selected[] (room for n_queued); returns their number. Queued job
+ * i needs qbytes[i] device bytes and qteams[i] workgroups and is expected to
+ * run qdur[i] seconds; running job i holds abytes[i] and ateams[i] and is
+ * expected to end in arem[i] seconds. Walking the queue in order, jobs are
+ * admitted while they fit the budget and the workgroup limit. With
+ * backfill = 0 the walk ends at the first job that does not fit. With
+ * backfill = 1 that job holds a reservation: its shadow time is when enough
+ * running jobs (in order of expected end) have ended for it to fit, and its
+ * extra room is what it would leave free then; a later job is admitted if it
+ * fits now and either ends by the shadow time or fits in the extra room
+ * (which it then uses up). qdur and arem may be NULL with backfill = 0. */
+int nh_serve_admit_select(const size_t *qbytes, const int *qteams, const double *qdur, int n_queued,
+                          const size_t *abytes, const int *ateams, const double *arem, int n_active,
+                          double budget_bytes, int max_blocks, int backfill, int *selected);
 
 #ifdef __cplusplus
 }

@@ -164,9 +164,9 @@ def load():
     lib.nh_serve_job_team.restype = ip
     lib.nh_serve_job_bytes.argtypes = [ip, ip, ip, ip, ip]
     lib.nh_serve_job_bytes.restype = ctypes.c_size_t
-    lib.nh_serve_admit_select.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ip),
-                                          ctypes.POINTER(ip), ip, ctypes.c_size_t, ip, dp, ip, ip,
-                                          ctypes.POINTER(ip)]
+    szp, dpp = ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(dp)
+    lib.nh_serve_admit_select.argtypes = [szp, ctypes.POINTER(ip), dpp, ip, szp, ctypes.POINTER(ip), dpp, ip,
+                                          dp, ip, ip, ctypes.POINTER(ip)]
     lib.nh_serve_admit_select.restype = ip
     lib.nh_server_set_backfill.argtypes = [vp, ip]
     for name in EXPORTED:

@@ -308,7 +308,8 @@ struct SJob {
   void* slots = nullptr;
   int *it_out = nullptr, *st_out = nullptr;
   int step = 0;            // the next step to compute (the adjoint counts down from N)
-  int waited = 0;          // ticks spent in the queue
+  int steps_done = 0;      // forward and adjoint steps completed
+  double busy_s = 0.0;     // measured time of its slices
   long long fwd_iters = 0, adj_iters = 0;
   int status = 0;
   double loss = 0;
@@ -325,7 +326,8 @@ struct nh_server {
   double budget = 0;
   int resident = 1;        // 1: nh::batch_resident_kernel, 0: nh::batch_run_kernel
   int slice_iters = 128;
-  int backfill_ticks = 64;
+  int backfill = 1;        // 1: EASY backfilling, 0: strict arrival order
+  std::map<long long, std::pair<double, long long>> shape_time;   // grid -> (seconds, steps) measured
   size_t used_bytes = 0;
   int used_blocks = 0;
   long long next_id = 1;
@@ -470,6 +472,25 @@ void job_run(const nh_server* s, const SJob* j, unsigned long long epoch_base, n
   J.budget = (long long)s->slice_iters * (s->resident ? kResCells + kResFixedCost : kVoxelsPerBlock + kReductionCost);
 }
 
+long long shape_key(const SJob* j) { return ((long long)j->nx << 42) | ((long long)j->ny << 21) | j->nz; }
+
+// Estimated seconds per step of job j: its own measured mean once it has run
+// a few steps, else the mean of its grid shape, else of all measured jobs.
+double step_estimate(const nh_server* s, const SJob* j) {
+  if (j->steps_done >= 4) return j->busy_s / j->steps_done;
+  auto it = s->shape_time.find(shape_key(j));
+  if (it != s->shape_time.end() && it->second.second > 0) return it->second.first / it->second.second;
+  double t = 0.0;
+  long long n = 0;
+  for (const auto& kv : s->shape_time) {
+    t += kv.second.first;
+    n += kv.second.second;
+  }
+  return n > 0 ? t / n : 1e-3;
+}
+
+double remaining_steps(const SJob* j) { return (double)std::max(0, 2 * j->nsteps - j->steps_done); }
+
 nh_status ensure_tables(nh_server* s, size_t njobs) {
   if (s->cap_jobs >= njobs) return NH_OK;
   const size_t cap = std::max<size_t>(64, 2 * njobs);
@@ -508,20 +529,70 @@ size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks) {
   return job_bytes(nx, ny, nz, nsteps, team_blocks);
 }
 
-int nh_serve_admit_select(const size_t* bytes, const int* teams, const int* waited, int n_queued, size_t used_bytes,
-                          int used_blocks, double budget_bytes, int max_blocks, int reserve_after, int* selected) {
-  if (!bytes || !teams || !waited || !selected || n_queued < 1) return 0;
+int nh_serve_admit_select(const size_t* qbytes, const int* qteams, const double* qdur, int n_queued,
+                          const size_t* abytes, const int* ateams, const double* arem, int n_active,
+                          double budget_bytes, int max_blocks, int backfill, int* selected) {
+  if (!qbytes || !qteams || !selected || n_queued < 1) return 0;
+  if (n_active > 0 && (!abytes || !ateams || !arem)) return 0;
+  if (backfill && !qdur) return 0;
+  struct Act {
+    double rem;
+    size_t bytes;
+    int team;
+  };
+  std::vector<Act> act;
+  double used_m = 0.0;
+  long long used_b = 0;
+  for (int i = 0; i < n_active; ++i) {
+    act.push_back({arem[i], abytes[i], ateams[i]});
+    used_m += (double)abytes[i];
+    used_b += ateams[i];
+  }
   int n = 0;
-  double b = (double)used_bytes;
-  long long w = used_blocks;
+  bool reserved = false;
+  double shadow = 0.0, extra_m = 0.0;
+  long long extra_b = 0;
   for (int i = 0; i < n_queued; ++i) {
-    if (b + (double)bytes[i] <= budget_bytes && w + teams[i] <= max_blocks) {
-      b += (double)bytes[i];
-      w += teams[i];
-      selected[n++] = i;
-    } else if (waited[i] >= reserve_after) {
-      break;  // this job holds a reservation: nothing behind it overtakes it
+    const bool fits = used_m + (double)qbytes[i] <= budget_bytes && used_b + qteams[i] <= max_blocks;
+    if (!reserved) {
+      if (fits) {
+        used_m += (double)qbytes[i];
+        used_b += qteams[i];
+        act.push_back({backfill ? qdur[i] : 0.0, qbytes[i], qteams[i]});
+        selected[n++] = i;
+        continue;
+      }
+      if (!backfill) break;
+      // the first job that does not fit holds a reservation: the shadow time
+      // is when enough running jobs have ended for it to fit, and the extra
+      // room is what it leaves free then
+      reserved = true;
+      std::sort(act.begin(), act.end(), [](const Act& x, const Act& y) { return x.rem < y.rem; });
+      double free_m = budget_bytes - used_m;
+      long long free_b = (long long)max_blocks - used_b;
+      for (const Act& x : act) {
+        if (free_m >= (double)qbytes[i] && free_b >= qteams[i]) break;
+        free_m += (double)x.bytes;
+        free_b += x.team;
+        shadow = x.rem;
+      }
+      extra_m = free_m - (double)qbytes[i];
+      extra_b = free_b - qteams[i];
+      continue;
     }
+    // behind the reservation: jobs that fit now and either end before the
+    // shadow time or use only the extra room
+    if (!fits) continue;
+    const bool early = qdur[i] <= shadow;
+    const bool spare = qteams[i] <= extra_b && (double)qbytes[i] <= extra_m;
+    if (!early && !spare) continue;
+    if (!early) {
+      extra_b -= qteams[i];
+      extra_m -= (double)qbytes[i];
+    }
+    used_m += (double)qbytes[i];
+    used_b += qteams[i];
+    selected[n++] = i;
   }
   return n;
 }
@@ -582,10 +653,10 @@ nh_status nh_server_set_slice(nh_server* s, int iters) {
   return NH_OK;
 }
 
-nh_status nh_server_set_backfill(nh_server* s, int ticks) {
+nh_status nh_server_set_backfill(nh_server* s, int mode) {
   if (!s) return NH_EINVAL;
-  if (ticks < 0) return sfail(s, NH_EINVAL, "backfill window must be >= 0 ticks");
-  s->backfill_ticks = ticks;
+  if (mode < 0 || mode > 1) return sfail(s, NH_EINVAL, "backfill mode must be 0 or 1");
+  s->backfill = mode;
   return NH_OK;
 }
 
@@ -645,18 +716,25 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
   if (hipSetDevice(s->device) != hipSuccess) return sfail(s, NH_EHIP, "hipSetDevice failed");
   int finished = 0;
 
-  // admission: arrival order, with backfilling of later jobs that fit while
-  // the jobs ahead of them have waited fewer than backfill_ticks ticks
+  // admission: arrival order, with EASY backfilling (the first job that does
+  // not fit holds a reservation; later jobs start only if they do not delay
+  // it, judged by run-time estimates from the measured step times)
   {
-    std::vector<size_t> qb;
-    std::vector<int> qt, qw, sel(s->queue.size());
+    std::vector<size_t> qb, ab;
+    std::vector<int> qt, at, sel(s->queue.size());
+    std::vector<double> qd, ar;
     for (const SJob* j : s->queue) {
       qb.push_back(j->bytes);
       qt.push_back(j->team);
-      qw.push_back(j->waited);
+      qd.push_back(2.0 * j->nsteps * step_estimate(s, j));
     }
-    const int na = nh_serve_admit_select(qb.data(), qt.data(), qw.data(), (int)qb.size(), s->used_bytes,
-                                         s->used_blocks, s->budget, s->max_blocks, s->backfill_ticks, sel.data());
+    for (const SJob* j : s->active) {
+      ab.push_back(j->bytes);
+      at.push_back(j->team);
+      ar.push_back(remaining_steps(j) * step_estimate(s, j));
+    }
+    const int na = nh_serve_admit_select(qb.data(), qt.data(), qd.data(), (int)qb.size(), ab.data(), at.data(),
+                                         ar.data(), (int)ab.size(), s->budget, s->max_blocks, s->backfill, sel.data());
     std::vector<SJob*> admitted;
     nh_status st = NH_OK;
     for (int k = 0; k < na && st == NH_OK; ++k) {
@@ -668,10 +746,7 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
     }
     std::deque<SJob*> rest;
     for (SJob* j : s->queue)
-      if (j->state == NH_JOB_QUEUED) {
-        ++j->waited;
-        rest.push_back(j);
-      }
+      if (j->state == NH_JOB_QUEUED) rest.push_back(j);
     s->queue.swap(rest);
     if (st != NH_OK) return st;
     if (na > 0) {
@@ -746,6 +821,14 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
       SJob* j = s->active[k];
       const nh::JobProg pr = s->h_prog[k];
       j->status |= pr.status;
+      {
+        const double sec = (double)(pr.t1 - pr.t0) / ((double)s->wallclock_khz * 1000.0);
+        j->busy_s += sec;
+        j->steps_done += pr.steps;
+        auto& st = s->shape_time[shape_key(j)];
+        st.first += sec;
+        st.second += pr.steps;
+      }
       const bool failed = (pr.status & (nh::kNonFinite | nh::kTimeout)) != 0;
       if (j->state == NH_JOB_FORWARD) {
         j->fwd_iters += pr.iters;

@@ -48,7 +48,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: float = 200e9, max_blocks: int = 0,
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None,
-                 slice_iters: int = 0, backfill_ticks: Optional[int] = None, kernel: str = "resident"):
+                 slice_iters: int = 0, backfill: Optional[int] = None, kernel: str = "resident"):
         if kernel not in ("resident", "streaming"):
             raise ValueError("kernel must be 'resident' or 'streaming'")
         self.kernel = kernel
@@ -64,12 +64,12 @@ class Server:
         self._done = (ctypes.c_longlong * 256)()
         if slice_iters:
             self.set_slice(slice_iters)
-        if backfill_ticks is not None:
-            self.set_backfill(backfill_ticks)
+        if backfill is not None:
+            self.set_backfill(backfill)
 
-    def set_backfill(self, ticks: int):
-        """Ticks a job that does not fit may be overtaken by later jobs (0 = strict order)."""
-        _check(self.lib.nh_server_set_backfill(self._srv, int(ticks)), self._srv, "nh_server_set_backfill",
+    def set_backfill(self, mode: int):
+        """1: EASY backfilling (default), 0: strict arrival order."""
+        _check(self.lib.nh_server_set_backfill(self._srv, int(mode)), self._srv, "nh_server_set_backfill",
                self.lib)
 
     def set_slice(self, iters: int):
@@ -227,10 +227,10 @@ def target_series(specs, rtol: float = 1e-6) -> List[np.ndarray]:
 
 def serve_stream(reqs: Sequence[Request], hbm_budget_bytes: float = 200e9, max_blocks: int = 0,
                  keep_grads: bool = False, log=None, slice_iters: int = 0,
-                 backfill_ticks: Optional[int] = None, kernel: str = "resident") -> StreamResult:
+                 backfill: Optional[int] = None, kernel: str = "resident") -> StreamResult:
     """Feed ``reqs`` to a ``Server`` at their arrival times (wall clock from
     the call) and tick until all are done. Latency = completion - arrival."""
-    srv = Server(hbm_budget_bytes, max_blocks, slice_iters=slice_iters, backfill_ticks=backfill_ticks,
+    srv = Server(hbm_budget_bytes, max_blocks, slice_iters=slice_iters, backfill=backfill,
                  kernel=kernel)
     order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival_s)
     pending = deque(order)
@@ -327,7 +327,7 @@ def sequential_stream(reqs: Sequence[Request], keep_grads: bool = False, log=Non
 
 def benchmark(n_jobs: int = 40, rate: float = 20.0, seed: int = 5, hbm_budget_bytes: float = 200e9,
               sequential: bool = True, log=None, slice_iters: int = 0,
-              backfill_ticks: Optional[int] = None, kernel: str = "resident") -> dict:
+              backfill: Optional[int] = None, kernel: str = "resident") -> dict:
     """Serve the first ``n_jobs`` of the Poisson stream of mixed grids, then
     (optionally) the same requests sequentially; returns both summaries and
     the speedup of the served stream (throughput and latency)."""
@@ -343,7 +343,7 @@ def benchmark(n_jobs: int = 40, rate: float = 20.0, seed: int = 5, hbm_budget_by
     reqs = requests_from_specs(specs, targets)
     torch.cuda.synchronize()
     say(f"serve: {n_jobs} jobs generated with targets in {time.perf_counter() - t:.1f} s")
-    a = serve_stream(reqs, hbm_budget_bytes, log=log, slice_iters=slice_iters, backfill_ticks=backfill_ticks,
+    a = serve_stream(reqs, hbm_budget_bytes, log=log, slice_iters=slice_iters, backfill=backfill,
                      kernel=kernel)
     out = {"rate_jobs_per_s": rate, "seed": seed, "hbm_budget_gb": hbm_budget_bytes / 1e9, "kernel": kernel,
            "batched": a.summary()}
@@ -372,12 +372,12 @@ def main(argv=None):
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--no-sequential", action="store_true")
     p.add_argument("--slice", type=int, default=0, help="CG iterations per tick (0 = library default)")
-    p.add_argument("--backfill", type=int, default=None, help="backfill window in ticks (0 = strict order)")
+    p.add_argument("--backfill", type=int, default=None, help="1 EASY backfilling (default), 0 strict order")
     p.add_argument("--kernel", default="resident", choices=["resident", "streaming"])
     args = p.parse_args(argv)
     res = benchmark(args.jobs, args.rate, args.seed, args.budget_gb * 1e9, not args.no_sequential,
                     log=lambda s: print(s, file=sys.stderr, flush=True), slice_iters=args.slice,
-                    backfill_ticks=args.backfill, kernel=args.kernel)
+                    backfill=args.backfill, kernel=args.kernel)
     print(json.dumps(res), flush=True)
 
 

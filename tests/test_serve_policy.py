@@ -19,20 +19,26 @@ def lib():
     return _lib.load()
 
 
-def select(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks, waited=None, reserve_after=0):
-    n = len(bytes_)
-    waited = [0] * n if waited is None else waited
-    b = (ctypes.c_size_t * max(n, 1))(*bytes_)
-    t = (ctypes.c_int * max(n, 1))(*teams)
-    w = (ctypes.c_int * max(n, 1))(*waited)
+def select(lib, qbytes, qteams, budget, max_blocks, qdur=None, active=(), backfill=0):
+    """Indices the next tick admits; active = [(bytes, team, remaining seconds)]."""
+    n = len(qbytes)
+    qdur = [1.0] * n if qdur is None else qdur
+    qb = (ctypes.c_size_t * max(n, 1))(*qbytes)
+    qt = (ctypes.c_int * max(n, 1))(*qteams)
+    qd = (ctypes.c_double * max(n, 1))(*qdur)
+    m = len(active)
+    ab = (ctypes.c_size_t * max(m, 1))(*[a[0] for a in active])
+    at = (ctypes.c_int * max(m, 1))(*[a[1] for a in active])
+    ar = (ctypes.c_double * max(m, 1))(*[a[2] for a in active])
     sel = (ctypes.c_int * max(n, 1))()
-    k = lib.nh_serve_admit_select(b, t, w, n, used_bytes, used_blocks, float(budget), max_blocks, reserve_after, sel)
+    k = lib.nh_serve_admit_select(qb, qt, qd, n, ab, at, ar, m, float(budget), max_blocks, backfill, sel)
     return [sel[i] for i in range(k)]
 
 
-def admit(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks):
+def admit(lib, qbytes, qteams, used_bytes, used_blocks, budget, max_blocks):
     """Strict arrival order: the number of jobs admitted from the head."""
-    sel = select(lib, bytes_, teams, used_bytes, used_blocks, budget, max_blocks)
+    active = [(used_bytes, used_blocks, 1.0)] if (used_bytes or used_blocks) else []
+    sel = select(lib, qbytes, qteams, budget, max_blocks, active=active)
     assert sel == list(range(len(sel)))
     return len(sel)
 
@@ -52,30 +58,42 @@ def test_admit_prefix_by_workgroups(lib):
 
 
 def test_strict_order_blocks_behind_the_head(lib):
-    # reserve_after = 0: a large job at the head holds back smaller ones
     assert admit(lib, [100, 1, 1], [1, 1, 1], 0, 0, 50, 100) == 0
     assert admit(lib, [1, 100, 1], [1, 1, 1], 0, 0, 50, 100) == 1
 
 
-def test_backfill_until_the_head_is_reserved(lib):
-    # the 72-workgroup head does not fit in 60 free workgroups
-    teams = [72, 4, 1, 32, 1]
-    bytes_ = [1] * 5
-    # young head: jobs behind it that fit are admitted, in order
-    assert select(lib, bytes_, teams, 0, 196, 1e18, 256, waited=[3, 2, 1, 0, 0], reserve_after=16) == [1, 2, 3, 4]
-    # the head has waited long enough: it holds its place, nothing overtakes
-    assert select(lib, bytes_, teams, 0, 196, 1e18, 256, waited=[16, 2, 1, 0, 0], reserve_after=16) == []
-    # a younger job that does not fit stops only itself
-    assert select(lib, [1, 1, 1], [8, 300, 8], 0, 0, 1e18, 256, waited=[0, 5, 0], reserve_after=16) == [0, 2]
-    # a reserved job in the middle stops the walk there
-    assert select(lib, [1, 1, 1], [8, 300, 8], 0, 0, 1e18, 256, waited=[0, 20, 0], reserve_after=16) == [0]
-    # the budget applies to what was admitted before in the same walk
-    assert select(lib, [30, 30, 10], [1, 1, 1], 0, 0, 45, 256, waited=[0, 0, 0], reserve_after=16) == [0, 2]
+def test_easy_backfill(lib):
+    # 196 of 256 workgroups busy: 100 until t = 5 s, 96 until t = 9 s
+    active = [(1, 100, 5.0), (1, 96, 9.0)]
+    # the 144-workgroup head fits once the first job ends (t = 5): at that
+    # time 160 are free, 16 of them to spare
+    q_teams = [144, 8, 40, 30, 16, 4]
+    q_dur = [3.0, 2.0, 6.0, 4.0, 20.0, 1.0]
+    sel = select(lib, [1] * 6, q_teams, 1e18, 256, q_dur, active, backfill=1)
+    # job 1 (8, ends at 2 s) and job 3 (30, 4 s) end before t = 5 s; job 2 (40
+    # workgroups, 6 s) would delay the head; job 4 (16, 20 s) fits in the
+    # spare room; job 5 (4) still fits now but the spare room is used up and it
+    # ends before the shadow time, so it goes too
+    assert sel == [1, 3, 4, 5]
+    # strict order admits nothing
+    assert select(lib, [1] * 6, q_teams, 1e18, 256, q_dur, active, backfill=0) == []
+
+
+def test_easy_backfill_bytes(lib):
+    # the memory budget, not workgroups, holds the head back
+    active = [(60, 1, 5.0)]
+    sel = select(lib, [50, 30, 10], [1, 1, 1], 100, 256, [1.0, 9.0, 9.0], active, backfill=1)
+    # head needs 50 of 40 free bytes: shadow 5 s, spare 100 - 50 = 50 bytes;
+    # job 1 (30 bytes, 9 s) fits the spare room, job 2 (10 bytes) too
+    assert sel == [1, 2]
+    sel = select(lib, [50, 30, 25], [1, 1, 1], 100, 256, [1.0, 9.0, 9.0], active, backfill=1)
+    # after job 1 only 20 spare bytes remain: job 2 would delay the head
+    assert sel == [1]
 
 
 def test_admit_edge_cases(lib):
-    assert admit(lib, [], [], 0, 0, 10, 10) == 0
-    assert lib.nh_serve_admit_select(None, None, None, 3, 0, 0, 10.0, 10, 0, None) == 0
+    assert select(lib, [], [], 10, 10) == []
+    assert lib.nh_serve_admit_select(None, None, None, 3, None, None, None, 0, 10.0, 10, 0, None) == 0
 
 
 def test_job_team_sizes_streaming(lib):
