@@ -152,12 +152,12 @@ nh_status nh_set_cg_variant(nh_ctx *ctx, int variant);
 
 /* CG initial guess of every solve. The states of the preceding time levels
  * are h1 = T^{n-1}, h2 = T^{n-2}, h3 = T^{n-3} (forward) or mu^{n+1},
- * mu^{n+2}, mu^{n+3} (adjoint); their extrapolation is 2 h1 - h2 with two of
- * them and 3 h1 - 3 h2 + h3 with three. mode 0 starts from h1; mode 1 from
- * the extrapolation; mode 2 (default) adaptively: in each period of 32 steps
- * of a sweep the first step starts from h1 and the second from the
- * extrapolation, and the rest from whichever of the two took fewer CG
- * iterations (the choice is made on the device, so nothing synchronises).
+ * mu^{n+2}, mu^{n+3} (adjoint); the extrapolation of order 1 is 2 h1 - h2 and
+ * of order 2 is 3 h1 - 3 h2 + h3 (limited by the states there are). mode 0
+ * starts from h1 (order 0); mode 1 from the order-2 extrapolation; mode 2
+ * (default) adaptively: in each period of 32 steps of a sweep the first three
+ * steps start from orders 0, 1 and 2, and the rest from the order that took
+ * the fewest CG iterations (chosen on the device, so nothing synchronises).
  * All modes converge to the same tolerance. With checkpointing the three
  * states below each checkpoint are kept and recomputed steps repeat the
  * forward's choices, so recomputation stays bit for bit. Drops any saved

@@ -419,46 +419,32 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   return NH_OK;
 }
 
-// The previous state h1 and the CG initial guess. With two (three) earlier
-// states available the extrapolated guess is the linear (quadratic)
-// extrapolation 2 h1 - h2 (3 h1 - 3 h2 + h3) of the states at the preceding
-// time levels; otherwise, or when the policy says so, x0 = h1. Null states are
-// zero. Policy (c->guess): 0 always h1; 1 always the extrapolation; 2
-// adaptive: the steps of a sweep are taken in periods of kGuessPeriod; the
-// first step of a period starts from h1, the second from the extrapolation,
-// and the others from whichever of the two needed fewer iterations (the
-// kernel compares the counts in gi, written by the earlier launches).
-// j is the step's position in its sweep, step(j) the step number at
-// position j; gi is indexed by step number - 1.
+// The previous states h1..h3 and the CG initial-guess policy (c->guess): 0
+// x0 = h1; 1 the quadratic extrapolation 3 h1 - 3 h2 + h3 (linear with two
+// states); 2 adaptive: the steps of a sweep are taken in periods of
+// kGuessPeriod; its first three steps probe orders 0, 1 and 2, and the others
+// use the order whose probe needed the fewest iterations (the kernel compares
+// the counts in gi, written by earlier launches). j is the step's position in
+// its sweep, step(j) the step number at position j; gi is indexed by step
+// number - 1. Null states are zero.
 constexpr int kGuessPeriod = 32;
 
 template <typename R, typename StepOf>
 void set_guess(const nh_ctx* c, StepArgs<R>& S, const R* const (&h)[3], int j, const int* gi, StepOf step) {
   S.xprev = h[0];
-  S.xprev2 = S.xprev3 = nullptr;
-  S.ex1 = R(1);
-  S.ex2 = S.ex3 = R(0);
-  S.gmode = 0;
-  S.gi = nullptr;
-  S.gpw = S.gpe = -1;
-  if (!c->guess || !h[0] || !h[1]) return;
   S.xprev2 = h[1];
-  if (h[2]) {
-    S.xprev3 = h[2];
-    S.ex1 = R(3); S.ex2 = R(-3); S.ex3 = R(1);
-  } else {
-    S.ex1 = R(2); S.ex2 = R(-1);
-  }
-  if (c->guess == 1) {
-    S.gmode = 1;
+  S.xprev3 = h[2];
+  S.gi = nullptr;
+  S.gp[0] = S.gp[1] = S.gp[2] = 0;
+  if (c->guess != 2) {
+    S.gmode = c->guess == 0 ? 0 : 2;
     return;
   }
   const int k = j % kGuessPeriod;
-  S.gmode = k == 0 ? 0 : (k == 1 ? 1 : 2);
-  if (k >= 2) {
+  S.gmode = k < 3 ? k : -1;
+  if (k >= 3) {
     S.gi = gi;
-    S.gpw = step(j - k) - 1;
-    S.gpe = step(j - k + 1) - 1;
+    for (int d = 0; d < 3; ++d) S.gp[d] = step(j - k + d) - 1;
   }
 }
 

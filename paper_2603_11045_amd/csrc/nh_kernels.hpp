@@ -62,11 +62,10 @@ struct StepArgs {
   R* x;                                     // the unknown, solved in place
   const R* xprev;                           // the previous state h1: T^{n-1} or mu^{n+1} (null = zero)
   const R* xprev2;                          // h2, h3: the two states before it, for the initial guess
-  const R* xprev3;                          //   x0 = ex1 h1 + ex2 h2 + ex3 h3 (null: x0 = h1)
-  R ex1, ex2, ex3;
-  int gmode;                                // 0: x0 = h1; 1: the extrapolation; 2: the extrapolation
-  const int* gi;                            //   iff the step gi[gpe] took no more iterations than the
-  int gpw, gpe;                             //   step gi[gpw] (earlier steps of the same sweep)
+  const R* xprev3;                          //   (guess_order)
+  int gmode;                                // initial guess: extrapolation order 0, 1 or 2; or -1: the order
+  const int* gi;                            //   whose probe step gi[gp[order]] took the fewest iterations
+  int gp[3];                                //   (earlier steps of the same sweep)
   R* z;                                     // preconditioned residual
   R* p0;                                    // search direction, ping-pong pair
   R* p1;
@@ -746,10 +745,9 @@ struct StepVar {
   const R* xprev;
   const R* xprev2;
   const R* xprev3;
-  R ex1, ex2, ex3;
   int gmode;
   const int* gi;
-  int gpw, gpe;
+  int gp[3];
   const R* top_src;
   R top_scale;
   R* surf_out;
@@ -761,14 +759,25 @@ struct StepVar {
   unsigned long long epoch_base;
 };
 
-// Whether this step starts from the extrapolated initial guess. In mode 2
-// every workgroup reads the same two iteration counts, written by earlier
-// launches, so the choice is uniform over the team.
+// The CG initial guess of a step: x0 = h1 (order 0), the linear
+// extrapolation 2 h1 - h2 (order 1) or the quadratic one 3 h1 - 3 h2 + h3
+// (order 2) of the states at the preceding time levels, limited by the states
+// there are. In mode -1 the order is the one whose probe step took the fewest
+// iterations (ties: the higher order); every workgroup reads the same counts,
+// written by earlier launches, so the choice is uniform over the team.
 template <typename R>
-__device__ __forceinline__ bool use_extrapolation(const StepVar<R>& V) {
-  if (V.gmode == 0) return false;
-  if (V.gmode == 1 || !V.gi || V.gpw < 0 || V.gpe < 0) return true;
-  return V.gi[V.gpe] <= V.gi[V.gpw];
+__device__ __forceinline__ int guess_order(const StepVar<R>& V) {
+  int o = V.gmode;
+  if (o < 0) {
+    const int c0 = V.gi[V.gp[0]], c1 = V.gi[V.gp[1]], c2 = V.gi[V.gp[2]];
+    o = 2;
+    int best = c2;
+    if (c1 < best) { o = 1; best = c1; }
+    if (c0 < best) o = 0;
+  }
+  if (!V.xprev || !V.xprev2) return 0;
+  if (o == 2 && !V.xprev3) o = 1;
+  return o;
 }
 
 template <typename R>
@@ -778,13 +787,11 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   V.xprev = S.xprev;
   V.xprev2 = S.xprev2;
   V.xprev3 = S.xprev3;
-  V.ex1 = S.ex1;
-  V.ex2 = S.ex2;
-  V.ex3 = S.ex3;
   V.gmode = S.gmode;
   V.gi = S.gi;
-  V.gpw = S.gpw;
-  V.gpe = S.gpe;
+  V.gp[0] = S.gp[0];
+  V.gp[1] = S.gp[1];
+  V.gp[2] = S.gp[2];
   V.top_src = S.top_src;
   V.top_scale = S.top_scale;
   V.surf_out = S.surf_out;
@@ -822,9 +829,12 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
   init.nxy = g.nxy;
   init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
   init.src = V.xprev;
-  init.h2 = (V.xprev && use_extrapolation(V)) ? V.xprev2 : nullptr;
-  init.h3 = init.h2 ? V.xprev3 : nullptr;
-  init.e1 = V.ex1; init.e2 = V.ex2; init.e3 = V.ex3;
+  const int order = guess_order(V);
+  init.h2 = order >= 1 ? V.xprev2 : nullptr;
+  init.h3 = order == 2 ? V.xprev3 : nullptr;
+  init.e1 = R(order == 2 ? 3 : 2);
+  init.e2 = R(order == 2 ? -3 : -1);
+  init.e3 = R(1);
   init.xw = (V.xprev == V.x) ? nullptr : V.x;
   sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
   stamp();

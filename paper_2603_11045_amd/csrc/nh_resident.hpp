@@ -370,13 +370,15 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   // ---------------- set-up: x0, b, r = b - A x0, u = r / D; x = x0 in memory
   // x0 = h1 (the previous state), or its extrapolation ex1 h1 + ex2 h2 + ex3 h3
   const float* x0src = V.xprev;
-  const float* h2 = (x0src && use_extrapolation(V)) ? V.xprev2 : nullptr;
-  const float* h3 = h2 ? V.xprev3 : nullptr;
+  const int order = guess_order(V);
+  const float* h2 = order >= 1 ? V.xprev2 : nullptr;
+  const float* h3 = order == 2 ? V.xprev3 : nullptr;
+  const float e1 = order == 2 ? 3.f : 2.f, e2 = order == 2 ? -3.f : -1.f;
   auto x0_at = [&](int i) -> float {
     if (!h2) return x0src[i];
-    float v = V.ex2 * h2[i];
-    if (h3) v = fmaf(V.ex3, h3[i], v);
-    return fmaf(V.ex1, x0src[i], v);
+    float v = e2 * h2[i];
+    if (h3) v = fmaf(1.f, h3[i], v);
+    return fmaf(e1, x0src[i], v);
   };
   if (q.own && x0src) {
 #pragma unroll

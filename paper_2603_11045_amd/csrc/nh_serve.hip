@@ -86,11 +86,11 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
   // come from the per-step record, later ones from this loop.
   auto pos = [&](int nn) { return fwd ? nn - 1 : J.nsteps - nn; };
   auto slot_of = [&](int jj) { return fwd ? jj : 2 * J.nsteps - 1 - jj; };
-  int pw = -1, pe = -1;
+  int pc[3] = {-1, -1, -1};
   {
     const int j0 = pos(n), base = j0 - j0 % kGuessPeriod;
-    if (base < j0) pw = J.it_out[slot_of(base)];
-    if (base + 1 < j0) pe = J.it_out[slot_of(base + 1)];
+    for (int d = 0; d < 3; ++d)
+      if (base + d < j0) pc[d] = J.it_out[slot_of(base + d)];
   }
   const StepArgs<float>& S = (const StepArgs<float>&)J.S;
   const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
@@ -118,21 +118,26 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
       V.surf_out = nullptr;
       V.T_grad = J.traj + (long long)(n - 1) * ng;
     }
-    // extrapolation: quadratic (linear) with three (two) previous states
+    // initial guess: probes of orders 0, 1, 2 open each period, then the
+    // order whose probe needed the fewest iterations (ties: the higher)
     const int k = pos(n) % kGuessPeriod;
-    if (k == 0) pw = pe = -1;
+    if (k == 0) pc[0] = pc[1] = pc[2] = -1;
     V.xprev = h[0];
-    V.xprev2 = h[0] ? h[1] : nullptr;
-    V.xprev3 = V.xprev2 ? h[2] : nullptr;
-    V.ex1 = V.xprev3 ? 3.f : (V.xprev2 ? 2.f : 1.f);
-    V.ex2 = V.xprev3 ? -3.f : (V.xprev2 ? -1.f : 0.f);
-    V.ex3 = V.xprev3 ? 1.f : 0.f;
-    V.gmode = k == 0 ? 0 : (k == 1 || pw < 0 || pe < 0 || pe <= pw ? 1 : 0);
+    V.xprev2 = h[1];
+    V.xprev3 = h[2];
+    int order = 2;
+    if (k < 3) {
+      order = k;
+    } else if (pc[0] >= 0 && pc[1] >= 0 && pc[2] >= 0) {
+      int best = pc[2];
+      if (pc[1] < best) { order = 1; best = pc[1]; }
+      if (pc[0] < best) order = 0;
+    }
+    V.gmode = order;
     V.gi = nullptr;
-    V.gpw = V.gpe = -1;
+    V.gp[0] = V.gp[1] = V.gp[2] = 0;
     const StepResult r = step(S, V);
-    if (k == 0) pw = r.iters;
-    if (k == 1) pe = r.iters;
+    if (k < 3) pc[k] = r.iters;
     if (m.y == 0 && threadIdx.x == 0) {
       const int slot = (fwd ? 0 : J.nsteps) + n - 1;
       J.it_out[slot] = r.iters;
