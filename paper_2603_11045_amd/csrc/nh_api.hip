@@ -406,7 +406,7 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
     NH_TRY(ensure(c, c->vs0, vb));
     NH_TRY(ensure(c, c->vs1, vb));
   }
-  const size_t slot_bytes = sizeof(nh::Slot) * ((size_t)c->team + 1);
+  const size_t slot_bytes = sizeof(nh::Slot) * (2 * (size_t)c->team + 2);   // streaming: team + 1; resident: 2 banks
   if (c->slots.bytes < slot_bytes || !c->slots.p) {
     NH_TRY(ensure(c, c->slots, slot_bytes));
     NH_HIP(c, hipMemsetAsync(c->slots.p, 0, c->slots.bytes, c->stream));  // epoch 0 is never used

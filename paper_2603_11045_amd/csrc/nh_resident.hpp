@@ -47,10 +47,16 @@ constexpr size_t kResRingFloats = 3 * (size_t)kResTZ * kRing;          // [3 vec
 constexpr size_t kResLdsBytes =
     (kResAlphaFloats + kResPlaneFloats + kResRingFloats) * sizeof(float) + sizeof(ResRed) + 64;
 
-// Team reduction for the resident kernel: like team_sum, but every value
-// another workgroup reads was written with device-scope stores, so the
-// publication needs only the completion of this workgroup's stores (a full
-// s_waitcnt in every wave) and no cache maintenance.
+// Team reduction for the resident kernel. Every workgroup stores its sum in
+// its own slot and publishes it with the reduction's epoch; then EVERY
+// workgroup gathers all slots and sums them in the same fixed order, so all
+// obtain bit-identical results after one exchange (no master round trip).
+// Slots alternate between two banks by epoch parity: a workgroup can be at
+// most one reduction ahead of the slowest reader (the next reduction needs
+// every workgroup's slot), so a bank is never rewritten while still read.
+// Every value another workgroup reads was written with device-scope stores,
+// so the publication needs only the completion of this workgroup's stores (a
+// full s_waitcnt in every wave) and no cache maintenance. Slots: 2 * team.
 template <int NV>
 __device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank, unsigned long long& epoch,
                                              double (&v)[NV], ResRed* rs) {
@@ -58,61 +64,36 @@ __device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank,
   block_sum<NV, kResBlock / 64>(v, rs->red, rs->bc);
   if (S.team == 1) return true;
   const unsigned long long e = ++epoch;
-  Slot* slots = (Slot*)S.slots;
-  Slot* res = slots + S.team;
-  int ok = 1;
-  if (rank != 0) {
-    if (threadIdx.x == 0) {
+  Slot* slots = (Slot*)S.slots + (size_t)(e & 1) * S.team;
+  if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < NV; ++i)
-        __hip_atomic_store(&slots[rank].v[i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0);
-      __hip_atomic_store(&slots[rank].epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const long long t0 = wall_clock64();
-      while (ld_epoch(&res->epoch) != e) {
-        __builtin_amdgcn_s_sleep(2);
-        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
-      }
-#pragma unroll
-      for (int i = 0; i < NV; ++i) rs->bc[i] = ld_val(&res->v[i]);
-      rs->flag = ok;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = rs->bc[i];
-    ok = rs->flag;
-    __syncthreads();
-  } else {
-    double s[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) s[i] = 0.0;
-    for (int b = threadIdx.x; b < S.team; b += kResBlock) {
-      if (b == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) s[i] += v[i];
-        continue;
-      }
-      const long long t0 = wall_clock64();
-      while (ld_epoch(&slots[b].epoch) != e) {
-        __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
-      }
-#pragma unroll
-      for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
-    }
-    ok = __syncthreads_and(ok);
-    block_sum<NV, kResBlock / 64>(s, rs->red, rs->bc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-        __hip_atomic_store(&res->v[i], s[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0);
-      __hip_atomic_store(&res->epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = s[i];
+    for (int i = 0; i < NV; ++i)
+      __hip_atomic_store(&slots[rank].v[i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_store(&slots[rank].epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  double s[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) s[i] = 0.0;
+  int ok = 1;
+  for (int b = threadIdx.x; b < S.team; b += kResBlock) {
+    if (b == rank) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) s[i] += v[i];
+      continue;
+    }
+    const long long t0 = wall_clock64();
+    while (ld_epoch(&slots[b].epoch) != e) {
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
+  }
+  ok = __syncthreads_and(ok);
+  block_sum<NV, kResBlock / 64>(s, rs->red, rs->bc);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = s[i];
   if (!ok && threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
   return ok != 0;
 }

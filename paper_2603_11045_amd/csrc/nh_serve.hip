@@ -290,7 +290,7 @@ size_t job_bytes(int nx, int ny, int nz, int nsteps, int team) {
   b += align256(4 * nxy) + 3 * align256(4 * nxy * N);       // q_xy, target, S, dL/dS
   b += align256(4 * N);                                     // source scale per step
   b += 2 * align256(4 * 2 * N) + align256(8 * 2 * N);       // per-step iterations, status, residuals
-  b += align256(sizeof(nh::Slot) * ((size_t)team + 1));     // team reduction slots
+  b += align256(sizeof(nh::Slot) * (2 * (size_t)team + 2)); // team reduction slots (2 banks)
   b += align256(8 * kMseBlocks) + 256;                      // MSE partials, loss
   return b;
 }
@@ -403,7 +403,7 @@ nh_status admit(nh_server* s, SJob* j) {
   j->it_out = (int*)take(4 * 2 * N);
   j->st_out = (int*)take(4 * 2 * N);
   j->rel_out = (double*)take(8 * 2 * N);
-  j->slots = take(sizeof(nh::Slot) * ((size_t)j->team + 1));
+  j->slots = take(sizeof(nh::Slot) * (2 * (size_t)j->team + 2));
   j->partial = (double*)take(8 * kMseBlocks);
   j->lossbuf = (double*)take(256);
   if ((size_t)(p - (char*)j->mem) > j->bytes) return sfail(s, NH_EINVAL, "internal: job layout exceeds its size");
@@ -411,7 +411,7 @@ nh_status admit(nh_server* s, SJob* j) {
   SV_HIP(s, hipMemcpyAsync(j->qxy, j->h_qxy.data(), 4 * nxy, hipMemcpyHostToDevice, s->stream));
   SV_HIP(s, hipMemcpyAsync(j->target, j->h_target.data(), 4 * nxy * N, hipMemcpyHostToDevice, s->stream));
   SV_HIP(s, hipMemcpyAsync(j->qscale, j->h_qscale.data(), 4 * N, hipMemcpyHostToDevice, s->stream));
-  SV_HIP(s, hipMemsetAsync(j->slots, 0, sizeof(nh::Slot) * ((size_t)j->team + 1), s->stream));
+  SV_HIP(s, hipMemsetAsync(j->slots, 0, sizeof(nh::Slot) * (2 * (size_t)j->team + 2), s->stream));
   const int blocks = (int)std::min<size_t>((ng + 255) / 256, 2048);
   hipLaunchKernelGGL(nh::fill_kernel<double>, dim3(blocks), dim3(256), 0, s->stream, j->G, (long long)ng, 0.0);
   SV_HIP(s, hipGetLastError());
