@@ -182,6 +182,20 @@ def test_checkpoint_recompute_is_bitwise(variant):
             assert ck["stats_adj"]["recompute_iters"] == full["stats_fwd"]["fwd_iters"]
 
 
+def test_step_iters_add_up_to_the_stats():
+    w = wl.small_problem(40, 24, 10, 12, seed=9, dt=3.0, precision="f32", rtol=1e-6)
+    gs = wl.random_surface_weights(12, 24, 40, seed=19).astype(np.float32)
+    out = run_gpu(w, gs=gs, checkpoint_every=5)
+    s = out["solver"]
+    fi, ai, ri = s.step_iters("forward"), s.step_iters("adjoint"), s.step_iters("recompute")
+    assert fi.shape == (12,) and (fi > 0).all() and (ai > 0).all()
+    assert fi.sum() == out["stats_fwd"]["fwd_iters"]
+    assert ai.sum() == out["stats_adj"]["adj_iters"]
+    assert ri.sum() == out["stats_adj"]["recompute_iters"]
+    # recomputation repeats the forward step for step
+    assert np.array_equal(ri, fi)
+
+
 def test_runs_are_bitwise_deterministic():
     w = wl.small_problem(64, 40, 12, 6, seed=11, dt=4.0, precision="f32", rtol=1e-6)
     gs = wl.random_surface_weights(6, 40, 64, seed=21).astype(np.float32)
