@@ -94,7 +94,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
-              "(one problem per GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(one problem per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
