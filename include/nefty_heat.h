@@ -128,6 +128,17 @@ nh_status nh_forward_f64(nh_ctx *ctx, const double *alpha, const double *q_xy, c
                          double dt, int nsteps, double *T_surf);
 nh_status nh_adjoint_f64(nh_ctx *ctx, const double *dL_dTsurf, double *dL_dalpha);
 
+/* The adjoint sweep with the other two vector-Jacobian products it yields
+ * (App. D.3): besides dL/dalpha, dL_dq[nsteps][ny][nx] receives
+ * dL/dq^n = dt * mu^n on the top plane k = 0 (the sensitivity to the source
+ * of step n; chain it through q^n = q_t[n-1] * q_xy for q_xy and q_t) and
+ * dL_dT0[nz][ny][nx] receives mu^1 = dL/dT^0 (the sensitivity to the initial
+ * state). Either may be NULL. Same precision rules and errors as nh_adjoint /
+ * nh_adjoint_f64. */
+nh_status nh_adjoint_vjp(nh_ctx *ctx, const float *dL_dTsurf, double *dL_dalpha, float *dL_dq, float *dL_dT0);
+nh_status nh_adjoint_vjp_f64(nh_ctx *ctx, const double *dL_dTsurf, double *dL_dalpha, double *dL_dq,
+                             double *dL_dT0);
+
 /* Copy the saved state T^n (1 <= n <= nsteps, full storage; or a checkpoint
  * step when checkpointing) of the last forward into `out` ([nz][ny][nx],
  * device, the forward's precision). NH_ESTATE if that state is not held. */

@@ -463,6 +463,7 @@ nh_status forward_step(nh_ctx* c, int n, const R* const (&h)[3], R* x, const R* 
   S.top_src = q_xy;
   S.top_scale = (R)(dt * qt);
   S.surf_out = surf;
+  S.surf_scale = R(1);
   S.ckpt_out = ckpt;
   StepOut o = step_out(c, region, n - 1);
   S.out_iters = o.iters;
@@ -614,7 +615,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
 }
 
 template <typename R>
-nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
+nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   auto t0 = std::chrono::steady_clock::now();
   if (!c) return NH_EINVAL;
   if (!gsurf || !G) return fail(c, NH_EINVAL, "null pointer argument");
@@ -643,6 +644,8 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
     base_args<R>(c, S, dt);
     S.mode = nh::kAdjoint;
     S.x = M[n & 3];
+    S.surf_out = dq ? dq + (size_t)(n - 1) * g.nxy : nullptr;   // dL/dq^n = dt mu^n on k = 0
+    S.surf_scale = (R)dt;
     const R* const h[3] = {mu_state(n + 1), mu_state(n + 2), mu_state(n + 3)};
     set_guess<R>(c, S, h, N - n, step_out(c, 1, 0).iters, [N](int jj) { return N - jj; });
     S.top_src = gsurf + (size_t)(n - 1) * g.nxy;
@@ -692,6 +695,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G) {
       for (int n = e; n >= s + 1; --n) NH_TRY(adj_step(n, seg + (size_t)(n - s - 1) * g.ng));
     }
   }
+  if (dT0) NH_HIP(c, hipMemcpyAsync(dT0, M[1 & 3], vb, hipMemcpyDeviceToDevice, c->stream));   // mu^1
   NH_TRY(collect_events(c, used, &tk));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   c->st.t_kernel_adj_s = tk;
@@ -817,7 +821,7 @@ nh_status nh_forward(nh_ctx* c, const float* alpha, const float* q_xy, const dou
 }
 
 nh_status nh_adjoint(nh_ctx* c, const float* dL_dTsurf, double* dL_dalpha) {
-  return do_adjoint<float>(c, dL_dTsurf, dL_dalpha);
+  return do_adjoint<float>(c, dL_dTsurf, dL_dalpha, nullptr, nullptr);
 }
 
 nh_status nh_forward_f64(nh_ctx* c, const double* alpha, const double* q_xy, const double* q_t, double dt,
@@ -826,7 +830,16 @@ nh_status nh_forward_f64(nh_ctx* c, const double* alpha, const double* q_xy, con
 }
 
 nh_status nh_adjoint_f64(nh_ctx* c, const double* dL_dTsurf, double* dL_dalpha) {
-  return do_adjoint<double>(c, dL_dTsurf, dL_dalpha);
+  return do_adjoint<double>(c, dL_dTsurf, dL_dalpha, nullptr, nullptr);
+}
+
+nh_status nh_adjoint_vjp(nh_ctx* c, const float* dL_dTsurf, double* dL_dalpha, float* dL_dq, float* dL_dT0) {
+  return do_adjoint<float>(c, dL_dTsurf, dL_dalpha, dL_dq, dL_dT0);
+}
+
+nh_status nh_adjoint_vjp_f64(nh_ctx* c, const double* dL_dTsurf, double* dL_dalpha, double* dL_dq,
+                             double* dL_dT0) {
+  return do_adjoint<double>(c, dL_dTsurf, dL_dalpha, dL_dq, dL_dT0);
 }
 
 nh_status nh_get_state(nh_ctx* c, int n, void* out) {

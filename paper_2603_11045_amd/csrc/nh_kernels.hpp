@@ -77,7 +77,8 @@ struct StepArgs {
   int variant;                              // 0: two reductions per iteration, 1: one
   const R* top_src;                         // [ny][nx] added on k = 0 (forward q_xy, adjoint g^n)
   R top_scale;                              // forward dt*q_t[n-1], adjoint 1
-  R* surf_out;                              // forward: frame of T^n on k = 0 (or null)
+  R* surf_out;                              // frame of the solution on k = 0 (or null), times
+  R surf_scale;                             //   surf_scale in the adjoint (dt: dL/dq^n = dt mu^n)
   R* ckpt_out;                              // forward: copy of T^n (or null)
   const R* T_grad;                          // adjoint: T^n for the gradient (or null)
   double* G;                                // adjoint: dL/dalpha accumulator
@@ -751,6 +752,7 @@ struct StepVar {
   const R* top_src;
   R top_scale;
   R* surf_out;
+  R surf_scale;
   R* ckpt_out;
   const R* T_grad;
   int* out_iters;
@@ -795,6 +797,7 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   V.top_src = S.top_src;
   V.top_scale = S.top_scale;
   V.surf_out = S.surf_out;
+  V.surf_scale = S.surf_scale;
   V.ckpt_out = S.ckpt_out;
   V.T_grad = S.T_grad;
   V.out_iters = S.out_iters;
@@ -944,7 +947,11 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
     } else if (V.surf_out) {
       top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.x[col]; });
     }
-  } else if (V.T_grad && ok) {
+  } else {
+    if (V.surf_out)
+      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.surf_scale * V.x[col]; });
+  }
+  if (S.mode == kAdjoint && V.T_grad && ok) {
     GradOp<R> Gop;
     Gop.alpha = S.alpha; Gop.mu = V.x; Gop.T = V.T_grad; Gop.G = S.G;
     Gop.sx = S.sx; Gop.sy = S.sy; Gop.sz = S.sz;

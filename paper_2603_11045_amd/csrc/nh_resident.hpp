@@ -565,7 +565,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   // ---------------- epilogue: surface frame, checkpoint copy; for the gradient
   // the final x on the tile's faces is republished with device-scope stores
   if (q.own) {
-    if (S.mode == kForward && V.surf_out && T.z0 == 0) V.surf_out[q.col] = xtop;
+    if (V.surf_out && T.z0 == 0) V.surf_out[q.col] = S.mode == kForward ? xtop : V.surf_scale * xtop;
     if (V.ckpt_out) {
       for (int z = 0; z < q.tzn; ++z) {
         const int i = q.col + (T.z0 + z) * nxy;

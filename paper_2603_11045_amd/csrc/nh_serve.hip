@@ -109,6 +109,7 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
       V.top_src = J.S.top_src;
       V.top_scale = J.qscale[n - 1];
       V.surf_out = J.surf + (long long)(n - 1) * nxy;
+      V.surf_scale = 1.f;
       V.T_grad = nullptr;
     } else {
       V.x = J.mu[n & 3];
@@ -116,6 +117,7 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
       V.top_src = J.gsurf + (long long)(n - 1) * nxy;
       V.top_scale = 1.f;
       V.surf_out = nullptr;
+      V.surf_scale = 1.f;
       V.T_grad = J.traj + (long long)(n - 1) * ng;
     }
     // initial guess: probes of orders 0, 1, 2 open each period, then the

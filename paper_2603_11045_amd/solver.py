@@ -147,6 +147,20 @@ class Solver:
         self.last_status = _check(code, self._ctx, "nh_adjoint", allow)
         return out
 
+    def adjoint_vjp(self, dL_dTsurf: torch.Tensor, allow_noconv: bool = False):
+        """``(dL/dalpha, dL/dq, dL/dT0)`` of the last forward: ``dL/dq`` is
+        ``[nsteps][ny][nx]`` (``dt * mu^n`` on the top plane, the sensitivity
+        to the source of step n) and ``dL/dT0 = mu^1`` is ``[nz][ny][nx]``."""
+        _dev_tensor(dL_dTsurf, "dL_dTsurf", self.dtype, self.nsteps * self.nx * self.ny)
+        G = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        dq = torch.empty((self.nsteps, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        dT0 = torch.empty((self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        fn = self.lib.nh_adjoint_vjp if self.precision == "f32" else self.lib.nh_adjoint_vjp_f64
+        code = fn(self._ctx, dL_dTsurf.data_ptr(), G.data_ptr(), dq.data_ptr(), dT0.data_ptr())
+        allow = (_lib.NH_ENOCONV,) if allow_noconv else ()
+        self.last_status = _check(code, self._ctx, "nh_adjoint_vjp", allow)
+        return G, dq, dT0
+
     def get_state(self, n: int) -> torch.Tensor:
         out = torch.empty((self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         _check(self.lib.nh_get_state(self._ctx, int(n), out.data_ptr()), self._ctx, "nh_get_state")
@@ -191,18 +205,24 @@ class HeatSolve(torch.autograd.Function):
     """``T_surf = HeatSolve.apply(alpha, solver, q_xy, q_t, dt, nsteps)``.
 
     Backward runs the library's adjoint sweep and returns ``dL/dalpha`` in
-    ``alpha``'s dtype (accumulated in FP64). If the solver ran another forward
-    in between, the forward of this call is recomputed first.
+    ``alpha``'s dtype (accumulated in FP64), and, when they require grad, the
+    gradients of the source map ``q_xy`` and of the schedule ``q_t`` (a torch
+    tensor then) from ``dL/dq^n = dt mu^n`` on the top plane and
+    ``q^n = q_t[n-1] q_xy``. If the solver ran another forward in between, the
+    forward of this call is recomputed first.
     """
 
     @staticmethod
     def forward(ctx, alpha, solver: Solver, q_xy, q_t, dt, nsteps):
         a = alpha.detach().to(solver.dtype).contiguous()
-        T = solver.forward(a, q_xy, q_t, dt, nsteps)
+        q = q_xy.detach().to(solver.dtype).contiguous()
+        qt = q_t.detach().cpu().double().numpy() if isinstance(q_t, torch.Tensor) else q_t
+        T = solver.forward(a, q, qt, dt, nsteps)
         ctx.solver = solver
         ctx.gen = solver.generation
-        ctx.args = (q_xy, q_t, dt, nsteps)
-        ctx.alpha_dtype = alpha.dtype
+        ctx.args = (q, qt, dt, nsteps)
+        ctx.dtypes = (alpha.dtype, q_xy.dtype, q_t.dtype if isinstance(q_t, torch.Tensor) else None)
+        ctx.q_t_device = q_t.device if isinstance(q_t, torch.Tensor) else None
         ctx.save_for_backward(a)
         return T
 
@@ -212,8 +232,21 @@ class HeatSolve(torch.autograd.Function):
         (a,) = ctx.saved_tensors
         if solver.generation != ctx.gen:
             solver.forward(a, *ctx.args)
-        G = solver.adjoint(g.detach().to(solver.dtype).contiguous())
-        return G.to(ctx.alpha_dtype), None, None, None, None, None
+        gg = g.detach().to(solver.dtype).contiguous()
+        want_q = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        d_qxy = d_qt = None
+        if want_q:
+            G, dq, _ = solver.adjoint_vjp(gg)
+            q, qt, _, nsteps = ctx.args
+            qt_t = torch.as_tensor(np.asarray(qt, dtype=np.float64), device=dq.device)
+            dq64 = dq.double()
+            if ctx.needs_input_grad[2]:
+                d_qxy = (qt_t[:, None, None] * dq64).sum(dim=0).to(ctx.dtypes[1])
+            if ctx.needs_input_grad[3]:
+                d_qt = (dq64 * q.double()).sum(dim=(1, 2)).to(device=ctx.q_t_device, dtype=ctx.dtypes[2])
+        else:
+            G = solver.adjoint(gg)
+        return G.to(ctx.dtypes[0]), None, d_qxy, d_qt, None, None
 
 
 def heat_solve(alpha, solver: Solver, q_xy, q_t, dt, nsteps):

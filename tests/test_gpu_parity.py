@@ -234,6 +234,66 @@ def test_heat_solve_autograd_matches_adjoint_and_gradcheck():
                                     atol=1e-7, rtol=1e-5)
 
 
+# ------------------------------------------------------------------ source and initial-state VJPs
+VJP_CASES = [((20, 12, 6), 7, "f64"), ((20, 12, 6), 7, "f32"), ((70, 40, 9), 5, "f32"), ((64, 8, 20), 6, "f32")]
+
+
+@pytest.mark.parametrize("shape,nsteps,precision", VJP_CASES)
+def test_adjoint_vjp_source_and_initial_state(shape, nsteps, precision):
+    """dL/dq^n = dt mu^n on the top plane and dL/dT0 = mu^1 (App. D.3) against
+    the oracle's adjoint; with checkpointing they are bit for bit the same."""
+    nx, ny, nz = shape
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=17, dt=2.0, precision=precision, pulse_steps=2,
+                         rtol=1e-13 if precision == "f64" else 1e-7)
+    gs = wl.random_surface_weights(nsteps, ny, nx, seed=23)
+    src = orc.source_series(w.q_xy, w.q_t)
+    _, T_o, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-13)
+    G_o, dq_o, mu1_o, _ = orc.adjoint(w.alpha, T_o, gs, w.dt, rtol=1e-13)
+    dt_t = torch.float32 if precision == "f32" else torch.float64
+    outs = []
+    for k in (0, 3):
+        s = Solver(nx, ny, nz, rtol=w.rtol, max_iter=5000, checkpoint_every=k, precision=precision)
+        s.forward(to_dev(w.alpha, dt_t), to_dev(w.q_xy, dt_t), w.q_t, w.dt, nsteps)
+        G, dq, dT0 = s.adjoint_vjp(to_dev(gs, dt_t))
+        outs.append((G.cpu().numpy(), dq.cpu().numpy(), dT0.cpu().numpy(), s.stats()["resident"]))
+    G, dq, dT0, res = outs[0]
+    e = (rel_l2(G, G_o), rel_l2(dq, dq_o), rel_l2(dT0, mu1_o))
+    say(shape, precision, "resident", res, "rel-L2 G, dq, dT0:", e)
+    tol = (1e-8, 1e-9, 1e-9) if precision == "f64" else (1e-4, 1e-5, 1e-5)
+    assert all(x <= t for x, t in zip(e, tol))
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(a, b)
+    # the plain adjoint gives the same dL/dalpha
+    s = Solver(nx, ny, nz, rtol=w.rtol, max_iter=5000, precision=precision)
+    s.forward(to_dev(w.alpha, dt_t), to_dev(w.q_xy, dt_t), w.q_t, w.dt, nsteps)
+    assert np.array_equal(s.adjoint(to_dev(gs, dt_t)).cpu().numpy(), G)
+
+
+def test_heat_solve_source_gradients():
+    """Autograd through HeatSolve for the source map and schedule: against
+    the chain rule through the oracle's dL/dq^n, and gradcheck."""
+    nx, ny, nz, nsteps = 5, 4, 3, 4
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=13, dt=1.5, precision="f64", rtol=1e-13)
+    s = Solver(nx, ny, nz, rtol=1e-13, max_iter=2000, precision="f64")
+    a = to_dev(w.alpha, torch.float64)
+    q = to_dev(w.q_xy, torch.float64).requires_grad_(True)
+    qt = torch.tensor(w.q_t, dtype=torch.float64, requires_grad=True)
+    T = HeatSolve.apply(a, s, q, qt, w.dt, nsteps)
+    gs = torch.from_numpy(wl.random_surface_weights(nsteps, ny, nx, seed=31)).cuda()
+    (T * gs).sum().backward()
+    src = orc.source_series(w.q_xy, w.q_t)
+    _, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    _, dq_o, _, _ = orc.adjoint(w.alpha, T_o, gs.cpu().numpy(), w.dt)
+    gq_o = np.einsum("n,nij->ij", np.asarray(w.q_t), dq_o)
+    gqt_o = np.einsum("nij,ij->n", dq_o, np.asarray(w.q_xy))
+    assert rel_l2(q.grad.cpu().numpy(), gq_o) <= 1e-9
+    assert rel_l2(qt.grad.numpy(), gqt_o) <= 1e-9
+    f = lambda qq, tt: HeatSolve.apply(a, s, qq, tt, w.dt, nsteps)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (q.detach().clone().requires_grad_(True),
+                                        qt.detach().clone().requires_grad_(True)),
+                                    eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
 # ------------------------------------------------------------------ error paths
 def test_error_paths():
     nx, ny, nz = 8, 6, 4
