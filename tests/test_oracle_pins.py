@@ -106,6 +106,21 @@ def test_adjoint_dot_product_source_map():
     assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0)
 
 
+def test_adjoint_dot_product_initial_state():
+    """With no source, T^0 -> S is linear and its transpose applied to w is
+    mu^1 (the adjoint recurrence run down to n = 1, eq. adjoint_eq): the
+    initial-state gradient of the linear functional <w, S>."""
+    alpha, _, w = _rand_problem((5, 6, 7), 6, seed=14)
+    dt = 2.5
+    T0 = np.random.default_rng(15).standard_normal(alpha.shape)
+    src = np.zeros((6,) + alpha.shape[1:])
+    S, T_all, _ = orc.forward(alpha, src, dt, T0=T0, rtol=1e-14)
+    _, _, mu1, _ = orc.adjoint(alpha, T_all, w, dt, rtol=1e-14)
+    lhs = np.sum(S * w)
+    rhs = np.sum(T0 * mu1)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), 1.0)
+
+
 def test_tangent_linear_vs_adjoint():
     """<J v, w> = <v, J^T w> with J = dS/dalpha: TLM against the adjoint gradient."""
     alpha, src, w = _rand_problem((5, 6, 7), 6, seed=5)
