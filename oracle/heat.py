@@ -38,7 +38,8 @@ def build(force: bool = False) -> str:
 
 class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
-                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double)]
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("periodic", ctypes.c_int), ("beta", ctypes.c_double), ("jacobi_k", ctypes.c_int)]
 
 
 _lib = None
@@ -54,6 +55,8 @@ def _load():
         g = P(_Grid)
         lib.orc_apply_A.argtypes = [g, dp, ctypes.c_double, dp, dp]
         lib.orc_diagonal.argtypes = [g, dp, ctypes.c_double, dp]
+        lib.orc_apply_R.argtypes = [g, dp, ctypes.c_double, dp, dp]
+        lib.orc_jacobi.argtypes = [g, dp, ctypes.c_double, dp, dp, dp, ctypes.c_int]
         lib.orc_pcg.argtypes = [g, dp, ctypes.c_double, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
         lib.orc_pcg.restype = ctypes.c_int
         lib.orc_forward.argtypes = [g, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
@@ -80,39 +83,59 @@ def _ptr(a: Optional[np.ndarray]):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _grid(alpha: np.ndarray, h=(1.0, 1.0, 1.0)) -> _Grid:
+def _grid(alpha: np.ndarray, h=(1.0, 1.0, 1.0), periodic=False, robin=0.0, jacobi_k=0) -> _Grid:
+    """Grid, closure and inner solver: ``periodic`` wraps the lateral faces
+    (needs nx, ny >= 3), ``robin`` is the coefficient h of the back-face
+    condition n.(alpha grad T) = -h T (sink beta = h / dz on k = nz-1),
+    ``jacobi_k`` > 0 replaces Jacobi-PCG by that many Jacobi sweeps."""
     nz, ny, nx = alpha.shape
-    return _Grid(nx, ny, nz, float(h[0]), float(h[1]), float(h[2]))
+    if periodic and (nx < 3 or ny < 3):
+        raise ValueError("lateral periodicity needs nx, ny >= 3")
+    if robin < 0 or jacobi_k < 0:
+        raise ValueError("robin and jacobi_k must be >= 0")
+    return _Grid(nx, ny, nz, float(h[0]), float(h[1]), float(h[2]), int(bool(periodic)),
+                 float(robin) / float(h[2]), int(jacobi_k))
 
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
-def apply_A(alpha, x, dt, h=(1.0, 1.0, 1.0)) -> np.ndarray:
+def apply_A(alpha, x, dt, h=(1.0, 1.0, 1.0), periodic=False, robin=0.0) -> np.ndarray:
     """``A x`` with ``A = I + dt L+(alpha)``."""
     a, xx = _d(alpha), _d(x)
     y = np.empty_like(a)
-    _load().orc_apply_A(ctypes.byref(_grid(a, h)), _ptr(a), float(dt), _ptr(xx), _ptr(y))
+    _load().orc_apply_A(ctypes.byref(_grid(a, h, periodic, robin)), _ptr(a), float(dt), _ptr(xx), _ptr(y))
     return y
 
 
-def diagonal(alpha, dt, h=(1.0, 1.0, 1.0)) -> np.ndarray:
+def diagonal(alpha, dt, h=(1.0, 1.0, 1.0), periodic=False, robin=0.0) -> np.ndarray:
     a = _d(alpha)
     d = np.empty_like(a)
-    _load().orc_diagonal(ctypes.byref(_grid(a, h)), _ptr(a), float(dt), _ptr(d))
+    _load().orc_diagonal(ctypes.byref(_grid(a, h, periodic, robin)), _ptr(a), float(dt), _ptr(d))
     return d
 
 
-def solve(alpha, b, dt, x0=None, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter=DEFAULT_MAX_ITER):
+def solve(alpha, b, dt, x0=None, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter=DEFAULT_MAX_ITER,
+          periodic=False, robin=0.0):
     """Solve ``A x = b`` by Jacobi-PCG from ``x0`` (default 0). Returns (x, iters, rel_res)."""
     a, bb = _d(alpha), _d(b)
     x = np.zeros_like(a) if x0 is None else _d(x0).copy()
-    dg = diagonal(a, dt, h)
+    dg = diagonal(a, dt, h, periodic, robin)
     rel = ctypes.c_double(0.0)
-    it = _load().orc_pcg(ctypes.byref(_grid(a, h)), _ptr(a), float(dt), _ptr(dg), _ptr(bb),
-                         _ptr(x), float(rtol), int(max_iter), ctypes.byref(rel))
+    it = _load().orc_pcg(ctypes.byref(_grid(a, h, periodic, robin)), _ptr(a), float(dt), _ptr(dg),
+                         _ptr(bb), _ptr(x), float(rtol), int(max_iter), ctypes.byref(rel))
     return x, int(it), float(rel.value)
+
+
+def jacobi(alpha, b, dt, x0, K, h=(1.0, 1.0, 1.0), periodic=False, robin=0.0):
+    """``K`` Jacobi sweeps ``x <- D^-1 (b - R x)`` on ``A x = b`` from ``x0`` (eq. jacobi_iter)."""
+    a, bb = _d(alpha), _d(b)
+    x = _d(x0).copy()
+    dg = diagonal(a, dt, h, periodic, robin)
+    _load().orc_jacobi(ctypes.byref(_grid(a, h, periodic, robin)), _ptr(a), float(dt), _ptr(dg),
+                       _ptr(bb), _ptr(x), int(K))
+    return x
 
 
 def source_series(q_xy, q_t) -> np.ndarray:
@@ -121,12 +144,14 @@ def source_series(q_xy, q_t) -> np.ndarray:
 
 
 def forward(alpha, src, dt, T0=None, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL,
-            max_iter=DEFAULT_MAX_ITER, keep_states=True):
+            max_iter=DEFAULT_MAX_ITER, keep_states=True, periodic=False, robin=0.0, jacobi_k=0):
     """Forward sweep. ``src`` is ``[nsteps][ny][nx]``.
 
     Returns ``(S, T_all, iters)``: surface series ``[nsteps][ny][nx]``, all
-    states ``[nsteps][nz][ny][nx]`` (None unless ``keep_states``) and the CG
-    iterations per step. Raises if a solve does not converge.
+    states ``[nsteps][nz][ny][nx]`` (None unless ``keep_states``) and the
+    inner-solver iterations per step. Raises if a solve does not converge.
+    ``periodic``, ``robin`` and ``jacobi_k`` choose the closure and the inner
+    solver (see ``_grid``).
     """
     a, s = _d(alpha), _d(src)
     nz, ny, nx = a.shape
@@ -136,7 +161,8 @@ def forward(alpha, src, dt, T0=None, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL,
     T_all = np.empty((nsteps, nz, ny, nx)) if keep_states else None
     iters = np.empty(nsteps, dtype=np.int32)
     t0 = None if T0 is None else _d(T0)
-    st = _load().orc_forward(ctypes.byref(_grid(a, h)), _ptr(a), _ptr(s), _ptr(t0), float(dt),
+    grid = _grid(a, h, periodic, robin, jacobi_k)
+    st = _load().orc_forward(ctypes.byref(grid), _ptr(a), _ptr(s), _ptr(t0), float(dt),
                              int(nsteps), float(rtol), int(max_iter), _ptr(S), _ptr(T_all),
                              iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     if st != 0:
@@ -144,7 +170,8 @@ def forward(alpha, src, dt, T0=None, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL,
     return S, T_all, iters
 
 
-def adjoint(alpha, T_all, gs, dt, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter=DEFAULT_MAX_ITER):
+def adjoint(alpha, T_all, gs, dt, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter=DEFAULT_MAX_ITER,
+            periodic=False, robin=0.0, jacobi_k=0):
     """Adjoint sweep. ``gs = dJ/dS`` is ``[nsteps][ny][nx]``.
 
     Returns ``(G, dq, mu1, iters)``: ``dJ/dalpha`` ``[nz][ny][nx]``,
@@ -159,7 +186,8 @@ def adjoint(alpha, T_all, gs, dt, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter
     dq = np.empty((nsteps, ny, nx))
     mu1 = np.empty_like(a)
     iters = np.empty(nsteps, dtype=np.int32)
-    st = _load().orc_adjoint(ctypes.byref(_grid(a, h)), _ptr(a), float(dt), int(nsteps), _ptr(T),
+    grid = _grid(a, h, periodic, robin, jacobi_k)
+    st = _load().orc_adjoint(ctypes.byref(grid), _ptr(a), float(dt), int(nsteps), _ptr(T),
                              _ptr(g), float(rtol), int(max_iter), _ptr(G), _ptr(dq), _ptr(mu1),
                              iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     if st != 0:
@@ -167,13 +195,14 @@ def adjoint(alpha, T_all, gs, dt, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter
     return G, dq, mu1, iters
 
 
-def tlm(alpha, v, T_all, dt, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter=DEFAULT_MAX_ITER):
+def tlm(alpha, v, T_all, dt, h=(1.0, 1.0, 1.0), rtol=DEFAULT_RTOL, max_iter=DEFAULT_MAX_ITER,
+        periodic=False, robin=0.0):
     """Directional derivative ``dS`` of the surface series along ``v`` (alpha direction)."""
     a, vv, T = _d(alpha), _d(v), _d(T_all)
     nz, ny, nx = a.shape
     nsteps = T.shape[0]
     dS = np.empty((nsteps, ny, nx))
-    st = _load().orc_tlm(ctypes.byref(_grid(a, h)), _ptr(a), _ptr(vv), float(dt), int(nsteps),
+    st = _load().orc_tlm(ctypes.byref(_grid(a, h, periodic, robin)), _ptr(a), _ptr(vv), float(dt), int(nsteps),
                          _ptr(T), float(rtol), int(max_iter), _ptr(dS))
     if st != 0:
         raise RuntimeError("oracle tlm: a solve did not converge")
@@ -191,11 +220,12 @@ def run_workload(w, rtol=DEFAULT_RTOL, with_adjoint=True):
     """Forward of ``w.alpha``, target surface from ``w.alpha_target``, MSE
     gradient and adjoint. Returns a dict of FP64 arrays."""
     src = source_series(w.q_xy, w.q_t)
-    S, T_all, it_f = forward(w.alpha, src, w.dt, h=w.h, rtol=rtol)
-    St, _, _ = forward(w.alpha_target, src, w.dt, h=w.h, rtol=rtol, keep_states=False)
+    opt = dict(h=w.h, rtol=rtol, periodic=w.periodic, robin=w.robin, jacobi_k=w.jacobi_k)
+    S, T_all, it_f = forward(w.alpha, src, w.dt, **opt)
+    St, _, _ = forward(w.alpha_target, src, w.dt, keep_states=False, **opt)
     L, gs = mse_loss_and_grad(S, St)
     out = dict(S=S, S_target=St, loss=L, gs=gs, iters_fwd=it_f, T_all=T_all)
     if with_adjoint:
-        G, dq, mu1, it_a = adjoint(w.alpha, T_all, gs, w.dt, h=w.h, rtol=rtol)
+        G, dq, mu1, it_a = adjoint(w.alpha, T_all, gs, w.dt, **opt)
         out.update(G=G, dq=dq, mu1=mu1, iters_adj=it_a)
     return out

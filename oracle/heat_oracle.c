@@ -9,21 +9,31 @@
  * A = I - dt*L with L = -L+):
  *
  *   face conductance   c_f = 2 a_p a_q / (a_p + a_q) / h_d^2       (Prop. 1, eq. fv_stencil)
- *   operator           (L+ x)_p = sum_{interior faces f=(p,q)} c_f (x_p - x_q)
- *                      boundary faces carry no term (zero flux on all six faces)
+ *   operator           (L+ x)_p = beta_p x_p + sum_{interior faces f=(p,q)} c_f (x_p - x_q)
+ *                      boundary faces carry no term (zero flux), except that
+ *                      - with lateral periodicity the x and y faces wrap around
+ *                        (circular padding, App. D.2), so cell 0 and cell n-1 of
+ *                        a row share a face;
+ *                      - with a Robin back face the rows k = nz-1 carry the sink
+ *                        beta_p = h/dz (App. D.2, "Symmetry, sign, and diagonal
+ *                        dominance"); every other row has beta_p = 0
  *   state equation     A T^n = T^{n-1} + dt q^n,   T^0 = 0          (eq. state_eq plus a source)
  *   observation        S^n = T^n restricted to the plane k = 0      (the projector Pi of eq. nefty_obj)
  *   adjoint            A mu^n = mu^{n+1} + Pi^T g^n,  mu^{N+1} = 0  (eq. adjoint_eq; A symmetric)
  *   gradient           dJ/da_p = -dt sum_n sum_{f ni p} dc_f/da_p (T_p-T_q)(mu_p-mu_q)
  *                      dc_f/da_p = 2 a_q^2 / (a_p + a_q)^2 / h_d^2   (eq. grad_assembly and the
- *                      harmonic-mean derivative of App. D.3)
+ *                      harmonic-mean derivative of App. D.3; the Robin sink
+ *                      does not depend on alpha and adds nothing)
  *   source sensitivity dJ/dq^n = dt * mu^n on k = 0
  *
- * Every linear solve is a plain Jacobi-preconditioned conjugate gradient in
- * FP64, run to a tight relative residual (1e-13 by default), so the result
- * is the exact discrete trajectory up to that tolerance.  The paper's own
- * inner solver (a fixed number of Jacobi sweeps, App. D.2) reaches the same
- * fixed point.  Nothing is fused or blocked: each step is one function.
+ * By default every linear solve is a plain Jacobi-preconditioned conjugate
+ * gradient in FP64, run to a tight relative residual (1e-13 by default), so
+ * the result is the exact discrete trajectory up to that tolerance.  The
+ * paper's own inner solver can be chosen instead: K plain Jacobi sweeps
+ * x <- D^-1 (b - R x), A = D + R, started from the previous time level's
+ * state (eq. jacobi_iter, App. D.2); the adjoint solves take the same K
+ * sweeps from mu^{n+1} (App. D.3 uses the same inner solver both ways).
+ * Nothing is fused or blocked: each step is one function.
  *
  * Layout: volumes are [nz][ny][nx], x fastest; k = 0 is the top face.
  */
@@ -31,9 +41,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The grid, its boundary closure and the inner solver. */
 typedef struct {
     int nx, ny, nz;
     double hx, hy, hz;
+    int periodic;   /* 1: the lateral x and y faces wrap around (needs nx, ny >= 3); 0: zero flux */
+    double beta;    /* Robin sink rate h/dz on the back-face rows k = nz-1; 0: adiabatic back face */
+    int jacobi_k;   /* 0: Jacobi-PCG to rtol; K > 0: K Jacobi sweeps per solve */
 } orc_grid;
 
 static long long ng_of(const orc_grid *g) { return (long long)g->nx * g->ny * g->nz; }
@@ -52,17 +66,48 @@ static double dconductance(double ap, double aq, double h) {
     return 2.0 * aq * aq / ((ap + aq) * (ap + aq)) / (h * h);
 }
 
-/* Calls f(p, q, h) once for every interior face (p, q) of the grid. The
- * neighbour q is the +x, +y or +z cell of p. */
+/* Index of the cell one step from (i, j, k) along axis d (0: x, 1: y, 2: z)
+ * in direction s (-1 or +1), or -1 where that side of the cell is a boundary
+ * face. Lateral periodicity wraps x and y; z never wraps. */
+static long long neighbour(const orc_grid *g, int i, int j, int k, int d, int s) {
+    if (d == 0) {
+        i += s;
+        if (i < 0 || i >= g->nx) {
+            if (!g->periodic) return -1;
+            i = (i + g->nx) % g->nx;
+        }
+    } else if (d == 1) {
+        j += s;
+        if (j < 0 || j >= g->ny) {
+            if (!g->periodic) return -1;
+            j = (j + g->ny) % g->ny;
+        }
+    } else {
+        k += s;
+        if (k < 0 || k >= g->nz) return -1;
+    }
+    return idx(g, i, j, k);
+}
+
+static double spacing(const orc_grid *g, int d) { return d == 0 ? g->hx : d == 1 ? g->hy : g->hz; }
+
+/* Robin sink of the row of cell (.., .., k): beta on the back face, else 0. */
+static double sink(const orc_grid *g, int k) { return k == g->nz - 1 ? g->beta : 0.0; }
+
+/* Runs BODY once for every interior face (p, q) of the grid, with h the
+ * spacing across it: q is the +x, +y or +z neighbour of p (wrapped where
+ * the lateral faces are periodic). */
 #define FOR_EACH_FACE(g, BODY)                                                  \
     for (int k = 0; k < (g)->nz; ++k)                                           \
         for (int j = 0; j < (g)->ny; ++j)                                       \
-            for (int i = 0; i < (g)->nx; ++i) {                                 \
-                long long p = idx((g), i, j, k);                                \
-                if (i + 1 < (g)->nx) { long long q = idx((g), i + 1, j, k); double h = (g)->hx; BODY } \
-                if (j + 1 < (g)->ny) { long long q = idx((g), i, j + 1, k); double h = (g)->hy; BODY } \
-                if (k + 1 < (g)->nz) { long long q = idx((g), i, j, k + 1); double h = (g)->hz; BODY } \
-            }
+            for (int i = 0; i < (g)->nx; ++i)                                   \
+                for (int d = 0; d < 3; ++d) {                                   \
+                    long long p = idx((g), i, j, k);                            \
+                    long long q = neighbour((g), i, j, k, d, +1);               \
+                    if (q < 0) continue;                                        \
+                    double h = spacing((g), d);                                 \
+                    BODY                                                        \
+                }
 
 /* y = A x = x + dt * L+ x, written per cell over its (up to) six faces. */
 void orc_apply_A(const orc_grid *g, const double *alpha, double dt, const double *x, double *y) {
@@ -72,18 +117,17 @@ void orc_apply_A(const orc_grid *g, const double *alpha, double dt, const double
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 long long p = idx(g, i, j, k);
-                double ap = alpha[p], s = 0.0;
-                if (i > 0)      { long long q = idx(g, i - 1, j, k); s += conductance(ap, alpha[q], g->hx) * (x[p] - x[q]); }
-                if (i + 1 < nx) { long long q = idx(g, i + 1, j, k); s += conductance(ap, alpha[q], g->hx) * (x[p] - x[q]); }
-                if (j > 0)      { long long q = idx(g, i, j - 1, k); s += conductance(ap, alpha[q], g->hy) * (x[p] - x[q]); }
-                if (j + 1 < ny) { long long q = idx(g, i, j + 1, k); s += conductance(ap, alpha[q], g->hy) * (x[p] - x[q]); }
-                if (k > 0)      { long long q = idx(g, i, j, k - 1); s += conductance(ap, alpha[q], g->hz) * (x[p] - x[q]); }
-                if (k + 1 < nz) { long long q = idx(g, i, j, k + 1); s += conductance(ap, alpha[q], g->hz) * (x[p] - x[q]); }
+                double ap = alpha[p], s = sink(g, k) * x[p];
+                for (int d = 0; d < 3; ++d)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        long long q = neighbour(g, i, j, k, d, sg);
+                        if (q >= 0) s += conductance(ap, alpha[q], spacing(g, d)) * (x[p] - x[q]);
+                    }
                 y[p] = x[p] + dt * s;
             }
 }
 
-/* Diagonal of A: D_p = 1 + dt * sum of the conductances of p's interior faces. */
+/* Diagonal of A: D_p = 1 + dt * (beta_p + sum of the conductances of p's interior faces). */
 void orc_diagonal(const orc_grid *g, const double *alpha, double dt, double *d) {
     const int nx = g->nx, ny = g->ny, nz = g->nz;
 #pragma omp parallel for collapse(2) schedule(static)
@@ -91,15 +135,49 @@ void orc_diagonal(const orc_grid *g, const double *alpha, double dt, double *d) 
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 long long p = idx(g, i, j, k);
-                double ap = alpha[p], s = 0.0;
-                if (i > 0)      s += conductance(ap, alpha[idx(g, i - 1, j, k)], g->hx);
-                if (i + 1 < nx) s += conductance(ap, alpha[idx(g, i + 1, j, k)], g->hx);
-                if (j > 0)      s += conductance(ap, alpha[idx(g, i, j - 1, k)], g->hy);
-                if (j + 1 < ny) s += conductance(ap, alpha[idx(g, i, j + 1, k)], g->hy);
-                if (k > 0)      s += conductance(ap, alpha[idx(g, i, j, k - 1)], g->hz);
-                if (k + 1 < nz) s += conductance(ap, alpha[idx(g, i, j, k + 1)], g->hz);
+                double ap = alpha[p], s = sink(g, k);
+                for (int dd = 0; dd < 3; ++dd)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        long long q = neighbour(g, i, j, k, dd, sg);
+                        if (q >= 0) s += conductance(ap, alpha[q], spacing(g, dd));
+                    }
                 d[p] = 1.0 + dt * s;
             }
+}
+
+/* y = R x with R = A - D the off-diagonal part of A: (R x)_p = -dt sum_{q ~ p} c_pq x_q. */
+void orc_apply_R(const orc_grid *g, const double *alpha, double dt, const double *x, double *y) {
+    const int nx = g->nx, ny = g->ny, nz = g->nz;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long long p = idx(g, i, j, k);
+                double ap = alpha[p], s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        long long q = neighbour(g, i, j, k, d, sg);
+                        if (q >= 0) s += conductance(ap, alpha[q], spacing(g, d)) * x[q];
+                    }
+                y[p] = -dt * s;
+            }
+}
+
+/*
+ * K Jacobi sweeps on A x = b from the x passed in (eq. jacobi_iter):
+ * x <- D^-1 (b - R x), R x formed from the whole previous iterate before
+ * any entry of x changes.
+ */
+void orc_jacobi(const orc_grid *g, const double *alpha, double dt, const double *dg,
+                const double *b, double *x, int K) {
+    const long long n = ng_of(g);
+    double *rx = malloc(sizeof(double) * n);
+    for (int kappa = 0; kappa < K; ++kappa) {
+        orc_apply_R(g, alpha, dt, x, rx);
+#pragma omp parallel for schedule(static)
+        for (long long i = 0; i < n; ++i) x[i] = (b[i] - rx[i]) / dg[i];
+    }
+    free(rx);
 }
 
 static double dot(long long n, const double *a, const double *b) {
@@ -161,12 +239,24 @@ int orc_pcg(const orc_grid *g, const double *alpha, double dt, const double *dg,
     return status < 0 ? -1 : it;
 }
 
+/* The configured inner solver on A x = b from the x passed in: Jacobi-PCG
+ * (returns its iterations, or -1 without convergence) or K Jacobi sweeps
+ * (returns K). */
+static int inner_solve(const orc_grid *g, const double *alpha, double dt, const double *dg,
+                       const double *b, double *x, double rtol, int max_iter) {
+    if (g->jacobi_k > 0) {
+        orc_jacobi(g, alpha, dt, dg, b, x, g->jacobi_k);
+        return g->jacobi_k;
+    }
+    return orc_pcg(g, alpha, dt, dg, b, x, rtol, max_iter, NULL);
+}
+
 /*
  * Forward sweep.  src is the top-face source per step, [nsteps][ny][nx]
  * (q^n = src[n-1]).  T0 may be NULL (T^0 = 0).  Outputs:
  *   S      [nsteps][ny][nx]  surface temperature of T^1..T^N
  *   T_all  [nsteps][ng]      every state T^1..T^N (may be NULL)
- *   iters  [nsteps]          CG iterations per step (may be NULL)
+ *   iters  [nsteps]          inner-solver iterations per step (may be NULL)
  * Returns 0, or -1 if some step did not converge.
  */
 int orc_forward(const orc_grid *g, const double *alpha, const double *src, const double *T0,
@@ -183,7 +273,7 @@ int orc_forward(const orc_grid *g, const double *alpha, const double *src, const
         memcpy(b, x, sizeof(double) * n);
         for (long long c = 0; c < nxy; ++c) b[c] += dt * src[(long long)(s - 1) * nxy + c];
         /* warm start from T^{s-1}, which is already in x */
-        int it = orc_pcg(g, alpha, dt, dg, b, x, rtol, max_iter, NULL);
+        int it = inner_solve(g, alpha, dt, dg, b, x, rtol, max_iter);
         if (it < 0) status = -1;
         if (iters) iters[s - 1] = it;
         memcpy(S + (long long)(s - 1) * nxy, x, sizeof(double) * nxy);
@@ -224,7 +314,7 @@ int orc_adjoint(const orc_grid *g, const double *alpha, double dt, int nsteps,
         /* c = mu^{s+1} + Pi^T g^s; mu holds mu^{s+1} and is the warm start */
         memcpy(c, mu, sizeof(double) * n);
         for (long long e = 0; e < nxy; ++e) c[e] += gs[(long long)(s - 1) * nxy + e];
-        int it = orc_pcg(g, alpha, dt, dg, c, mu, rtol, max_iter, NULL);
+        int it = inner_solve(g, alpha, dt, dg, c, mu, rtol, max_iter);
         if (it < 0) status = -1;
         if (iters) iters[s - 1] = it;
         accumulate_gradient(g, alpha, T_all + (long long)(s - 1) * n, mu, -dt, G);
@@ -258,7 +348,7 @@ int orc_tlm(const orc_grid *g, const double *alpha, const double *v, double dt, 
             b[p] -= dt * f;
             b[q] += dt * f;
         })
-        if (orc_pcg(g, alpha, dt, dg, b, dT, rtol, max_iter, NULL) < 0) status = -1;
+        if (inner_solve(g, alpha, dt, dg, b, dT, rtol, max_iter) < 0) status = -1;
         memcpy(dS + (long long)(s - 1) * nxy, dT, sizeof(double) * nxy);
     }
     free(dg); free(b); free(dT);

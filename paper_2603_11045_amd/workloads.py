@@ -135,6 +135,9 @@ class Workload:
     h: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     checkpoint_every: int = 0
     precision: str = "f32"
+    periodic: bool = False                  # lateral x, y faces wrap around
+    robin: float = 0.0                      # back-face Robin coefficient (0: adiabatic)
+    jacobi_k: int = 0                       # > 0: that many Jacobi sweeps per solve instead of PCG
 
     @property
     def ng(self) -> int:
@@ -204,6 +207,78 @@ def long_512x512x64(seed: int = 4, nsteps: int = 2000, checkpoint_every: int = 6
     return Workload(f"long_{nx}x{ny}x{nz}", nx, ny, nz, 10.0, nsteps, _cast(a, "f32"),
                     uniform_pulse(ny, nx).astype(np.float32), first_step_schedule(nsteps),
                     _cast(at, "f32"), rtol=1e-6, checkpoint_every=checkpoint_every)
+
+
+def add_defects(alpha: np.ndarray, count: int, lo: float, hi: float,
+                rng: np.random.Generator) -> List[dict]:
+    """Overwrite ``count`` buried defects, each an ellipsoid, a vertical
+    cylinder or a box (kind uniform), with a constant diffusivity ~U(lo, hi).
+
+    Lateral extents are 3..10 voxels (semi-axis or radius) or 6..20 (box
+    edge), through-thickness extents 2..6 voxels; the top of each defect lies
+    at depth 1..nz/2 and every defect is clipped at the walls. Later defects
+    win where they overlap.
+    """
+    nz, ny, nx = alpha.shape
+    zc, yc, xc = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
+                             indexing="ij")
+    out = []
+    for _ in range(count):
+        kind = ("ellipsoid", "cylinder", "box")[int(rng.integers(0, 3))]
+        val = float(rng.uniform(lo, hi))
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        ez = float(rng.uniform(2, 6))
+        top = float(rng.uniform(1, max(nz // 2, 2)))
+        if kind == "ellipsoid":
+            rx, ry = rng.uniform(3, 10, size=2)
+            cz = top + ez / 2
+            inside = (((xc - cx) / rx) ** 2 + ((yc - cy) / ry) ** 2 + ((zc - cz) / (ez / 2)) ** 2) <= 1.0
+        elif kind == "cylinder":
+            r = float(rng.uniform(3, 10))
+            inside = ((xc - cx) ** 2 + (yc - cy) ** 2 <= r * r) & (zc >= top) & (zc <= top + ez)
+        else:
+            ex, ey = rng.uniform(6, 20, size=2)
+            inside = ((np.abs(xc - cx) <= ex / 2) & (np.abs(yc - cy) <= ey / 2)
+                      & (zc >= top) & (zc <= top + ez))
+        alpha[inside] = val
+        out.append(dict(kind=kind, alpha=val, center=(cx, cy), top=top, thickness=ez))
+    return out
+
+
+def paper_64x64x16(seed: int = 6, nsteps: int = 50, layered: bool = False, jacobi_k: int = 50,
+                   robin: float = 0.0, periodic: bool = True, precision: str = "f32") -> Workload:
+    """The paper's synthetic specimen shape (App. E, Table 5): 64x64x16 on
+    [0,10]^2 x [0,1] (dx = dy = 0.156, dz = 0.0625), dt = 0.05, lateral
+    periodic faces, adiabatic or Robin back face, K = 50 Jacobi sweeps per
+    solve; 50 steps as in the solver benchmark of Table 4 (100 frames in the
+    training set-up). Bulk alpha ~U(0.1, 0.2), constant or in 3..4 strata
+    along z (layered); 1..4 buried defects alpha ~U(0.005, 0.015). Uniform
+    pulse 100 on step 1. Target: the defects redrawn from seed + 1000 over
+    the same bulk."""
+    nx, ny, nz = 64, 64, 16
+    rng = np.random.default_rng(seed)
+    if layered:
+        nl = int(rng.integers(3, 5))
+        cuts = np.sort(rng.choice(np.arange(2, nz - 1), size=nl - 1, replace=False))
+        vals = rng.uniform(0.1, 0.2, size=nl)
+        prof = np.empty(nz)
+        edges = [0] + cuts.tolist() + [nz]
+        for l in range(nl):
+            prof[edges[l]:edges[l + 1]] = vals[l]
+        bulk = np.broadcast_to(prof[:, None, None], (nz, ny, nx)).copy()
+    else:
+        bulk = np.full((nz, ny, nx), float(rng.uniform(0.1, 0.2)))
+    a = bulk.copy()
+    add_defects(a, int(rng.integers(1, 5)), 0.005, 0.015, rng)
+    at = bulk.copy()
+    trng = np.random.default_rng(seed + 1000)
+    add_defects(at, int(trng.integers(1, 5)), 0.005, 0.015, trng)
+    name = f"paper_{nx}x{ny}x{nz}" + ("_layered" if layered else "") + ("_robin" if robin else "")
+    qdt = np.float64 if precision == "f64" else np.float32
+    return Workload(name, nx, ny, nz, 0.05, nsteps, _cast(a, precision),
+                    uniform_pulse(ny, nx).astype(qdt), first_step_schedule(nsteps),
+                    _cast(at, precision), rtol=1e-6, h=(0.156, 0.156, 0.0625), precision=precision,
+                    periodic=periodic, robin=robin, jacobi_k=jacobi_k)
 
 
 SERVE_GRIDS = [(32, 32, 16), (64, 64, 32), (96, 96, 32), (128, 128, 48), (192, 192, 48)]

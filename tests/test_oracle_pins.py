@@ -327,3 +327,150 @@ def test_plain_fp64_workload_converges():
     tot = out["T_all"].sum(axis=(1, 2, 3))
     np.testing.assert_allclose(tot, w.dt * 100.0 * 256, rtol=1e-11)
     assert np.isfinite(out["G"]).all() and np.abs(out["G"]).max() > 0
+
+
+# ---------------------------------------------------------------- P13 closures and the fixed-K inner solver
+# App. D.2: lateral periodicity by circular padding, a Robin back face with the
+# diagonal sink beta = h / dz, and K Jacobi sweeps warm-started from T^{n-1}.
+
+@pytest.mark.parametrize("shape,h,dt,a", [((5, 6, 7), (1.0, 1.0, 1.0), 0.8, 0.7),
+                                          ((4, 8, 6), (0.156, 0.156, 0.0625), 0.05, 0.15)])
+def test_periodic_uniform_alpha_matches_fourier_cosine_basis(shape, h, dt, a):
+    """Uniform alpha, periodic x, y and zero-flux z: the discrete operator is
+    diagonal in Fourier (x, y) times DCT-II (z) modes, the grid counterpart of
+    the slab eigenfunctions of App. B (step 4), with eigenvalue
+    4 sin^2(pi m / nx) / hx^2 + 4 sin^2(pi l / ny) / hy^2 + 4 sin^2(pi p / (2 nz)) / hz^2.
+    Each implicit step divides a mode by 1 + dt a lambda."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(21)
+    T0 = rng.standard_normal(shape)
+    nsteps = 3
+    alpha = np.full(shape, a)
+    S, T_all, _ = orc.forward(alpha, np.zeros((nsteps, ny, nx)), dt, T0=T0, h=h, rtol=1e-14,
+                              periodic=True)
+    m = np.arange(nx)
+    l = np.arange(ny)
+    p = np.arange(nz)
+    lam = (4 * np.sin(np.pi * p / (2 * nz)) ** 2 / h[2] ** 2)[:, None, None] \
+        + (4 * np.sin(np.pi * l / ny) ** 2 / h[1] ** 2)[None, :, None] \
+        + (4 * np.sin(np.pi * m / nx) ** 2 / h[0] ** 2)[None, None, :]
+    spec = scipy.fft.dct(np.fft.fft2(T0, axes=(1, 2)), type=2, axis=0, norm="ortho")
+    for n in range(1, nsteps + 1):
+        Tn = np.fft.ifft2(scipy.fft.idct(spec / (1 + dt * a * lam) ** n, type=2, axis=0, norm="ortho"),
+                          axes=(1, 2)).real
+        np.testing.assert_allclose(T_all[n - 1], Tn, rtol=0, atol=1e-11 * np.abs(T0).max())
+
+
+def test_robin_single_layer_decays_by_one_plus_dt_beta():
+    """nz = 1 and a uniform state: no face carries flux, so the finite-volume
+    balance of the Robin face leaves A T = (1 + dt h / dz) T on every cell."""
+    shape = (1, 4, 5)
+    alpha = np.exp(0.4 * np.random.default_rng(22).standard_normal(shape))
+    h, dt, hr = (0.3, 0.4, 0.0625), 0.05, 0.8
+    T0 = np.full(shape, 2.0)
+    _, T_all, _ = orc.forward(alpha, np.zeros((4, 4, 5)), dt, T0=T0, h=h, rtol=1e-14,
+                              periodic=True, robin=hr)
+    for n in range(4):
+        np.testing.assert_allclose(T_all[n], 2.0 / (1 + dt * hr / h[2]) ** (n + 1), rtol=1e-12)
+
+
+def test_robin_heat_balance():
+    """Column sums of A are 1 + dt beta_p (App. D.2): the heat lost per step is
+    dt beta times the back-face heat of the new state."""
+    alpha, src, gs = _rand_problem((5, 6, 7), 5, seed=23)
+    h, dt, hr = (1.0, 0.7, 0.5), 0.9, 0.3
+    _, T_all, _ = orc.forward(alpha, src, dt, h=h, rtol=1e-14, robin=hr, periodic=True)
+    prev = 0.0
+    for n in range(5):
+        lhs = T_all[n].sum() + dt * hr / h[2] * T_all[n][-1].sum()
+        np.testing.assert_allclose(lhs, prev + dt * src[n].sum(), rtol=1e-12)
+        prev = T_all[n].sum()
+    # the adjoint carries the same balance with A^T = A
+    _, _, mu1, _ = orc.adjoint(alpha, T_all, gs, dt, h=h, rtol=1e-14, robin=hr, periodic=True)
+    assert np.isfinite(mu1).all()
+
+
+def test_robin_column_reduces_to_tridiagonal():
+    """nx = ny = 1 is a 1-D column: the Robin sink sits on the last diagonal
+    entry of the tridiagonal system (scipy.linalg.solve_banded)."""
+    nz = 9
+    rng = np.random.default_rng(24)
+    a = np.exp(0.5 * rng.standard_normal(nz))
+    hz, dt, hr = 0.1, 0.02, 0.7
+    c = 2 * a[:-1] * a[1:] / (a[:-1] + a[1:]) / hz ** 2
+    diag = 1 + dt * (np.r_[c, 0.0] + np.r_[0.0, c])
+    diag[-1] += dt * hr / hz
+    ab = np.zeros((3, nz))
+    ab[0, 1:] = -dt * c
+    ab[1] = diag
+    ab[2, :-1] = -dt * c
+    src = rng.uniform(0, 5, size=(3, 1, 1))
+    _, T_all, _ = orc.forward(a.reshape(nz, 1, 1), src, dt, h=(1.0, 1.0, hz), rtol=1e-14, robin=hr)
+    T = np.zeros(nz)
+    for n in range(3):
+        b = T.copy()
+        b[0] += dt * src[n, 0, 0]
+        T = scipy.linalg.solve_banded((1, 1), ab, b)
+        np.testing.assert_allclose(T_all[n].ravel(), T, rtol=1e-12)
+
+
+@pytest.mark.parametrize("periodic,robin", [(True, 0.0), (False, 0.6), (True, 0.6)])
+def test_closures_match_dense_assembly(periodic, robin):
+    """States and gradient against the dense assembly of App. D.2 with the
+    wrapped faces and the Robin rows."""
+    alpha, src, gs = _rand_problem((3, 4, 5), 4, seed=25)
+    h, dt = (0.5, 0.8, 0.3), 0.2
+    opt = dict(periodic=periodic, robin=robin)
+    S, T_all, _ = orc.forward(alpha, src, dt, h=h, rtol=1e-14, **opt)
+    Td, Sd = dense_ref.forward(alpha, src, dt, h, **opt)
+    np.testing.assert_allclose(T_all.reshape(Td.shape), Td, rtol=1e-11, atol=1e-12 * np.abs(Td).max())
+    G, _, _, _ = orc.adjoint(alpha, T_all, gs, dt, h=h, rtol=1e-14, **opt)
+    Gd, _ = dense_ref.adjoint_gradient(alpha, src, gs, dt, h, **opt)
+    np.testing.assert_allclose(G, Gd, rtol=1e-9, atol=1e-11 * np.abs(Gd).max())
+    # and the operator itself
+    x = np.random.default_rng(26).standard_normal(alpha.shape)
+    Ad = dense_ref.system_matrix(alpha, dt, h, **opt)
+    np.testing.assert_allclose(orc.apply_A(alpha, x, dt, h=h, **opt).ravel(), Ad @ x.ravel(), rtol=1e-13,
+                               atol=1e-13 * np.abs(x).max())
+    np.testing.assert_allclose(orc.diagonal(alpha, dt, h=h, **opt).ravel(), np.diag(Ad), rtol=1e-14)
+
+
+@pytest.mark.parametrize("periodic,robin,K", [(False, 0.0, 1), (True, 0.0, 7), (True, 0.5, 50)])
+def test_jacobi_sweeps_match_dense_splitting(periodic, robin, K):
+    """K sweeps x <- D^-1 (b - R x) (eq. jacobi_iter) against the dense
+    splitting A = D + R, and a whole fixed-K forward and adjoint (warm starts
+    T^{n-1} and mu^{n+1}) against the dense run of the same recurrences."""
+    alpha, src, gs = _rand_problem((3, 4, 5), 3, seed=27)
+    h, dt = (0.5, 0.8, 0.3), 0.05
+    opt = dict(periodic=periodic, robin=robin)
+    rng = np.random.default_rng(28)
+    b, x0 = rng.standard_normal(alpha.shape), rng.standard_normal(alpha.shape)
+    A = dense_ref.system_matrix(alpha, dt, h, **opt)
+    D = np.diag(A)
+    x = x0.ravel().copy()
+    for _ in range(K):
+        x = (b.ravel() - (A - np.diag(D)) @ x) / D
+    np.testing.assert_allclose(orc.jacobi(alpha, b, dt, x0, K, h=h, **opt).ravel(), x, rtol=1e-12,
+                               atol=1e-13 * np.abs(x).max())
+    S, T_all, it = orc.forward(alpha, src, dt, h=h, jacobi_k=K, **opt)
+    assert (it == K).all()
+    Td, _ = dense_ref.forward(alpha, src, dt, h, jacobi_k=K, **opt)
+    np.testing.assert_allclose(T_all.reshape(Td.shape), Td, rtol=1e-12, atol=1e-13 * np.abs(Td).max())
+    G, _, _, _ = orc.adjoint(alpha, T_all, gs, dt, h=h, jacobi_k=K, **opt)
+    Gd, _ = dense_ref.adjoint_gradient(alpha, src, gs, dt, h, jacobi_k=K, **opt)
+    np.testing.assert_allclose(G, Gd, rtol=1e-10, atol=1e-12 * np.abs(Gd).max())
+
+
+def test_jacobi_converges_to_the_exact_solve():
+    """Strict diagonal dominance (App. D.2) makes the sweeps contract: many
+    sweeps reach the PCG fixed point, and the paper's K = 50 on its grid
+    spacing and dt leaves a small residual."""
+    w = wl.paper_64x64x16(nsteps=4, precision="f64")
+    src = orc.source_series(w.q_xy, w.q_t)
+    opt = dict(h=w.h, periodic=True)
+    S, _, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-14, **opt)
+    Sj, _, _ = orc.forward(w.alpha, src, w.dt, jacobi_k=400, **opt)
+    assert np.abs(Sj - S).max() <= 1e-10 * np.abs(S).max()
+    S50, _, _ = orc.forward(w.alpha, src, w.dt, jacobi_k=50, **opt)
+    err = np.abs(S50 - S).max() / np.abs(S).max()
+    assert 0 < err < 1e-2
