@@ -14,9 +14,11 @@ voxel and CG iteration plus 24 (forward) or 52 (adjoint) bytes per voxel and
 step, the traffic of textbook two-pass Jacobi-PCG with its vectors in HBM,
 over the kernel's HIP-event time; ``traffic`` is the counter-measured HBM
 bytes per launch when a record taken on the same kernel sources is stored
-under profiles/. ``serve`` runs the first jobs of the Poisson serving stream
-through the batching server and, as the baseline, one by one through the
-single-problem path.
+under profiles/. ``paper_fixed_k`` times the paper's own solver set-up
+(64x64x16, periodic lateral faces, K = 50 Jacobi sweeps; forward and
+backward apart, as in its Table 4). ``serve`` runs the first jobs of the
+Poisson serving stream through the batching server and, as the baseline,
+one by one through the single-problem path.
 """
 from __future__ import annotations
 
@@ -46,6 +48,8 @@ def make_workload(name: str, nsteps: int = 0):
         w = wl.mixed_64x64x32(nsteps=nsteps or 200)
     elif name == "plain_fp64_16x16x8":
         w = wl.plain_fp64_16x16x8()
+    elif name == "paper_64x64x16":
+        w = wl.paper_64x64x16(nsteps=nsteps or 50)
     else:
         raise SystemExit(f"unknown workload {name}")
     return w
@@ -58,15 +62,69 @@ def cpu_baseline(w, sample_steps: int):
 
     src = orc.source_series(w.q_xy, w.q_t)[:sample_steps]
     t0 = time.perf_counter()
-    S, T_all, it_f = orc.forward(w.alpha, src, w.dt, h=w.h, rtol=w.rtol)
+    opt = dict(h=w.h, rtol=w.rtol, periodic=w.periodic, robin=w.robin, jacobi_k=w.jacobi_k)
+    S, T_all, it_f = orc.forward(w.alpha, src, w.dt, **opt)
     gs = np.random.default_rng(0).standard_normal(S.shape) * 1e-3
-    G, _, _, it_a = orc.adjoint(w.alpha, T_all, gs, w.dt, h=w.h, rtol=w.rtol)
+    G, _, _, it_a = orc.adjoint(w.alpha, T_all, gs, w.dt, **opt)
     t = time.perf_counter() - t0
     vs = w.ng * sample_steps / t
+    solver = (f"{w.jacobi_k} Jacobi sweeps per solve" if w.jacobi_k
+              else f"Jacobi-PCG at rtol {w.rtol:g}")
     return {"value": vs, "unit": "voxel-steps/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": f"{w.nx}x{w.ny}x{w.nz}, first {sample_steps} of {w.nsteps} steps, forward+adjoint, "
-                      f"FP64 matrix-free Jacobi-PCG at rtol {w.rtol:g} (OpenMP), {t:.1f} s",
+                      f"FP64 matrix-free {solver} (OpenMP), {t:.1f} s",
             "cg_iters": int(it_f.sum() + it_a.sum()), "seconds": t}
+
+
+def paper_fixed_k(Solver, dev, reps: int):
+    """The paper's own solver set-up (App. D.2, Table 5): the 64x64x16
+    specimen with periodic lateral faces, dx = dy = 0.156, dz = 0.0625,
+    dt = 0.05 and K = 50 Jacobi sweeps per solve, FP32. Forward and backward
+    (adjoint) are timed apart, as in the solver benchmark of Table 4 (50
+    steps), and together over the 100 frames of the training set-up. Median
+    over `reps` repetitions after one warm-up."""
+    import torch
+
+    from paper_2603_11045_amd import workloads as wl
+
+    out = {"workload": "paper_64x64x16", "grid": [64, 64, 16], "spacing": [0.156, 0.156, 0.0625], "dt": 0.05,
+           "jacobi_k": 50, "lateral": "periodic", "dtype": "f32"}
+    for nsteps in (50, 100):
+        w = wl.paper_64x64x16(nsteps=nsteps)
+        s = Solver(w.nx, w.ny, w.nz, h=w.h, device=0, periodic=True, jacobi_k=w.jacobi_k)
+        alpha = torch.from_numpy(w.alpha).to(dev)
+        q_xy = torch.from_numpy(w.q_xy).to(dev)
+        target = s.forward(torch.from_numpy(w.alpha_target).to(dev), q_xy, w.q_t, w.dt, nsteps).clone()
+        tf, tb = [], []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S = s.forward(alpha, q_xy, w.q_t, w.dt, nsteps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = (2.0 / S.numel()) * (S - target)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            s.adjoint(g)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if r > 0:
+                tf.append(t1 - t0)
+                tb.append(t3 - t2)
+        st = s.stats()
+        fwd, bwd = float(np.median(tf)), float(np.median(tb))
+        sweeps = 2 * nsteps * w.jacobi_k
+        key = f"steps_{nsteps}"
+        out[key] = {"fwd_s": fwd, "bwd_s": bwd, "fwd_bwd_ms": (fwd + bwd) * 1e3,
+                    "voxel_sweeps_per_s": w.ng * sweeps / (fwd + bwd),
+                    "alg_gb_per_s": (st["bytes_alg_fwd"] + st["bytes_alg_adj"]) / (fwd + bwd) / 1e9,
+                    "team_blocks": st["team_blocks"], "peak_workspace_mb": st["peak_workspace_bytes"] / 1e6}
+        print(f"[bench] paper fixed-K, {nsteps} steps: fwd {fwd * 1e3:.2f} ms, bwd {bwd * 1e3:.2f} ms",
+              file=sys.stderr, flush=True)
+        s.close()
+    out["paper_table4_context"] = {"fwd_s": 0.46, "bwd_s": 0.50, "peak_mb": 21.9, "steps": 50,
+                                   "gpu": "NVIDIA RTX PRO 6000 (the paper's; not this machine)"}
+    return out
 
 
 def main():
@@ -87,6 +145,8 @@ def main():
                          "and report peak device memory of both")
     ap.add_argument("--serve-jobs", type=int, default=40,
                     help="jobs of the Poisson serving stream to serve (0 = skip the serving run)")
+    ap.add_argument("--paper-reps", type=int, default=5,
+                    help="repetitions of the paper-shaped fixed-K timing (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (nh_copy_f32) three times, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -127,7 +187,7 @@ def main():
 
     solver = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=w.rtol, max_iter=2000, checkpoint_every=ck,
                     precision=w.precision, device=0, team_blocks_max=args.team, tile_z=args.tile_z,
-                    profile=not args.no_profile)
+                    profile=not args.no_profile, periodic=w.periodic, robin=w.robin, jacobi_k=w.jacobi_k)
     alpha = torch.from_numpy(w.alpha).to(dev)
     q_xy = torch.from_numpy(w.q_xy).to(dev)
     # synthetic measurement: the surface of the target diffusivity
@@ -183,13 +243,15 @@ def main():
         alg_per_launch = (bytes_f + bytes_a) / max(launches, 1)
         tr_path = os.path.join(ROOT, "profiles", f"traffic_{kname.split('::')[1].split('<')[0]}_{w.name}.json")
         tr = profiling.load_traffic(tr_path, kname)
+        model = ("16 B/voxel/Jacobi sweep + 28 (adj) B/voxel/step" if w.jacobi_k
+                 else "48 B/voxel/CG iteration + 24 (fwd) or 52 (adj) B/voxel/step")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr["traffic_bytes_per_launch"] if tr else None,
                 "kernel": kname,
                 "avg_launch_us": round((tk_f + tk_a) / max(launches, 1) * 1e6, 2),
                 "alg_bytes_per_launch": alg_per_launch,
-                "alg_bytes_model": "48 B/voxel/CG iteration + 24 (fwd) or 52 (adj) B/voxel/step",
+                "alg_bytes_model": model,
                 "kernel_time_frac": round((tk_f + tk_a) / elapsed, 4)}
         if tr:
             roof["traffic_over_alg"] = round(tr["traffic_bytes_per_launch"] / alg_per_launch, 4)
@@ -249,6 +311,8 @@ def main():
         full.close()
     del solver, alpha, q_xy, target
     torch.cuda.empty_cache()
+    if args.paper_reps > 0:
+        rec["paper_fixed_k"] = paper_fixed_k(Solver, dev, args.paper_reps)
     if args.serve_jobs > 0:
         from paper_2603_11045_amd import serve
 

@@ -8,8 +8,10 @@
  * A = I - dt*L):
  *
  *   c_f    = 2 a_p a_q / (a_p + a_q) / h_d^2        harmonic-mean face conductance (Prop. 1)
- *   (A x)_p = x_p + dt * sum_{interior faces f=(p,q)} c_f (x_p - x_q)
- *            every boundary face is zero-flux (carries no term)
+ *   (A x)_p = x_p + dt * sum_{interior faces f=(p,q)} c_f (x_p - x_q)  [+ dt beta x_p on k = nz-1]
+ *            every boundary face is zero-flux (carries no term) unless
+ *            nh_set_boundary makes the lateral faces periodic or gives the
+ *            back face a Robin sink beta
  *   A T^n   = T^{n-1} + dt q^n,   T^0 = 0,   q^n = q_t[n-1] * q_xy on the top plane k = 0
  *   S^n     = T^n on k = 0                         (the observation projector of eq. nefty_obj)
  *   A mu^n  = mu^{n+1} + Pi^T dL/dS^n,  mu^{N+1} = 0   (eq. adjoint_eq)
@@ -18,7 +20,8 @@
  *
  * Every linear solve is a Jacobi-preconditioned conjugate gradient run to
  * ||r||_2 <= rtol * ||b||_2, warm-started from the previous state (forward)
- * or from mu^{n+1} (adjoint), as App. D.2 warm-starts its Jacobi sweeps.
+ * or from mu^{n+1} (adjoint), as App. D.2 warm-starts its Jacobi sweeps;
+ * nh_set_jacobi_sweeps selects those fixed-K sweeps instead.
  *
  * Layout: every volume is [nz][ny][nx], C-contiguous, x fastest, index
  * i + nx*(j + ny*k); k = 0 is the heated and observed top face. Surface
@@ -70,7 +73,9 @@ typedef struct {
     double bytes_alg_fwd;       /* algorithmic bytes of the last forward: 12R per voxel and CG iteration, 6R
                                    per voxel and step (textbook two-pass Jacobi-PCG, vectors in HBM) */
     double bytes_alg_adj;       /* same for the last adjoint, 10R + 16 per voxel and step for the state load
-                                   and the FP64 gradient (recomputed forward steps counted as forward) */
+                                   and the FP64 gradient (recomputed forward steps counted as forward).
+                                   With fixed-K Jacobi sweeps: 4R per voxel and sweep, plus 3R + 16 per
+                                   voxel and adjoint step for the gradient */
     double t_fwd_s, t_adj_s;    /* host wall time of the last forward / adjoint call */
     double t_kernel_fwd_s;      /* summed HIP-event durations of the forward step kernels
                                    (only when profiling is enabled, else 0) */
@@ -102,6 +107,27 @@ nh_status nh_set_grid(nh_ctx *ctx, int nx, int ny, int nz, double hx, double hy,
  * and recomputes each segment during the adjoint). Defaults: 1e-6, 1000, 0.
  * Frees the saved forward state. */
 nh_status nh_set_solver(nh_ctx *ctx, double rtol, int max_iter, int checkpoint_every);
+
+/* Boundary closure (App. D.2, boundary conditions and the Robin row sums).
+ * periodic_xy = 1 closes the x and y rows into rings, as the paper's circular
+ * padding does: cell 0 and cell n-1 of a row share a face with the harmonic-
+ * mean conductance (needs nx, ny >= 3, else NH_EINVAL). robin_h >= 0 is the
+ * coefficient h of the back-face condition n.(alpha grad T) = -h T on the
+ * plane k = nz-1: its rows carry the diagonal sink beta = h / hz, which does
+ * not depend on alpha. Default 0, 0: zero flux on all six faces. The plane
+ * k = 0 stays adiabatic. Grids with either closure run on the streaming step
+ * kernel. Frees the saved forward state. */
+nh_status nh_set_boundary(nh_ctx *ctx, int periodic_xy, double robin_h);
+
+/* Inner solver. k = 0 (default): Jacobi-preconditioned CG to rtol. k > 0:
+ * the paper's fixed-K solver (eq. jacobi_iter, App. D.2): every solve takes
+ * exactly k sweeps x <- D^-1 (b - R x), A = D + R, from the previous time
+ * level's state (T^{n-1} forward, mu^{n+1} adjoint); the initial-guess mode
+ * does not apply. nh_stats reports k iterations per step, and worst_rel_res
+ * the largest ||b - A x|| / ||b|| of a last sweep's input. rtol is ignored
+ * and NH_ENOCONV never returned. k <= 100000, else NH_EINVAL. Frees the
+ * saved forward state. */
+nh_status nh_set_jacobi_sweeps(nh_ctx *ctx, int k);
 
 /* Forward sweep, FP32 vectors with FP64 reductions.
  *   alpha  [nz][ny][nx] diffusivity, every value finite and > 0 (checked on

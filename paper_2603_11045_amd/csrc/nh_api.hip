@@ -51,6 +51,11 @@ struct nh_ctx {
   int max_iter = 1000;
   int ckpt_every = 0;
 
+  // boundary closure and inner solver (App. D.2)
+  int periodic = 0;                          // lateral x, y faces wrap around
+  double robin = 0;                          // back-face Robin coefficient h (sink h / hz)
+  int jacobi_k = 0;                          // > 0: K Jacobi sweeps per solve instead of CG
+
   int team_max = 0, tile_z = 0, profile = 0;
   double barrier_timeout_s = 20.0;
 
@@ -148,14 +153,17 @@ nh_status fill(nh_ctx* c, T* p, long long n, T v) {
 }
 
 // Tile shape and team size for the current grid, for workgroups of `block`
-// threads; resident_ok allows the register-resident kernel (FP32, variant 2).
+// threads; resident_ok allows the register-resident kernel (FP32, variant 2,
+// zero-flux walls and the CG inner solver).
 void plan(nh_ctx* c, int occ, int block, bool resident_ok = false) {
+  resident_ok = resident_ok && !c->periodic && c->robin == 0 && c->jacobi_k == 0;
   Geom g{};
   g.nx = c->nx;
   g.ny = c->ny;
   g.nz = c->nz;
   g.nxy = (long long)c->nx * c->ny;
   g.ng = g.nxy * c->nz;
+  g.periodic = c->periodic;
   g.TX = c->nx > 32 ? 64 : (c->nx > 16 ? 32 : 16);
   g.TY = block / g.TX;
   g.txs = g.TX == 64 ? 6 : (g.TX == 32 ? 5 : 4);
@@ -268,6 +276,7 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.sx = (R)(2.0 * dt / (c->hx * c->hx));
   S.sy = (R)(2.0 * dt / (c->hy * c->hy));
   S.sz = (R)(2.0 * dt / (c->hz * c->hz));
+  S.sb = (R)(dt * c->robin / c->hz);
   S.alpha = (const R*)c->alpha.p;
   S.z = (R*)c->z.p;
   S.p0 = (R*)c->p0.p;
@@ -278,6 +287,7 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.s0 = (R*)c->vs0.p;
   S.s1 = (R*)c->vs1.p;
   S.variant = c->variant == 0 ? 0 : 1;
+  S.jacobi_k = c->jacobi_k;
   S.slots = c->slots.p;
   S.epoch_base = (++c->launch_ctr) << 24;
   S.rtol2 = c->rtol * c->rtol;
@@ -380,8 +390,16 @@ nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
 // stored (R); an adjoint step also loads T^n (R) and accumulates the gradient
 // (T, mu, alpha read: 3R; the FP64 accumulator read and written: 16 bytes).
 // FP32: 48 bytes per voxel-iteration, 24 per forward step, 52 per adjoint step.
-double step_bytes(const Geom& g, int R, int mode, int iters) {
-  const double per_voxel = 12.0 * R * iters + (mode == nh::kForward ? 6.0 * R : 10.0 * R + 16.0);
+// With the fixed-K Jacobi solver a sweep reads x, alpha and the previous
+// state and writes the new x (4R per voxel and sweep); the last sweep writes
+// the state itself, and an adjoint step adds the gradient pass (T, mu,
+// alpha: 3R; the FP64 accumulator: 16 bytes).
+double step_bytes(const Geom& g, int R, int mode, int iters, bool jacobi) {
+  double per_voxel;
+  if (jacobi)
+    per_voxel = 4.0 * R * iters + (mode == nh::kForward ? 0.0 : 3.0 * R + 16.0);
+  else
+    per_voxel = 12.0 * R * iters + (mode == nh::kForward ? 6.0 * R : 10.0 * R + 16.0);
   return per_voxel * (double)g.ng;
 }
 
@@ -602,7 +620,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     NH_HIP(c, hipStreamSynchronize(c->stream));
     double bytes = 0;
     for (int n = 1; n <= nsteps; ++n)
-      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1]);
+      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1], c->jacobi_k > 0);
     c->st.bytes_alg_fwd = bytes;
   }
   c->saved_prec = sizeof(R);
@@ -712,7 +730,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 1, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   for (int n = 1; n <= N; ++n)
-    bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1]);
+    bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1], c->jacobi_k > 0);
   c->st.recompute_iters = 0;
   if (k > 0) {
     long long rsum = 0;
@@ -725,7 +743,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
     NH_HIP(c, hipMemcpyAsync(ir.data(), step_out(c, 2, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
     NH_HIP(c, hipStreamSynchronize(c->stream));
     for (int n = 1; n <= N; ++n)
-      bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1]);
+      bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1], c->jacobi_k > 0);
   }
   c->st.bytes_alg_adj = bytes;
   c->st.workspace_bytes = c->ws_bytes;
@@ -790,6 +808,7 @@ nh_status nh_set_grid(nh_ctx* c, int nx, int ny, int nz, double hx, double hy, d
   if ((long long)nx * ny * nz > (1LL << 40)) return fail(c, NH_EINVAL, "grid too large");
   if (!(hx > 0) || !(hy > 0) || !(hz > 0) || !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz))
     return fail(c, NH_EINVAL, "spacings must be finite and > 0");
+  if (c->periodic && (nx < 3 || ny < 3)) return fail(c, NH_EINVAL, "periodic lateral faces need nx, ny >= 3");
   drop_forward(c);
   c->nx = nx; c->ny = ny; c->nz = nz;
   c->hx = hx; c->hy = hy; c->hz = hz;
@@ -872,9 +891,10 @@ nh_status nh_apply_A(nh_ctx* c, const float* alpha, const float* x, float* y, do
   plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
   const Geom& g = c->geom;
   const int blocks = std::min(g.ntiles, std::max(1, c->occ_f32 * c->num_cu));
+  const nh::Coef<float> cf{(float)(2.0 * dt / (c->hx * c->hx)), (float)(2.0 * dt / (c->hy * c->hy)),
+                           (float)(2.0 * dt / (c->hz * c->hz)), (float)(dt * c->robin / c->hz), g.nz - 1};
   hipLaunchKernelGGL(nh::apply_kernel<float>, dim3(blocks), dim3(nh::Cfg<float>::kBlock), 0, c->stream, g, alpha, x, y,
-                     (float)(2.0 * dt / (c->hx * c->hx)), (float)(2.0 * dt / (c->hy * c->hy)),
-                     (float)(2.0 * dt / (c->hz * c->hz)));
+                     cf);
   NH_HIP(c, hipGetLastError());
   NH_HIP(c, hipStreamSynchronize(c->stream));
   return NH_OK;
@@ -888,6 +908,27 @@ nh_status nh_set_launch(nh_ctx* c, int team_blocks_max, int tile_z, int profile)
   c->tile_z = tile_z;
   c->profile = profile != 0;
   if (c->grid_set) plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
+  return NH_OK;
+}
+
+nh_status nh_set_boundary(nh_ctx* c, int periodic_xy, double robin_h) {
+  if (!c) return NH_EINVAL;
+  if (periodic_xy != 0 && periodic_xy != 1) return fail(c, NH_EINVAL, "periodic_xy must be 0 or 1");
+  if (!(robin_h >= 0) || !std::isfinite(robin_h)) return fail(c, NH_EINVAL, "robin_h must be finite and >= 0");
+  if (periodic_xy && c->grid_set && (c->nx < 3 || c->ny < 3))
+    return fail(c, NH_EINVAL, "periodic lateral faces need nx, ny >= 3");
+  drop_forward(c);
+  c->periodic = periodic_xy;
+  c->robin = robin_h;
+  if (c->grid_set) plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
+  return NH_OK;
+}
+
+nh_status nh_set_jacobi_sweeps(nh_ctx* c, int k) {
+  if (!c) return NH_EINVAL;
+  if (k < 0 || k > 100000) return fail(c, NH_EINVAL, "the number of Jacobi sweeps must be in [0, 100000]");
+  drop_forward(c);
+  c->jacobi_k = k;
   return NH_OK;
 }
 

@@ -52,12 +52,14 @@ struct Geom {
   int TX, TY, TZ, txs;                      // tile extents, txs = log2(TX)
   int ntx, nty, ntz, ntiles;
   long long nxy, ng;
+  int periodic;                             // 1: the lateral x and y faces wrap around (nx, ny >= 3)
 };
 
 template <typename R>
 struct StepArgs {
   Geom g;
   R sx, sy, sz;                             // 2 dt / h_d^2 per axis
+  R sb;                                     // dt beta: Robin sink of the back plane k = nz-1 (0: adiabatic)
   const R* alpha;
   R* x;                                     // the unknown, solved in place
   const R* xprev;                           // the previous state h1: T^{n-1} or mu^{n+1} (null = zero)
@@ -75,6 +77,7 @@ struct StepArgs {
   R* s0;
   R* s1;
   int variant;                              // 0: two reductions per iteration, 1: one
+  int jacobi_k;                             // > 0: K Jacobi sweeps from h1 instead of CG
   const R* top_src;                         // [ny][nx] added on k = 0 (forward q_xy, adjoint g^n)
   R top_scale;                              // forward dt*q_t[n-1], adjoint 1
   R* surf_out;                              // frame of the solution on k = 0 (or null), times
@@ -275,6 +278,19 @@ __device__ __forceinline__ int first_tile(int rank, int team, int xcd_order) {
   return rank;
 }
 
+// The operator's coefficients: 2 dt / h_d^2 per axis, and the Robin sink
+// dt beta that the rows of the plane zb (the back face) carry.
+template <typename R>
+struct Coef {
+  R sx, sy, sz, sb;
+  int zb;
+};
+
+template <typename R>
+__device__ __forceinline__ Coef<R> coef_of(const StepArgs<R>& S) {
+  return Coef<R>{S.sx, S.sy, S.sz, S.sb, S.g.nz - 1};
+}
+
 // Stencil values of one cell: index 0 centre, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z.
 template <typename R, int NV>
 struct Pt {
@@ -303,6 +319,10 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
   const bool own = gx < g.nx && gy < g.ny;
   const long long col = own ? (long long)gx + (long long)g.nx * gy : 0;
   const int oslot = (ty + 1) * PW + tx + 1;
+  // the column this thread stages: its own; with periodic lateral faces a
+  // thread past the grid edge stages the column across the wrap instead
+  const bool ld = own || g.periodic;
+  const long long lcol = own ? col : (g.periodic ? (long long)(gx % g.nx) + (long long)g.nx * (gy % g.ny) : 0);
 
   // the halo cell this thread stages (perimeter of the TX x TY tile)
   int hslot = -1;
@@ -315,6 +335,10 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
     else if ((h -= TX) < TY) { hx = T.x0 - 1; hy = T.y0 + h; hslot = (h + 1) * PW; }
     else if ((h -= TY) < TY) { hx = T.x0 + TX; hy = T.y0 + h; hslot = (h + 1) * PW + TX + 1; }
     if (hslot >= 0) {
+      if (g.periodic) {                     // hx, hy >= -1
+        hx = (hx + g.nx) % g.nx;
+        hy = (hy + g.ny) % g.ny;
+      }
       hin = hx >= 0 && hx < g.nx && hy >= 0 && hy < g.ny;
       if (hin) hcol = (long long)hx + (long long)g.nx * hy;
     }
@@ -342,8 +366,8 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
 #pragma unroll
   for (int j = 0; j < QS - 1; ++j) {
     const int z = T.z0 - 1 + j;
-    if (own && z >= 0 && z < g.nz) {
-      const long long i = col + (long long)z * g.nxy;
+    if (ld && z >= 0 && z < g.nz) {
+      const long long i = lcol + (long long)z * g.nxy;
       qa[j] = op.alpha[i];
 #pragma unroll
       for (int k = 0; k < NV; ++k) qv[j][k] = op.load(k, i);
@@ -374,8 +398,8 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
       qa[QS - 1] = 0;
 #pragma unroll
       for (int k = 0; k < NV; ++k) qv[QS - 1][k] = 0;
-      if (own && zs < g.nz) {
-        const long long i = col + (long long)zs * g.nxy;
+      if (ld && zs < g.nz) {
+        const long long i = lcol + (long long)zs * g.nxy;
         qa[QS - 1] = op.alpha[i];
 #pragma unroll
         for (int k = 0; k < NV; ++k) qv[QS - 1][k] = op.load(k, i);
@@ -453,12 +477,14 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
 }
 
 // A v and the diagonal D of A at one cell, from staged alpha and v (row k of P).
+// A cell of the plane kz carries the Robin sink if kz is the back plane.
 template <typename R, int NV>
-__device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, R sx, R sy, R sz, R& Av, R& D) {
+__device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, const Coef<R>& cf, int kz, R& Av, R& D) {
   const R a = P.a[0];
-  const R c1 = face<R>(sx, a, P.a[1]), c2 = face<R>(sx, a, P.a[2]);
-  const R c3 = face<R>(sy, a, P.a[3]), c4 = face<R>(sy, a, P.a[4]);
-  const R c5 = face<R>(sz, a, P.a[5]), c6 = face<R>(sz, a, P.a[6]);
+  const R c1 = face<R>(cf.sx, a, P.a[1]), c2 = face<R>(cf.sx, a, P.a[2]);
+  const R c3 = face<R>(cf.sy, a, P.a[3]), c4 = face<R>(cf.sy, a, P.a[4]);
+  const R c5 = face<R>(cf.sz, a, P.a[5]), c6 = face<R>(cf.sz, a, P.a[6]);
+  const R sk = kz == cf.zb ? cf.sb : R(0);
   const R v = P.v[k][0];
   R s = c1 * (v - P.v[k][1]);
   s += c2 * (v - P.v[k][2]);
@@ -466,8 +492,9 @@ __device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, R sx, R sy, R
   s += c4 * (v - P.v[k][4]);
   s += c5 * (v - P.v[k][5]);
   s += c6 * (v - P.v[k][6]);
+  s += sk * v;
   Av = v + s;
-  D = R(1) + (((c1 + c2) + (c3 + c4)) + (c5 + c6));
+  D = R(1) + ((((c1 + c2) + (c3 + c4)) + (c5 + c6)) + sk);
 }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +515,7 @@ struct InitOp {
   R* z;
   const R* top;
   R top_scale;
-  R sx, sy, sz;
+  Coef<R> cf;
   long long nxy;
   double acc[3];                            // |b|^2, r.z, |r|^2
   __device__ R load(int, long long i) const {
@@ -502,7 +529,7 @@ struct InitOp {
   __device__ R own(int, long long i) const { return h2 ? src[i] : R(0); }
   __device__ void point(const Pt<R, 1>& P, const R (&o)[1], long long i, int kz) {
     R Av, D;
-    stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
+    stencil<R, 1>(P, 0, cf, kz, Av, D);
     R b = h2 ? o[0] : P.v[0][0];
     if (kz == 0) b += top_scale * top[i];
     const R r = b - Av;
@@ -528,13 +555,13 @@ struct DirOp {
   R* pnew;
   R beta;
   int first;
-  R sx, sy, sz;
+  Coef<R> cf;
   double acc[1];
   __device__ R load(int, long long i) const { return first ? z[i] : z[i] + beta * pold[i]; }
   __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
     R Av, D;
-    stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
+    stencil<R, 1>(P, 0, cf, kz, Av, D);
     st_out(pnew + i, P.v[0][0]);
     acc[0] += (double)P.v[0][0] * (double)Av;
   }
@@ -551,13 +578,13 @@ struct UpdOp {
   R* x;
   R* z;
   R a;
-  R sx, sy, sz;
+  Coef<R> cf;
   double acc[2];
   __device__ R load(int, long long i) const { return p[i]; }
   __device__ R own(int k, long long i) const { return k == 0 ? x[i] : z[i]; }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int) {
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int kz) {
     R Ap, D;
-    stencil<R, 1>(P, 0, sx, sy, sz, Ap, D);
+    stencil<R, 1>(P, 0, cf, kz, Ap, D);
     st_out(x + i, o[0] + a * P.v[0][0]);
     const R zn = o[1] - a * (Ap * rcp<R>(D));
     st_out(z + i, zn);
@@ -604,13 +631,13 @@ struct WOp {
   const R* alpha;
   const R* u;
   R* what;
-  R sx, sy, sz;
+  Coef<R> cf;
   double acc[1];
   __device__ R load(int, long long i) const { return u[i]; }
   __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
     R w, D;
-    stencil<R, 1>(P, 0, sx, sy, sz, w, D);
+    stencil<R, 1>(P, 0, cf, kz, w, D);
     st_out(what + i, w * rcp<R>(D));
     acc[0] += (double)P.v[0][0] * (double)w;
   }
@@ -639,7 +666,7 @@ struct FusedOp {
   R* shn;                                   // s_i / D
   R a, b;
   int first;
-  R sx, sy, sz;
+  Coef<R> cf;
   double acc[3];
   __device__ R load(int, long long i) const {
     const R sv = first ? wh[i] : wh[i] + b * sho[i];
@@ -654,14 +681,14 @@ struct FusedOp {
       default: return first ? R(0) : sho[i];
     }
   }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[5], long long i, int) {
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[5], long long i, int kz) {
     const R sv = first ? o[3] : o[3] + b * o[4];
     const R pv = first ? o[2] : o[2] + b * o[1];
     st_out(x + i, o[0] + a * pv);
     st_out(p + i, pv);
     st_out(shn + i, sv);
     R w, D;
-    stencil<R, 1>(P, 0, sx, sy, sz, w, D);
+    stencil<R, 1>(P, 0, cf, kz, w, D);
     const R uv = P.v[0][0];
     st_out(un + i, uv);
     st_out(whn + i, w * rcp<R>(D));
@@ -681,13 +708,44 @@ struct ApplyOp {
   const R* alpha;
   const R* xin;
   R* y;
-  R sx, sy, sz;
+  Coef<R> cf;
   __device__ R load(int, long long i) const { return xin[i]; }
   __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int) {
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
     R Av, D;
-    stencil<R, 1>(P, 0, sx, sy, sz, Av, D);
+    stencil<R, 1>(P, 0, cf, kz, Av, D);
     y[i] = Av;
+  }
+};
+
+// One sweep of the paper's fixed-K inner solver (eq. jacobi_iter):
+// x_new = D^-1 (b - R x) = x + (b - A x) / D with b = h1 + the top source;
+// accumulates |b|^2 and |b - A x|^2 (the residual of the sweep's input).
+template <typename R>
+struct JacobiOp {
+  static constexpr int NV = 1;
+  static constexpr int NO = 1;
+  using OT = R;
+  const R* alpha;
+  const R* xin;                             // x^(kappa) (null: zero)
+  const R* h1;                              // the previous state in b (null: zero)
+  R* xout;                                  // x^(kappa+1)
+  const R* top;
+  R top_scale;
+  Coef<R> cf;
+  double acc[2];
+  __device__ R load(int, long long i) const { return xin ? xin[i] : R(0); }
+  __device__ R own(int, long long i) const { return h1 ? h1[i] : R(0); }
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[1], long long i, int kz) {
+    R Av, D;
+    stencil<R, 1>(P, 0, cf, kz, Av, D);
+    R b = o[0];
+    if (kz == 0) b += top_scale * top[i];
+    const R r = b - Av;
+    st_out(xout + i, P.v[0][0] + r * rcp<R>(D));
+    const double bd = b, rd = r;
+    acc[0] += bd * bd;
+    acc[1] += rd * rd;
   }
 };
 
@@ -810,6 +868,7 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
 template <typename R>
 __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int rank, Smem<R>& sh) {
   const Geom& g = S.g;
+  const Coef<R> cf = coef_of(S);
   unsigned long long red = V.epoch_base;
   bool ok = true;
   int ntr = 0;
@@ -822,115 +881,144 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
   };
   stamp();
 
-  // set-up
-  InitOp<R> init;
-  init.alpha = S.alpha;
-  init.sx = S.sx; init.sy = S.sy; init.sz = S.sz;
-  init.z = S.z;
-  init.top = V.top_src;
-  init.top_scale = V.top_scale;
-  init.nxy = g.nxy;
-  init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
-  init.src = V.xprev;
-  const int order = guess_order(V);
-  init.h2 = order >= 1 ? V.xprev2 : nullptr;
-  init.h3 = order == 2 ? V.xprev3 : nullptr;
-  init.e1 = R(order == 2 ? 3 : 2);
-  init.e2 = R(order == 2 ? -3 : -1);
-  init.e3 = R(1);
-  init.xw = (V.xprev == V.x) ? nullptr : V.x;
-  sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
-  stamp();
-  double v3[3] = {init.acc[0], init.acc[1], init.acc[2]};
-  ok &= team_sum<R, 3>(S, rank, red, v3, sh);
-  stamp();
-  const double bb = v3[0];
-  double rz = v3[1], rr = v3[2];
-
   int it = 0, status = kOk;
-  if (ok && bb == 0.0) {
-    // b = 0: the solution is x = 0
-    own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) { V.x[i] = R(0); });
-    double v0[1] = {0.0};
-    ok &= team_sum<R, 1>(S, rank, red, v0, sh);
-    rr = 0.0;
-  } else if (S.variant == 0) {
-    R* pc = S.p0;
-    R* pn = S.p1;
-    double rz_old = 1.0;
-    while (ok && rr > S.rtol2 * bb) {
-      if (it >= S.max_iter) { status |= kNoConv; break; }
-      DirOp<R> A;
-      A.alpha = S.alpha; A.z = S.z; A.pold = pc; A.pnew = pn;
-      A.first = (it == 0);
-      A.beta = (R)(it == 0 ? 0.0 : rz / rz_old);
-      A.sx = S.sx; A.sy = S.sy; A.sz = S.sz;
-      A.acc[0] = 0.0;
-      sweep<R>(g, rank, S.team, S.xcd_order, A, sh);
+  double bb = 0.0, rr = 0.0;
+  if (S.jacobi_k > 0) {
+    // the paper's inner solver: K sweeps from x^(0) = h1, alternating between
+    // p0 and x so that the last one lands in x; each sweep ends with a team
+    // reduction, which is also the barrier before the next sweep reads halos
+    const R* xin = V.xprev;
+    while (ok && it < S.jacobi_k) {
+      JacobiOp<R> J;
+      J.alpha = S.alpha;
+      J.xin = xin;
+      J.h1 = V.xprev;
+      J.xout = ((S.jacobi_k - 1 - it) & 1) ? S.p0 : V.x;
+      J.top = V.top_src;
+      J.top_scale = V.top_scale;
+      J.cf = cf;
+      J.acc[0] = J.acc[1] = 0.0;
+      sweep<R>(g, rank, S.team, S.xcd_order, J, sh);
       stamp();
-      double v1[1] = {A.acc[0]};
-      ok &= team_sum<R, 1>(S, rank, red, v1, sh);
-      stamp();
-      if (!ok) break;
-      const double alpha_cg = rz / v1[0];
-
-      UpdOp<R> B;
-      B.alpha = S.alpha; B.p = pn; B.x = V.x; B.z = S.z;
-      B.a = (R)alpha_cg;
-      B.sx = S.sx; B.sy = S.sy; B.sz = S.sz;
-      B.acc[0] = B.acc[1] = 0.0;
-      sweep<R>(g, rank, S.team, S.xcd_order, B, sh);
-      stamp();
-      double v2[2] = {B.acc[0], B.acc[1]};
+      double v2[2] = {J.acc[0], J.acc[1]};
       ok &= team_sum<R, 2>(S, rank, red, v2, sh);
       stamp();
-      rz_old = rz;
-      rz = v2[0];
+      bb = v2[0];
       rr = v2[1];
+      xin = J.xout;
       ++it;
-      R* t = pc; pc = pn; pn = t;
     }
-  } else if (ok && rr > S.rtol2 * bb) {
-    // single-reduction form: w_0 = A u_0, then one fused sweep per iteration
-    WOp<R> W;
-    W.alpha = S.alpha; W.u = S.z; W.what = S.w0;
-    W.sx = S.sx; W.sy = S.sy; W.sz = S.sz;
-    W.acc[0] = 0.0;
-    sweep<R>(g, rank, S.team, S.xcd_order, W, sh);
+  } else {
+    // set-up
+    InitOp<R> init;
+    init.alpha = S.alpha;
+    init.cf = cf;
+    init.z = S.z;
+    init.top = V.top_src;
+    init.top_scale = V.top_scale;
+    init.nxy = g.nxy;
+    init.acc[0] = init.acc[1] = init.acc[2] = 0.0;
+    init.src = V.xprev;
+    const int order = guess_order(V);
+    init.h2 = order >= 1 ? V.xprev2 : nullptr;
+    init.h3 = order == 2 ? V.xprev3 : nullptr;
+    init.e1 = R(order == 2 ? 3 : 2);
+    init.e2 = R(order == 2 ? -3 : -1);
+    init.e3 = R(1);
+    init.xw = (V.xprev == V.x) ? nullptr : V.x;
+    sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
     stamp();
-    double vd[1] = {W.acc[0]};
-    ok &= team_sum<R, 1>(S, rank, red, vd, sh);
+    double v3[3] = {init.acc[0], init.acc[1], init.acc[2]};
+    ok &= team_sum<R, 3>(S, rank, red, v3, sh);
     stamp();
-    double gam = rz;
-    double a_cg = gam / vd[0], b_cg = 0.0;
-    R* ub[2] = {S.z, S.u1};
-    R* wb[2] = {S.w0, S.w1};
-    R* sb[2] = {S.s0, S.s1};
-    int cur = 0;
-    while (ok) {
-      if (it >= S.max_iter) { status |= kNoConv; break; }
-      FusedOp<R> F;
-      F.alpha = S.alpha;
-      F.u = ub[cur]; F.wh = wb[cur]; F.sho = sb[cur];
-      F.x = V.x; F.p = S.p0;
-      F.un = ub[cur ^ 1]; F.whn = wb[cur ^ 1]; F.shn = sb[cur ^ 1];
-      F.a = (R)a_cg; F.b = (R)b_cg;
-      F.first = (it == 0);
-      F.sx = S.sx; F.sy = S.sy; F.sz = S.sz;
-      F.acc[0] = F.acc[1] = F.acc[2] = 0.0;
-      sweep<R>(g, rank, S.team, S.xcd_order, F, sh);
+    bb = v3[0];
+    double rz = v3[1];
+    rr = v3[2];
+
+    if (ok && bb == 0.0) {
+      // b = 0: the solution is x = 0
+      own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) { V.x[i] = R(0); });
+      double v0[1] = {0.0};
+      ok &= team_sum<R, 1>(S, rank, red, v0, sh);
+      rr = 0.0;
+    } else if (S.variant == 0) {
+      R* pc = S.p0;
+      R* pn = S.p1;
+      double rz_old = 1.0;
+      while (ok && rr > S.rtol2 * bb) {
+        if (it >= S.max_iter) { status |= kNoConv; break; }
+        DirOp<R> A;
+        A.alpha = S.alpha; A.z = S.z; A.pold = pc; A.pnew = pn;
+        A.first = (it == 0);
+        A.beta = (R)(it == 0 ? 0.0 : rz / rz_old);
+        A.cf = cf;
+        A.acc[0] = 0.0;
+        sweep<R>(g, rank, S.team, S.xcd_order, A, sh);
+        stamp();
+        double v1[1] = {A.acc[0]};
+        ok &= team_sum<R, 1>(S, rank, red, v1, sh);
+        stamp();
+        if (!ok) break;
+        const double alpha_cg = rz / v1[0];
+
+        UpdOp<R> B;
+        B.alpha = S.alpha; B.p = pn; B.x = V.x; B.z = S.z;
+        B.a = (R)alpha_cg;
+        B.cf = cf;
+        B.acc[0] = B.acc[1] = 0.0;
+        sweep<R>(g, rank, S.team, S.xcd_order, B, sh);
+        stamp();
+        double v2[2] = {B.acc[0], B.acc[1]};
+        ok &= team_sum<R, 2>(S, rank, red, v2, sh);
+        stamp();
+        rz_old = rz;
+        rz = v2[0];
+        rr = v2[1];
+        ++it;
+        R* t = pc; pc = pn; pn = t;
+      }
+    } else if (ok && rr > S.rtol2 * bb) {
+      // single-reduction form: w_0 = A u_0, then one fused sweep per iteration
+      WOp<R> W;
+      W.alpha = S.alpha; W.u = S.z; W.what = S.w0;
+      W.cf = cf;
+      W.acc[0] = 0.0;
+      sweep<R>(g, rank, S.team, S.xcd_order, W, sh);
       stamp();
-      double v3n[3] = {F.acc[0], F.acc[1], F.acc[2]};
-      ok &= team_sum<R, 3>(S, rank, red, v3n, sh);
+      double vd[1] = {W.acc[0]};
+      ok &= team_sum<R, 1>(S, rank, red, vd, sh);
       stamp();
-      ++it;
-      cur ^= 1;
-      rr = v3n[2];
-      if (!(rr > S.rtol2 * bb)) break;
-      const double gn = v3n[0], dn = v3n[1];
-      b_cg = gn / gam;
-      a_cg = gn / (dn - b_cg * gn / a_cg);
-      gam = gn;
+      double gam = rz;
+      double a_cg = gam / vd[0], b_cg = 0.0;
+      R* ub[2] = {S.z, S.u1};
+      R* wb[2] = {S.w0, S.w1};
+      R* sb[2] = {S.s0, S.s1};
+      int cur = 0;
+      while (ok) {
+        if (it >= S.max_iter) { status |= kNoConv; break; }
+        FusedOp<R> F;
+        F.alpha = S.alpha;
+        F.u = ub[cur]; F.wh = wb[cur]; F.sho = sb[cur];
+        F.x = V.x; F.p = S.p0;
+        F.un = ub[cur ^ 1]; F.whn = wb[cur ^ 1]; F.shn = sb[cur ^ 1];
+        F.a = (R)a_cg; F.b = (R)b_cg;
+        F.first = (it == 0);
+        F.cf = cf;
+        F.acc[0] = F.acc[1] = F.acc[2] = 0.0;
+        sweep<R>(g, rank, S.team, S.xcd_order, F, sh);
+        stamp();
+        double v3n[3] = {F.acc[0], F.acc[1], F.acc[2]};
+        ok &= team_sum<R, 3>(S, rank, red, v3n, sh);
+        stamp();
+        ++it;
+        cur ^= 1;
+        rr = v3n[2];
+        if (!(rr > S.rtol2 * bb)) break;
+        const double gn = v3n[0], dn = v3n[1];
+        b_cg = gn / gam;
+        a_cg = gn / (dn - b_cg * gn / a_cg);
+        gam = gn;
+      }
     }
   }
   if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
@@ -975,11 +1063,11 @@ __global__ void __launch_bounds__(Cfg<R>::kBlock, 1) step_kernel(StepArgs<R> S) 
 
 template <typename R>
 __global__ void __launch_bounds__(Cfg<R>::kBlock, 1) apply_kernel(Geom g, const R* alpha, const R* x, R* y,
-                                                          R sx, R sy, R sz) {
+                                                          Coef<R> cf) {
   __shared__ Smem<R> sh;
   ApplyOp<R> op;
   op.alpha = alpha; op.xin = x; op.y = y;
-  op.sx = sx; op.sy = sy; op.sz = sz;
+  op.cf = cf;
   sweep<R>(g, blockIdx.x, gridDim.x, 0, op, sh);
 }
 

@@ -47,7 +47,9 @@ class Solver:
     (streaming kernel), 2 one reduction with the register-resident kernel
     where the grid fits on the chip, else as 1. ``initial_guess`` is the CG
     starting point of each solve: ``"adaptive"`` (default), ``"extrapolate"``
-    from the last three states, or ``"previous"`` state alone.
+    from the last three states, or ``"previous"`` state alone. ``periodic``
+    wraps the lateral faces, ``robin`` is the back-face Robin coefficient and
+    ``jacobi_k > 0`` replaces CG by the paper's fixed-K Jacobi sweeps (App. D.2).
     """
 
     def __init__(self, nx: int, ny: int, nz: int, h: Sequence[float] = (1.0, 1.0, 1.0),
@@ -55,7 +57,8 @@ class Solver:
                  precision: str = "f32", device: Optional[int] = None,
                  stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
                  tile_z: int = 0, profile: bool = False, cg_variant: int = 2,
-                 initial_guess: str = "adaptive"):
+                 initial_guess: str = "adaptive", periodic: bool = False, robin: float = 0.0,
+                 jacobi_k: int = 0):
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.lib = _lib.load()
@@ -70,6 +73,8 @@ class Solver:
                                   ctypes.c_void_p(self.stream.cuda_stream)), None, "nh_create")
         _check(self.lib.nh_set_grid(self._ctx, self.nx, self.ny, self.nz, *self.h), self._ctx,
                "nh_set_grid")
+        self.set_boundary(periodic, robin)
+        self.set_jacobi_sweeps(jacobi_k)
         self.set_cg_variant(cg_variant)
         self.set_initial_guess(initial_guess)
         self.set_solver(rtol, max_iter, checkpoint_every)
@@ -88,6 +93,18 @@ class Solver:
     def set_launch(self, team_blocks_max: int = 0, tile_z: int = 0, profile: bool = False):
         _check(self.lib.nh_set_launch(self._ctx, int(team_blocks_max), int(tile_z), int(bool(profile))),
                self._ctx, "nh_set_launch")
+
+    def set_boundary(self, periodic: bool = False, robin: float = 0.0):
+        """Lateral periodic faces and the back-face Robin coefficient h (the
+        sink h / hz on the plane k = nz-1); the defaults are zero flux."""
+        _check(self.lib.nh_set_boundary(self._ctx, int(bool(periodic)), float(robin)), self._ctx,
+               "nh_set_boundary")
+        self.periodic, self.robin = bool(periodic), float(robin)
+
+    def set_jacobi_sweeps(self, k: int):
+        """0: Jacobi-PCG to rtol; k > 0: exactly k Jacobi sweeps per solve."""
+        _check(self.lib.nh_set_jacobi_sweeps(self._ctx, int(k)), self._ctx, "nh_set_jacobi_sweeps")
+        self.jacobi_k = int(k)
 
     def set_cg_variant(self, variant: int):
         _check(self.lib.nh_set_cg_variant(self._ctx, int(variant)), self._ctx, "nh_set_cg_variant")
