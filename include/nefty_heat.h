@@ -175,6 +175,25 @@ nh_status nh_get_state(nh_ctx *ctx, int n, void *out);
  * alpha, x, y: [nz][ny][nx] FP32 device arrays (y must not alias x). */
 nh_status nh_apply_A(nh_ctx *ctx, const float *alpha, const float *x, float *y, double dt);
 
+/* The total-variation regulariser of the inverse problem (eq. tv_discrete,
+ * App. D.1) on the context's grid and spacings, value and gradient in one
+ * pass:
+ *   R(a) = hx hy hz sum_p sqrt((d_x a/hx)^2 + (d_y a/hy)^2 + (d_z a/hz)^2 + eps^2)
+ * with forward differences along the array axes; the x and y differences
+ * wrap around (the paper's lateral periodicity, whatever nh_set_boundary
+ * says) and the z difference is 0 on the plane k = nz-1.
+ *   alpha  [nz][ny][nx] device, FP32 (nh_tv) or FP64 (nh_tv_f64); any values.
+ *   value  device pointer to one double: receives weight * R(alpha).
+ *   grad   [nz][ny][nx] FP64 device: receives weight * dR/dalpha, added to
+ *          its contents when accumulate = 1 (e.g. onto the adjoint's
+ *          dL/dalpha), written over them when accumulate = 0.
+ *   eps > 0 and weight finite, else NH_EINVAL; NH_ESTATE before nh_set_grid.
+ * The value is summed in a fixed order (bit-reproducible). */
+nh_status nh_tv(nh_ctx *ctx, const float *alpha, double eps, double weight, double *value, double *grad,
+                int accumulate);
+nh_status nh_tv_f64(nh_ctx *ctx, const double *alpha, double eps, double weight, double *value, double *grad,
+                    int accumulate);
+
 /* Launch tuning: team_blocks_max caps the workgroups of one step (0 = all
  * that fit on the device), tile_z sets the z extent of a tile (0 = auto).
  * profile != 0 times every step kernel with HIP events (nh_stats.t_kernel_*). */

@@ -11,6 +11,7 @@
 #include "nefty_heat.h"
 #include "nh_kernels.hpp"
 #include "nh_resident.hpp"
+#include "nh_tv.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -67,6 +68,7 @@ struct nh_ctx {
 
   // workspaces
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
+  Buf tvpart;                                // per-workgroup partial sums of the TV regulariser
   Buf mu[4];                                 // adjoint states, mu^n in mu[n & 3]
   Buf w[4];                                  // checkpointed forward: T^n in w[n & 3]
   int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive
@@ -752,9 +754,55 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   return status_to_code(c, any);
 }
 
+template <typename R>
+nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* value, double* grad,
+                int accumulate) {
+  if (!c) return NH_EINVAL;
+  if (!c->grid_set) return fail(c, NH_ESTATE, "nh_set_grid has not been called");
+  if (!alpha || !value || !grad) return fail(c, NH_EINVAL, "null pointer argument");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(c, NH_EINVAL, "eps must be finite and > 0");
+  if (!std::isfinite(weight)) return fail(c, NH_EINVAL, "weight must be finite");
+  if (accumulate != 0 && accumulate != 1) return fail(c, NH_EINVAL, "accumulate must be 0 or 1");
+  const long long ng = (long long)c->nx * c->ny * c->nz;
+  const int blocks = (int)std::min<long long>((ng + nh::kTvBlock - 1) / nh::kTvBlock, nh::kTvMaxBlocks);
+  NH_TRY(ensure(c, c->tvpart, sizeof(double) * (size_t)blocks));
+  nh::TvArgs<R> A;
+  A.alpha = alpha;
+  A.nx = c->nx;
+  A.ny = c->ny;
+  A.nz = c->nz;
+  A.nxy = (long long)c->nx * c->ny;
+  A.ng = ng;
+  A.ix2 = (R)(1.0 / (c->hx * c->hx));
+  A.iy2 = (R)(1.0 / (c->hy * c->hy));
+  A.iz2 = (R)(1.0 / (c->hz * c->hz));
+  A.eps2 = (R)(eps * eps);
+  A.scale = weight * c->hx * c->hy * c->hz;
+  A.grad = grad;
+  A.accumulate = accumulate;
+  A.partial = (double*)c->tvpart.p;
+  hipLaunchKernelGGL(nh::tv_kernel<R>, dim3(blocks), dim3(nh::kTvBlock), 0, c->stream, A);
+  NH_HIP(c, hipGetLastError());
+  hipLaunchKernelGGL(nh::tv_finish_kernel, dim3(1), dim3(nh::kTvBlock), 0, c->stream, (const double*)A.partial,
+                     blocks, A.scale, value);
+  NH_HIP(c, hipGetLastError());
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  return NH_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+nh_status nh_tv(nh_ctx* c, const float* alpha, double eps, double weight, double* value, double* grad,
+                int accumulate) {
+  return do_tv<float>(c, alpha, eps, weight, value, grad, accumulate);
+}
+
+nh_status nh_tv_f64(nh_ctx* c, const double* alpha, double eps, double weight, double* value, double* grad,
+                    int accumulate) {
+  return do_tv<double>(c, alpha, eps, weight, value, grad, accumulate);
+}
 
 nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
   if (!out) return NH_EINVAL;
@@ -986,7 +1034,7 @@ void nh_destroy(nh_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
-                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag};
+                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart};
   for (Buf* b : bufs) release(c, *b);
   for (Buf& b : c->mu) release(c, b);
   for (Buf& b : c->w) release(c, b);

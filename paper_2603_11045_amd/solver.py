@@ -192,6 +192,24 @@ class Solver:
                self._ctx, "nh_apply_A")
         return y
 
+    def tv(self, alpha: torch.Tensor, eps: float = 1e-6, weight: float = 1.0,
+           grad: Optional[torch.Tensor] = None):
+        """The TV regulariser of eq. tv_discrete on this grid: returns
+        ``(weight * R(alpha), grad)`` with ``grad`` FP64 holding
+        ``weight * dR/dalpha`` -- added to the given ``grad`` (e.g. the
+        adjoint's dL/dalpha) in place, or in a new tensor."""
+        _dev_tensor(alpha, "alpha", self.dtype, self.ng)
+        accumulate = grad is not None
+        if grad is None:
+            grad = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        else:
+            _dev_tensor(grad, "grad", torch.float64, self.ng)
+        value = torch.empty(1, dtype=torch.float64, device=self.device)
+        fn = self.lib.nh_tv if self.precision == "f32" else self.lib.nh_tv_f64
+        _check(fn(self._ctx, alpha.data_ptr(), float(eps), float(weight), value.data_ptr(), grad.data_ptr(),
+                  int(accumulate)), self._ctx, "nh_tv")
+        return float(value.item()), grad
+
     def stats(self) -> dict:
         s = _lib.nh_stats()
         _check(self.lib.nh_get_stats(self._ctx, ctypes.byref(s)), self._ctx, "nh_get_stats")

@@ -474,3 +474,67 @@ def test_jacobi_converges_to_the_exact_solve():
     S50, _, _ = orc.forward(w.alpha, src, w.dt, jacobi_k=50, **opt)
     err = np.abs(S50 - S).max() / np.abs(S).max()
     assert 0 < err < 1e-2
+
+
+# ---------------------------------------------------------------- P14 total variation (eq. tv_discrete)
+from oracle import tv as orc_tv  # noqa: E402
+
+
+def test_tv_constant_field_is_volume_times_eps():
+    """No differences: every term is eps, R = N dx dy dz eps."""
+    h, eps = (0.156, 0.156, 0.0625), 1e-3
+    a = np.full((4, 5, 6), 0.3)
+    assert abs(orc_tv.tv_value(a, h, eps) - 120 * h[0] * h[1] * h[2] * eps) <= 1e-15
+    assert np.abs(orc_tv.tv_grad(a, h, eps)).max() == 0.0
+
+
+def test_tv_step_in_x_counts_both_periodic_jumps():
+    """alpha = a on the first half of each x row, b on the second: with the
+    lateral wrap every row has two jumps of |a - b|, so as eps -> 0
+    R = dx dy dz * 2 |a - b| / dx * ny * nz (plus eps on the flat cells)."""
+    nz, ny, nx = 3, 4, 8
+    h, eps = (0.5, 0.7, 0.3), 1e-12
+    a = np.full((nz, ny, nx), 0.2)
+    a[:, :, nx // 2:] = 0.05
+    want = h[0] * h[1] * h[2] * (2 * 0.15 / h[0] * ny * nz + (nx - 2) * ny * nz * eps)
+    assert abs(orc_tv.tv_value(a, h, eps) - want) <= 1e-13 * want
+
+
+def test_tv_ramp_in_z_has_no_last_plane_term():
+    """alpha_k = c k: nz - 1 vertical differences per column (the last plane's
+    is zero by definition), so R = dx dy dz nx ny ((nz - 1) |c| / dz + eps)."""
+    nz, ny, nx = 5, 3, 4
+    h, eps, c = (1.0, 1.0, 0.25), 1e-12, 0.07
+    a = np.broadcast_to((c * np.arange(nz))[:, None, None], (nz, ny, nx)).copy()
+    want = h[0] * h[1] * h[2] * nx * ny * ((nz - 1) * c / h[2] + eps)
+    assert abs(orc_tv.tv_value(a, h, eps) - want) <= 1e-13 * want
+
+
+def test_tv_isotropic_combination_in_one_cell():
+    """One raised cell p: p's own term combines its +x, +y, +z differences
+    under one square root (isotropic TV), not as a sum of absolute values."""
+    nz, ny, nx = 3, 3, 3
+    h, eps, d = (1.0, 2.0, 0.5), 1e-9, 0.4
+    a = np.zeros((nz, ny, nx))
+    a[1, 1, 1] = d
+    # p: all three forward differences are -d; its -x, -y, -z neighbours each see +d along one axis
+    own = np.sqrt((d / h[0]) ** 2 + (d / h[1]) ** 2 + (d / h[2]) ** 2 + eps ** 2)
+    nb = [np.sqrt((d / hh) ** 2 + eps ** 2) for hh in h]
+    want = h[0] * h[1] * h[2] * (own + sum(nb) + (27 - 4) * eps)
+    assert abs(orc_tv.tv_value(a, h, eps) - want) <= 1e-14 * want
+
+
+def test_tv_gradient_matches_central_differences():
+    """Brute-force central differences of R on a small random field."""
+    rng = np.random.default_rng(31)
+    a = rng.uniform(0.05, 0.2, size=(3, 4, 5))
+    h, eps = (0.156, 0.156, 0.0625), 1e-2
+    g = orc_tv.tv_grad(a, h, eps)
+    step = 1e-6
+    for flat in range(a.size):
+        p = np.unravel_index(flat, a.shape)
+        ap, am = a.copy(), a.copy()
+        ap[p] += step
+        am[p] -= step
+        fd = (orc_tv.tv_value(ap, h, eps) - orc_tv.tv_value(am, h, eps)) / (2 * step)
+        assert abs(fd - g[p]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(g).max()), (p, fd, g[p])
