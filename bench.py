@@ -16,7 +16,8 @@ over the kernel's HIP-event time; ``traffic`` is the counter-measured HBM
 bytes per launch when a record taken on the same kernel sources is stored
 under profiles/. ``paper_fixed_k`` times the paper's own solver set-up
 (64x64x16, periodic lateral faces, K = 50 Jacobi sweeps; forward and
-backward apart, as in its Table 4). ``serve`` runs the first jobs of the
+backward apart, as in its Table 4); ``invert`` the time per iteration of
+the two inversion drivers on its training set-up (Table 9). ``serve`` runs the first jobs of the
 Poisson serving stream through the batching server and, as the baseline,
 one by one through the single-problem path.
 """
@@ -127,6 +128,35 @@ def paper_fixed_k(Solver, dev, reps: int):
     return out
 
 
+def invert_iterations(dev, iters: int):
+    """Time per optimisation iteration of the two inversion drivers on the
+    paper's training set-up (64x64x16, 100 frames, K = 50, TV, Adam; the
+    neural field at its full size, 10 layers of width 512 with 12 bands):
+    one forward sweep, one adjoint sweep, the TV kernel and the optimiser step
+    (plus the MLP forward and backward for the neural field)."""
+    import torch
+
+    from paper_2603_11045_amd import workloads as wl
+    from paper_2603_11045_amd.invert import InvertConfig, reconstruct
+    from paper_2603_11045_amd.solver import Solver
+
+    w = wl.paper_64x64x16(nsteps=100)
+    s = Solver(w.nx, w.ny, w.nz, h=w.h, periodic=True, jacobi_k=w.jacobi_k)
+    target = s.forward(torch.from_numpy(w.alpha).to(dev), torch.from_numpy(w.q_xy).to(dev), w.q_t, w.dt,
+                       w.nsteps).clone()
+    s.close()
+    out = {"workload": "paper_64x64x16", "nsteps": 100, "jacobi_k": 50, "iters_timed": iters}
+    for method in ("grid", "nefty"):
+        reconstruct(w, target, InvertConfig(method=method, iters=2), bulk_mean=float(np.median(w.alpha)))
+        r = reconstruct(w, target, InvertConfig(method=method, iters=iters), alpha_true=w.alpha,
+                        bulk_mean=float(np.median(w.alpha)))
+        out[method] = {"ms_per_iter": r.ms_per_iter, "metrics_after": r.metrics}
+        print(f"[bench] invert {method}: {r.ms_per_iter:.2f} ms/iteration", file=sys.stderr, flush=True)
+    out["paper_table9_context_ms_per_iter"] = {"grid": 47.8, "nefty": 57.5,
+                                               "gpu": "NVIDIA RTX PRO 6000 (the paper's; not this machine)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +177,8 @@ def main():
                     help="jobs of the Poisson serving stream to serve (0 = skip the serving run)")
     ap.add_argument("--paper-reps", type=int, default=5,
                     help="repetitions of the paper-shaped fixed-K timing (0 = skip)")
+    ap.add_argument("--invert-iters", type=int, default=20,
+                    help="timed iterations of each inversion driver (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (nh_copy_f32) three times, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -313,6 +345,8 @@ def main():
     torch.cuda.empty_cache()
     if args.paper_reps > 0:
         rec["paper_fixed_k"] = paper_fixed_k(Solver, dev, args.paper_reps)
+    if args.invert_iters > 0:
+        rec["invert"] = invert_iterations(dev, args.invert_iters)
     if args.serve_jobs > 0:
         from paper_2603_11045_amd import serve
 
