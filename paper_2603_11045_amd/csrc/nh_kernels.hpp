@@ -78,6 +78,7 @@ struct StepArgs {
   R* s1;
   int variant;                              // 0: two reductions per iteration, 1: one
   int jacobi_k;                             // > 0: K Jacobi sweeps from h1 instead of CG
+  int jtx, jty;                             // temporally blocked fixed-K kernel: interior tiles per axis
   const R* top_src;                         // [ny][nx] added on k = 0 (forward q_xy, adjoint g^n)
   R top_scale;                              // forward dt*q_t[n-1], adjoint 1
   R* surf_out;                              // frame of the solution on k = 0 (or null), times
@@ -184,10 +185,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
 // order with a fixed reduction tree, and releases the result slot; the other
 // workgroups wait for that. Waits are bounded by timeout_ticks; a timeout
 // returns false and is recorded in err_flag.
-template <typename R, int NV>
+template <typename R, int NV, int BLOCK = Cfg<R>::kBlock>
 __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigned long long& epoch,
                                          double (&v)[NV], Smem<R>& sh) {
-  constexpr int BLOCK = Cfg<R>::kBlock;
   block_sum<NV, BLOCK / 64>(v, sh.red, sh.bc);
   if (S.team == 1) return true;
   const unsigned long long e = ++epoch;
@@ -865,6 +865,46 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   return V;
 }
 
+// The end of a step, after the solve: the surface frame (times surf_scale in
+// the adjoint) and the checkpoint copy, the gradient pass of an adjoint step,
+// and the per-step outputs (written by rank 0). The caller's last team
+// reduction is the barrier that makes x complete before this reads it.
+template <typename R>
+__device__ StepResult step_epilogue(const StepArgs<R>& S, const StepVar<R>& V, int rank, bool ok, int it,
+                                    int status, double bb, double rr, Smem<R>& sh) {
+  const Geom& g = S.g;
+  if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
+  if (!ok) status |= kTimeout;
+  if (S.mode == kForward) {
+    if (V.ckpt_out) {
+      own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long col, int kz) {
+        const R v = V.x[i];
+        if (kz == 0 && V.surf_out) V.surf_out[col] = v;
+        V.ckpt_out[i] = v;
+      });
+    } else if (V.surf_out) {
+      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.x[col]; });
+    }
+  } else {
+    if (V.surf_out)
+      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.surf_scale * V.x[col]; });
+  }
+  if (S.mode == kAdjoint && V.T_grad && ok) {
+    GradOp<R> Gop;
+    Gop.alpha = S.alpha; Gop.mu = V.x; Gop.T = V.T_grad; Gop.G = S.G;
+    Gop.sx = S.sx; Gop.sy = S.sy; Gop.sz = S.sz;
+    sweep<R>(g, rank, S.team, S.xcd_order, Gop, sh);
+  }
+
+  const double relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  if (V.out_iters && rank == 0 && threadIdx.x == 0) {
+    V.out_iters[0] = it;
+    V.out_relres[0] = relres;
+    V.out_status[0] = status;
+  }
+  return StepResult{it, status, relres};
+}
+
 template <typename R>
 __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int rank, Smem<R>& sh) {
   const Geom& g = S.g;
@@ -1021,38 +1061,7 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
       }
     }
   }
-  if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
-  if (!ok) status |= kTimeout;
-
-  // epilogue
-  if (S.mode == kForward) {
-    if (V.ckpt_out) {
-      own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long col, int kz) {
-        const R v = V.x[i];
-        if (kz == 0 && V.surf_out) V.surf_out[col] = v;
-        V.ckpt_out[i] = v;
-      });
-    } else if (V.surf_out) {
-      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.x[col]; });
-    }
-  } else {
-    if (V.surf_out)
-      top_cells(g, rank, S.team, S.xcd_order, [&](long long col) { V.surf_out[col] = V.surf_scale * V.x[col]; });
-  }
-  if (S.mode == kAdjoint && V.T_grad && ok) {
-    GradOp<R> Gop;
-    Gop.alpha = S.alpha; Gop.mu = V.x; Gop.T = V.T_grad; Gop.G = S.G;
-    Gop.sx = S.sx; Gop.sy = S.sy; Gop.sz = S.sz;
-    sweep<R>(g, rank, S.team, S.xcd_order, Gop, sh);
-  }
-
-  const double relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-  if (V.out_iters && rank == 0 && threadIdx.x == 0) {
-    V.out_iters[0] = it;
-    V.out_relres[0] = relres;
-    V.out_status[0] = status;
-  }
-  return StepResult{it, status, relres};
+  return step_epilogue<R>(S, V, rank, ok, it, status, bb, rr, sh);
 }
 
 template <typename R>

@@ -190,3 +190,39 @@ def test_closure_and_jacobi_errors():
     with pytest.raises(_lib.NHError) as e:
         _check(s.lib.nh_set_grid(s._ctx, 4, 2, 3, 1.0, 1.0, 1.0), s._ctx, "nh_set_grid")
     assert e.value.code == _lib.NH_EINVAL
+
+
+@pytest.mark.parametrize("K", [1, 4, 9])
+@pytest.mark.parametrize("case", [(64, 64, 16, 3), (37, 20, 5, 4), (50, 9, 7, 3), (3, 3, 16, 3), (70, 17, 3, 2)])
+def test_jacobi_blocked_kernel_matches_oracle(K, case):
+    """FP32 fixed-K steps on thin grids (nz <= 16) take the temporally blocked
+    kernel (K sweeps in phases of 4 between team barriers, overlapped tiles):
+    against the oracle for zero-flux, periodic and Robin closures, ragged
+    tiles, grids narrower than a tile, phases shorter than 4; and against the
+    streaming kernel (forced by an explicit tile depth) to 1e-5."""
+    nx, ny, nz, nsteps = case
+    for periodic, robin in ((False, 0.0), (True, 0.0), (True, 0.6)):
+        say("blocked jacobi K", K, case, "periodic", periodic, "robin", robin)
+        w = wl.small_problem(nx, ny, nz, nsteps, seed=K + nx + ny, dt=0.4, precision="f32")
+        gs = wl.random_surface_weights(nsteps, ny, nx, seed=400 + K)
+        src = orc.source_series(w.q_xy, w.q_t)
+        h = (0.9, 1.1, 0.5)
+        opt = dict(h=h, periodic=periodic, robin=robin, jacobi_k=K)
+        S_o, T_o, _ = orc.forward(w.alpha, src, w.dt, **opt)
+        G_o, dq_o, mu1_o, _ = orc.adjoint(w.alpha, T_o, gs, w.dt, **opt)
+        outs = []
+        for tz in (0, 1):
+            s = Solver(nx, ny, nz, h=h, periodic=periodic, robin=robin, jacobi_k=K, tile_z=tz)
+            S = s.forward(dev(w.alpha, torch.float32), dev(w.q_xy, torch.float32), w.q_t, w.dt, nsteps)
+            st = s.stats()
+            assert st["block_threads"] == (512 if tz == 0 else 1024)
+            assert st["fwd_iters"] == K * nsteps
+            G, dq, dT0 = s.adjoint_vjp(dev(gs, torch.float32))
+            outs.append([S.cpu().numpy(), G.cpu().numpy(), dq.cpu().numpy(), dT0.cpu().numpy()])
+            s.close()
+        S, G, dq, dT0 = outs[0]
+        e = [rel_l2(S, S_o), rel_l2(G, G_o), rel_l2(dq, dq_o), rel_l2(dT0, mu1_o)]
+        d = [rel_l2(a, b) for a, b in zip(outs[0], outs[1])]
+        say("  vs oracle", e, "vs streaming", d)
+        assert e[0] <= 1e-5 and max(e[1:]) <= 1e-4
+        assert max(d) <= 1e-5
