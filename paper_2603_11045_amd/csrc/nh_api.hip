@@ -71,6 +71,8 @@ struct nh_ctx {
   // workspaces
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
   Buf tvpart;                                // per-workgroup partial sums of the TV regulariser
+  Buf jt[2];                                 // tagged iterates of the blocked fixed-K kernel
+  unsigned jt_tag = 1;                       // tag of the next launch's first phase (0: cleared)
   Buf mu[4];                                 // adjoint states, mu^n in mu[n & 3]
   Buf w[4];                                  // checkpointed forward: T^n in w[n & 3]
   int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive
@@ -293,9 +295,20 @@ nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) 
   if (sizeof(R) == 4 && c->resident)
     NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::resident_step_kernel<64>, dim3(S.team),
                                          dim3(nh::kResBlock), args, (unsigned)nh::kResLdsBytes, c->stream));
-  else if (sizeof(R) == 4 && c->jac_tb)
-    NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::jacobi_step_kernel<nh::kJacNZ>, dim3(S.team),
+  else if (sizeof(R) == 4 && c->jac_tb) {
+    // phase tags only grow between clears of the tagged buffers, so no stale word can match
+    const unsigned phases = (unsigned)((S.jacobi_k + nh::kJacS - 1) / nh::kJacS);
+    if (c->jt_tag > 0xFFFFFFF0u - phases) {
+      for (Buf& b : c->jt) NH_TRY(fill<unsigned long long>(c, (unsigned long long*)b.p, c->geom.ng, 0ull));
+      c->jt_tag = 1;
+    }
+    S.jt[0] = (unsigned long long*)c->jt[0].p;
+    S.jt[1] = (unsigned long long*)c->jt[1].p;
+    S.jtag = c->jt_tag;
+    c->jt_tag += phases;
+    NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::jacobi_step_kernel<nh::kJacH>, dim3(S.team),
                                          dim3(nh::kJacBlock), args, 0, c->stream));
+  }
   else
     NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(nh::Cfg<R>::kBlock),
                                          args, 0, c->stream));
@@ -493,6 +506,14 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
     NH_HIP(c, hipMemsetAsync(c->flag.p, 0, 64, c->stream));
   }
   NH_TRY(ensure(c, c->steps, step_out_bytes(nsteps)));
+  if (c->jac_tb) {
+    const size_t tb = sizeof(unsigned long long) * (size_t)c->geom.ng;
+    if (c->jt[0].bytes < tb || c->jt[1].bytes < tb) {
+      for (Buf& b : c->jt) NH_TRY(ensure(c, b, tb));
+      for (Buf& b : c->jt) NH_TRY(fill<unsigned long long>(c, (unsigned long long*)b.p, c->geom.ng, 0ull));
+      c->jt_tag = 1;
+    }
+  }
   return NH_OK;
 }
 
@@ -565,6 +586,23 @@ nh_status forward_step(nh_ctx* c, int n, const R* const (&h)[3], R* x, const R* 
     // stamps: start, set-up sweep(s) and reduction(s), then per iteration its
     // sweep(s) and reduction(s): two pairs (variant 0) or one pair (variant 1)
     const double us = 1e3 / (double)c->wallclock_khz;
+    if (c->jac_tb) {
+      // stamps: start, set-up, then per phase: iterate loaded, sweeps done, barrier passed
+      const long long* t = tall.data();
+      int m = 0;
+      while (m < cap && t[m] != 0) ++m;
+      double ld = 0, sw = 0, br = 0;
+      const int np = m > 2 ? (m - 2) / 3 : 0;
+      for (int k = 0; k < np; ++k) {
+        ld += (t[2 + 3 * k] - t[1 + 3 * k]) * us;
+        sw += (t[3 + 3 * k] - t[2 + 3 * k]) * us;
+        br += (t[4 + 3 * k] - t[3 + 3 * k]) * us;
+      }
+      std::fprintf(stderr, "[nh trace] step %d rank %d blocked fixed-K: set-up %.2f us, %d phases, mean us per phase: "
+                   "load %.2f, sweeps %.2f, store+barrier %.2f\n", n, S.trace_rank, m > 1 ? (t[1] - t[0]) * us : 0.0,
+                   np, np ? ld / np : 0.0, np ? sw / np : 0.0, np ? br / np : 0.0);
+      return NH_OK;
+    }
     const int head = c->variant == 0 ? 3 : 5, per = c->variant == 0 ? 4 : (S.trace_detail ? 5 : 2);
     const int nranks = c->trace_rank < 0 ? c->team : 1;
     for (int r = 0; r < nranks; ++r) {
@@ -902,7 +940,7 @@ nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
     if (std::getenv("NH_TRACE_STEP"))
       std::fprintf(stderr, "[nh] resident kernel: %zu B LDS, %d workgroups per CU\n", nh::kResLdsBytes, c->res_occ);
     int jo = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&jo, (const void*)nh::jacobi_step_kernel<nh::kJacNZ>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&jo, (const void*)nh::jacobi_step_kernel<nh::kJacH>,
                                                      nh::kJacBlock, 0) == hipSuccess)
       c->jac_occ = jo;
     (void)hipGetLastError();
@@ -1098,7 +1136,8 @@ void nh_destroy(nh_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
-                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart};
+                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart,
+                 &c->jt[0], &c->jt[1]};
   for (Buf* b : bufs) release(c, *b);
   for (Buf& b : c->mu) release(c, b);
   for (Buf& b : c->w) release(c, b);

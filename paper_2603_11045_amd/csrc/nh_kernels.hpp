@@ -78,7 +78,9 @@ struct StepArgs {
   R* s1;
   int variant;                              // 0: two reductions per iteration, 1: one
   int jacobi_k;                             // > 0: K Jacobi sweeps from h1 instead of CG
-  int jtx, jty;                             // temporally blocked fixed-K kernel: interior tiles per axis
+  int jtx, jty;                             // temporally blocked fixed-K kernel: interior tiles per axis,
+  unsigned long long* jt[2];                //   its tagged iterate buffers (value | tag << 32) and the
+  unsigned jtag;                            //   tag of this launch's first phase
   const R* top_src;                         // [ny][nx] added on k = 0 (forward q_xy, adjoint g^n)
   R top_scale;                              // forward dt*q_t[n-1], adjoint 1
   R* surf_out;                              // frame of the solution on k = 0 (or null), times

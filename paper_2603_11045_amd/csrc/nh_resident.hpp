@@ -57,11 +57,11 @@ constexpr size_t kResLdsBytes =
 // Every value another workgroup reads was written with device-scope stores,
 // so the publication needs only the completion of this workgroup's stores (a
 // full s_waitcnt in every wave) and no cache maintenance. Slots: 2 * team.
-template <int NV>
+template <int NV, int BLOCK = kResBlock>
 __device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank, unsigned long long& epoch,
                                              double (&v)[NV], ResRed* rs) {
   __builtin_amdgcn_s_waitcnt(0);
-  block_sum<NV, kResBlock / 64>(v, rs->red, rs->bc);
+  block_sum<NV, BLOCK / 64>(v, rs->red, rs->bc);
   if (S.team == 1) return true;
   const unsigned long long e = ++epoch;
   Slot* slots = (Slot*)S.slots + (size_t)(e & 1) * S.team;
@@ -76,7 +76,7 @@ __device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank,
 #pragma unroll
   for (int i = 0; i < NV; ++i) s[i] = 0.0;
   int ok = 1;
-  for (int b = threadIdx.x; b < S.team; b += kResBlock) {
+  for (int b = threadIdx.x; b < S.team; b += BLOCK) {
     if (b == rank) {
 #pragma unroll
       for (int i = 0; i < NV; ++i) s[i] += v[i];
@@ -91,7 +91,7 @@ __device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank,
     for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
   }
   ok = __syncthreads_and(ok);
-  block_sum<NV, kResBlock / 64>(s, rs->red, rs->bc);
+  block_sum<NV, BLOCK / 64>(s, rs->red, rs->bc);
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = s[i];
   if (!ok && threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
