@@ -88,6 +88,7 @@ typedef struct {
     int tile_x, tile_y, tile_z; /* tile extents of the stencil kernels */
     int resident;               /* 1: the register-resident step kernel runs this grid */
     int resident_occupancy;     /* workgroups of that kernel that fit one CU (0: unusable) */
+    int jacobi_blocked;         /* 1: fixed-K steps run on the temporally blocked kernel */
 } nh_stats;
 
 /* Create a context on HIP device `hip_device`. All work of the context is

@@ -63,6 +63,7 @@ class nh_stats(ctypes.Structure):
         ("tile_z", ctypes.c_int),
         ("resident", ctypes.c_int),
         ("resident_occupancy", ctypes.c_int),
+        ("jacobi_blocked", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -203,6 +203,7 @@ void plan(nh_ctx* c, int occ, int block, bool resident_ok = false, bool tb_ok = 
       c->st.tile_z = c->nz;
       c->st.resident = 0;
       c->st.resident_occupancy = c->res_occ;
+      c->st.jacobi_blocked = 1;
       return;
     }
   }
@@ -276,6 +277,7 @@ void plan(nh_ctx* c, int occ, int block, bool resident_ok = false, bool tb_ok = 
   c->st.tile_z = g.TZ;
   c->st.resident = c->resident ? 1 : 0;
   c->st.resident_occupancy = c->res_occ;
+  c->st.jacobi_blocked = 0;
 }
 
 template <typename R>
