@@ -212,6 +212,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--layered", action="store_true")
     ap.add_argument("--seed", type=int, default=6)
+    ap.add_argument("--log-every", type=int, default=100)
     a = ap.parse_args(argv)
     w = wl.paper_64x64x16(seed=a.seed, nsteps=a.nsteps, layered=a.layered)
     dev = torch.device("cuda", 0)
@@ -224,7 +225,8 @@ def main(argv=None):
     if a.lr is not None:
         cfg.lr = a.lr
     bulk = float(np.median(w.alpha))
-    r = reconstruct(w, target, cfg, alpha_true=w.alpha, bulk_mean=bulk, log=print)
+    r = reconstruct(w, target, cfg, alpha_true=w.alpha, bulk_mean=bulk, log=lambda m: print(m, flush=True),
+                    log_every=a.log_every)
     print(json.dumps({"method": a.method, "iters": a.iters, "ms_per_iter": r.ms_per_iter, "metrics": r.metrics}))
 
 
