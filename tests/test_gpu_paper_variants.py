@@ -227,3 +227,47 @@ def test_jacobi_blocked_kernel_matches_oracle(K, case):
         say("  vs oracle", e, "vs streaming", d)
         assert e[0] <= 1e-5 and max(e[1:]) <= 1e-4
         assert max(d) <= 1e-5
+
+
+def test_closure_gradient_finite_differences():
+    """With periodic lateral faces and a Robin back face (FP64, CG to 1e-13),
+    central differences of the MSE loss in single voxels (step 1e-4 alpha_p)
+    and along one random direction match the adjoint gradient; the Robin sink
+    does not depend on alpha, so the gradient formula is the zero-flux one on
+    the wrapped faces."""
+    nx, ny, nz, nsteps = 20, 16, 8, 8
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=51, dt=0.8, precision="f64")
+    h = (0.8, 1.0, 0.5)
+    s = Solver(nx, ny, nz, h=h, rtol=1e-13, max_iter=5000, precision="f64", periodic=True, robin=0.4)
+    q = dev(w.q_xy, torch.float64)
+    target = s.forward(dev(w.alpha_target, torch.float64), q, w.q_t, w.dt, nsteps).clone()
+    m = target.numel()
+
+    def loss(a_np):
+        S = s.forward(dev(a_np, torch.float64), q, w.q_t, w.dt, nsteps)
+        return float(((S - target) ** 2).sum() / m)
+
+    a = w.alpha.astype(np.float64)
+    S = s.forward(dev(a, torch.float64), q, w.q_t, w.dt, nsteps)
+    G = s.adjoint(((2.0 / m) * (S - target)).contiguous()).cpu().numpy()
+    gmax = float(np.abs(G).max())
+    rng = np.random.default_rng(52)
+    # voxels on the wrapped edges and the Robin plane, and random ones
+    vox = [(0, 0, 0), (0, ny - 1, nx - 1), (nz - 1, 3, 0), (nz - 1, ny - 1, 7), (2, 0, nx - 1)]
+    vox += [(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(7)]
+    worst = 0.0
+    for p in vox:
+        ap, am = a.copy(), a.copy()
+        hp = 1e-4 * a[p]
+        ap[p] += hp
+        am[p] -= hp
+        g_fd = (loss(ap) - loss(am)) / (2 * hp)
+        tol = 1e-5 * max(abs(g_fd), 1e-3 * gmax)
+        worst = max(worst, abs(g_fd - G[p]) / tol)
+        assert abs(g_fd - G[p]) <= tol, (p, g_fd, G[p])
+    v = rng.standard_normal(a.shape) * a
+    e = 1e-5
+    d_v = (loss(a + e * v) - loss(a - e * v)) / (2 * e)
+    gv = float(np.sum(G * v))
+    say("closure FD: worst |g_fd - g| / tol", worst, "direction", gv, d_v)
+    assert abs(gv - d_v) <= 1e-6 * abs(d_v)
