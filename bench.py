@@ -56,10 +56,14 @@ def make_workload(name: str, nsteps: int = 0):
     return w
 
 
-def cpu_baseline(w, sample_steps: int):
+def cpu_baseline(w, sample_steps: int, threads: int = 0):
     """The FP64 oracle, as it stands, on the first `sample_steps` steps of the
-    same workload (forward + adjoint at the workload's own rtol)."""
+    same workload (forward + adjoint at the workload's own rtol), on all the
+    host's cores or on `threads` of them."""
     from oracle import heat as orc
+
+    if threads > 0:
+        orc.set_num_threads(threads)
 
     src = orc.source_series(w.q_xy, w.q_t)[:sample_steps]
     t0 = time.perf_counter()
@@ -169,6 +173,8 @@ def main():
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=16)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="OpenMP threads of the oracle timing (0 = all the host gives it)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
     ap.add_argument("--ckpt-overhead", action="store_true",
                     help="with checkpointing on: also time the same passes with full trajectory storage "
@@ -366,7 +372,7 @@ def main():
         }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps))
+        cb = cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps), args.cpu_threads)
         rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     print(json.dumps(rec), flush=True)
 

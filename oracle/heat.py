@@ -69,6 +69,7 @@ def _load():
                                 ctypes.c_int, dp]
         lib.orc_tlm.restype = ctypes.c_int
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -99,6 +100,11 @@ def _grid(alpha: np.ndarray, h=(1.0, 1.0, 1.0), periodic=False, robin=0.0, jacob
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Run the oracle on n OpenMP threads from now on (timing only)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def apply_A(alpha, x, dt, h=(1.0, 1.0, 1.0), periodic=False, robin=0.0) -> np.ndarray:

@@ -370,3 +370,13 @@ int orc_num_threads(void) {
     }
     return t;
 }
+
+/* Use n OpenMP threads from now on (n >= 1; for timing the oracle on one core). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -149,3 +149,31 @@ def test_fp32_gradient_matches_fp64_at_full_size(fd_setup):
     say("FP32 (rtol 1e-6) vs FP64 (rtol 1e-13) gradient at 256x256x64,", NSTEPS_FD, "steps:", e)
     assert s.stats()["resident"] == 1
     assert e <= 1e-4
+
+
+def test_long_512x512x64_short_horizon_matches_oracle():
+    """The 512x512x64 grid (4x what the registers of the chip hold, so the
+    streaming kernel runs it, as in the benchmark's long-horizon line), two
+    steps with a checkpoint after each (the adjoint recomputes both segments),
+    against the FP64 oracle at rtol 1e-12: surface 1e-5, dL/dalpha 1e-4."""
+    w = wl.long_512x512x64(nsteps=2)
+    src = orc.source_series(w.q_xy, w.q_t)
+    say("512x512x64: oracle target forward")
+    St, _, _ = orc.forward(w.alpha_target, src, w.dt, rtol=1e-12, keep_states=False)
+    say("512x512x64: oracle forward")
+    S_o, T_all, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-12)
+    _, gs = orc.mse_loss_and_grad(S_o, St)
+    say("512x512x64: oracle adjoint")
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_all, gs, w.dt, rtol=1e-12)
+    del T_all
+    say("512x512x64: GPU")
+    s = Solver(w.nx, w.ny, w.nz, rtol=w.rtol, max_iter=2000, checkpoint_every=1)
+    S = s.forward(dev(w.alpha, torch.float32), dev(w.q_xy, torch.float32), w.q_t, w.dt, w.nsteps)
+    G = s.adjoint(dev(gs, torch.float32)).cpu().numpy()
+    st = s.stats()
+    eS, eG = rel_l2(S.cpu().numpy(), S_o), rel_l2(G, G_o)
+    say("512x512x64, 2 steps: resident", st["resident"], "team", st["team_blocks"], "recomputed steps",
+        st["recompute_steps"], "S rel", eS, "G rel", eG)
+    assert st["resident"] == 0 and st["recompute_steps"] == 2     # both one-step segments
+    assert eS <= 1e-5
+    assert eG <= 1e-4
