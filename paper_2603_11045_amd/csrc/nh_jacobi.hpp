@@ -44,7 +44,7 @@ constexpr int kJacIY = kJacEY - 2 * kJacS;
 constexpr int kJacNZ = 16;                  // largest nz the kernel takes
 constexpr int kJacH = kJacNZ / 2;           // cells per thread
 
-// LDS: xs the exchanged iterate, bs and rs_ the per-cell b and 1/D, each
+// LDS: xs the exchanged iterate, bs and rds the per-cell b and 1/D, each
 // [2H planes][kJacCols columns].
 template <int H>
 __device__ StepResult jacobi_tb_step(const StepArgs<float>& S, const StepVar<float>& V, int rank, float* xs,
@@ -69,7 +69,7 @@ __device__ StepResult jacobi_tb_step(const StepArgs<float>& S, const StepVar<flo
   const bool inner = lx >= kJacS && lx < kJacS + kJacIX && ly >= kJacS && ly < kJacS + kJacIY && ux < g.nx &&
                      uy < g.ny;
   const bool hl = lx > 0, hr = lx < kJacEX - 1, hd = ly > 0, hu = ly < kJacEY - 1;
-  const bool hb = k0 > 0, ha = k0 + H < 2 * H;   // the other half of the column lies below / above
+  const bool hb = k0 > 0, ha = k0 + H < 2 * H;   // the other half of the column holds cell k0-1 / k0+H
   const int nz = g.nz;
   const long long nxy = g.nxy;
   unsigned long long red = V.epoch_base;
