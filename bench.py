@@ -161,6 +161,25 @@ def invert_iterations(dev, iters: int):
     return out
 
 
+def serve_section(n_jobs: int) -> dict:
+    """The first n_jobs of the Poisson serving stream through the batching
+    server, and one by one through the single-problem path as the baseline."""
+    from paper_2603_11045_amd import serve
+
+    print(f"[bench] serving: first {n_jobs} jobs of the Poisson stream (20 jobs/s, seed 5)",
+          file=sys.stderr, flush=True)
+    sv = serve.benchmark(n_jobs, log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
+    b, q = sv["batched"], sv["sequential"]
+    return {
+        "jobs": b["jobs"], "rate_jobs_per_s": sv["rate_jobs_per_s"], "hbm_budget_gb": sv["hbm_budget_gb"],
+        "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"], "jobs_per_s": b["jobs_per_s"],
+        "voxel_steps_per_s": b["voxel_steps_per_s"], "workgroup_busy_frac": b["workgroup_busy_frac"],
+        "sequential": {"p50_ms": q["p50_ms"], "p99_ms": q["p99_ms"], "jobs_per_s": q["jobs_per_s"]},
+        "speedup": {"throughput": sv["speedup_throughput"], "p50": sv["speedup_p50"],
+                    "p99": sv["speedup_p99"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,29 +370,25 @@ def main():
         full.close()
     del solver, alpha, q_xy, target
     torch.cuda.empty_cache()
-    if args.paper_reps > 0:
-        rec["paper_fixed_k"] = paper_fixed_k(Solver, dev, args.paper_reps)
-    if args.invert_iters > 0:
-        rec["invert"] = invert_iterations(dev, args.invert_iters)
-    if args.serve_jobs > 0:
-        from paper_2603_11045_amd import serve
+    def section(name, fn):
+        # the extra sections never cost the main line: a failure is recorded instead
+        try:
+            rec[name] = fn()
+        except Exception as e:  # noqa: BLE001
+            print(f"[bench] section {name} failed: {e!r}", file=sys.stderr, flush=True)
+            rec[name] = {"error": repr(e)}
 
-        print(f"[bench] serving: first {args.serve_jobs} jobs of the Poisson stream (20 jobs/s, seed 5)",
-              file=sys.stderr, flush=True)
-        sv = serve.benchmark(args.serve_jobs, log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
-        b, q = sv["batched"], sv["sequential"]
-        rec["serve"] = {
-            "jobs": b["jobs"], "rate_jobs_per_s": sv["rate_jobs_per_s"], "hbm_budget_gb": sv["hbm_budget_gb"],
-            "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"], "jobs_per_s": b["jobs_per_s"],
-            "voxel_steps_per_s": b["voxel_steps_per_s"], "workgroup_busy_frac": b["workgroup_busy_frac"],
-            "sequential": {"p50_ms": q["p50_ms"], "p99_ms": q["p99_ms"], "jobs_per_s": q["jobs_per_s"]},
-            "speedup": {"throughput": sv["speedup_throughput"], "p50": sv["speedup_p50"],
-                        "p99": sv["speedup_p99"]},
-        }
+    if args.paper_reps > 0:
+        section("paper_fixed_k", lambda: paper_fixed_k(Solver, dev, args.paper_reps))
+    if args.invert_iters > 0:
+        section("invert", lambda: invert_iterations(dev, args.invert_iters))
+    if args.serve_jobs > 0:
+        section("serve", lambda: serve_section(args.serve_jobs))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps), args.cpu_threads)
-        rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        section("cpu_baseline", lambda: {k: v for k, v in cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps),
+                                                                         args.cpu_threads).items()
+                                         if k in ("value", "unit", "cores", "kind", "sample")})
     print(json.dumps(rec), flush=True)
 
 
