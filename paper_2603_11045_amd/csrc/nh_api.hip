@@ -185,11 +185,16 @@ void plan(nh_ctx* c, int occ, int block, bool resident_ok = false, bool tb_ok = 
       g.TX = 64;
       g.TY = nh::kJacBlock / 64;
       g.txs = 6;
-      g.TZ = c->nz;
       g.ntx = (g.nx + g.TX - 1) / g.TX;
       g.nty = (g.ny + g.TY - 1) / g.TY;
-      g.ntz = 1;
-      g.ntiles = g.ntx * g.nty;
+      {
+        // split in z so that the team shares the gradient pass
+        const long long xy = (long long)g.ntx * g.nty;
+        const long long want_ntz = std::max<long long>(1, (nt + xy - 1) / xy);
+        g.TZ = (int)std::max<long long>(1, (g.nz + want_ntz - 1) / want_ntz);
+      }
+      g.ntz = (g.nz + g.TZ - 1) / g.TZ;
+      g.ntiles = g.ntx * g.nty * g.ntz;
       c->geom = g;
       c->team = (int)nt;
       c->jac_tb = true;
