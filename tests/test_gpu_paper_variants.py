@@ -271,3 +271,28 @@ def test_closure_gradient_finite_differences():
     gv = float(np.sum(G * v))
     say("closure FD: worst |g_fd - g| / tol", worst, "direction", gv, d_v)
     assert abs(gv - d_v) <= 1e-6 * abs(d_v)
+
+
+def test_jacobi_blocked_zero_time_limit_recovers():
+    """A zero time limit on every wait of the blocked kernel (forced from the
+    host) ends the call early, with NH_ETIMEOUT if some wait was cut short, and
+    never hangs; with the limit restored the same context reproduces a fresh
+    context's result bit for bit (the tagged buffers' stale words from the cut
+    launches do not match later tags)."""
+    w = wl.paper_64x64x16(nsteps=6)
+    a = dev(w.alpha, torch.float32)
+    q = dev(w.q_xy, torch.float32)
+    s = Solver(w.nx, w.ny, w.nz, h=w.h, periodic=True, jacobi_k=w.jacobi_k)
+    s.set_barrier_timeout(0.0)
+    try:
+        s.forward(a, q, w.q_t, w.dt, w.nsteps)
+        say("zero time limit: no wait was cut short")
+    except _lib.NHError as e:
+        assert e.code == _lib.NH_ETIMEOUT
+        say("zero time limit: NH_ETIMEOUT")
+    s.set_barrier_timeout(20.0)
+    S1 = s.forward(a, q, w.q_t, w.dt, w.nsteps).clone()
+    fresh = Solver(w.nx, w.ny, w.nz, h=w.h, periodic=True, jacobi_k=w.jacobi_k)
+    S2 = fresh.forward(a, q, w.q_t, w.dt, w.nsteps)
+    assert s.stats()["jacobi_blocked"] == 1
+    assert torch.equal(S1, S2)
