@@ -73,6 +73,11 @@ struct nh_ctx {
   Buf tvpart;                                // per-workgroup partial sums of the TV regulariser
   Buf jt[2];                                 // tagged iterates of the blocked fixed-K kernel
   unsigned jt_tag = 1;                       // tag of the next launch's first phase (0: cleared)
+  // steps of the blocked fixed-K kernel waiting to be launched together
+  nh::JacSteps jq{};
+  nh::StepArgs<float> jq_base{};
+  int jq_ev = -1;                            // event slot of the first queued step (-1: none)
+  unsigned long long jq_epoch = 0;
   Buf mu[4];                                 // adjoint states, mu^n in mu[n & 3]
   Buf w[4];                                  // checkpointed forward: T^n in w[n & 3]
   int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive
@@ -88,6 +93,8 @@ struct nh_ctx {
   nh_stats st{};
   std::string err = "";
   std::vector<hipEvent_t> ev;
+  std::vector<char> ev_rec;                  // event pair i was recorded (a queued step records none)
+  long long kernel_launches = 0;             // step-kernel launches so far
   // diagnostics: NH_TRACE_STEP=n prints phase timings of forward step n
   int trace_step = 0;
   int trace_rank = 0;
@@ -290,8 +297,70 @@ int occupancy(nh_ctx* c) {
   return sizeof(R) == 4 ? c->occ_f32 : c->occ_f64;
 }
 
+// Launch the queued steps of the blocked fixed-K kernel as one launch, timed
+// with the event pair of the first of them.
+nh_status flush_steps(nh_ctx* c) {
+  if (c->jq.count == 0) return NH_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profile && c->jq_ev >= 0) {
+    e0 = c->ev[2 * c->jq_ev];
+    e1 = c->ev[2 * c->jq_ev + 1];
+    NH_HIP(c, hipEventRecord(e0, c->stream));
+  }
+  void* args[] = {(void*)&c->jq_base, (void*)&c->jq};
+  NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::jacobi_steps_kernel<nh::kJacH>, dim3(c->jq_base.team),
+                                       dim3(nh::kJacBlock), args, 0, c->stream));
+  if (e1) {
+    NH_HIP(c, hipEventRecord(e1, c->stream));
+    c->ev_rec[c->jq_ev] = 1;
+  }
+  ++c->kernel_launches;
+  c->jq.count = 0;
+  c->jq_ev = -1;
+  return NH_OK;
+}
+
+// Queue one step of the blocked fixed-K kernel. Steps of one sweep share
+// everything but their StepVar fields; step i of a launch gets the epoch
+// base B + i (B even), so consecutive steps' final reductions use
+// alternating slot banks. Returns in *launched whether the step was
+// launched now (the caller's event slot is then used).
+nh_status queue_step(nh_ctx* c, StepArgs<float>& S, int slot_ev, bool* launched) {
+  const unsigned phases = (unsigned)((S.jacobi_k + nh::kJacS - 1) / nh::kJacS);
+  if (c->jq.count > 0 && (S.mode != c->jq_base.mode || S.G != c->jq_base.G || S.alpha != c->jq_base.alpha))
+    NH_TRY(flush_steps(c));
+  if (c->jt_tag > 0xFFFFFFF0u - phases) {
+    NH_TRY(flush_steps(c));
+    for (Buf& b : c->jt) NH_TRY(fill<unsigned long long>(c, (unsigned long long*)b.p, c->geom.ng, 0ull));
+    c->jt_tag = 1;
+  }
+  S.jt[0] = (unsigned long long*)c->jt[0].p;
+  S.jt[1] = (unsigned long long*)c->jt[1].p;
+  S.jtag = c->jt_tag;
+  c->jt_tag += phases;
+  if (c->jq.count == 0) {
+    c->jq_epoch = (++c->launch_ctr) << 24;
+    c->jq_ev = slot_ev;
+  }
+  S.epoch_base = c->jq_epoch + (unsigned long long)c->jq.count;
+  if (c->jq.count == 0) c->jq_base = S;
+  c->jq.v[c->jq.count++] = nh::step_var(S);
+  *launched = c->jq.count == nh::kJacBatch;
+  if (*launched) NH_TRY(flush_steps(c));
+  return NH_OK;
+}
+
 template <typename R>
 nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) {
+  if constexpr (sizeof(R) == 4) {
+    if (c->jac_tb && !S.trace) {
+      bool launched = false;
+      NH_TRY(queue_step(c, S, slot_ev, &launched));
+      (void)t_kernel;
+      return NH_OK;
+    }
+  }
+  NH_TRY(flush_steps(c));
   void* args[] = {(void*)&S};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profile) {
@@ -319,7 +388,11 @@ nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) 
   else
     NH_HIP(c, hipLaunchCooperativeKernel((const void*)nh::step_kernel<R>, dim3(S.team), dim3(nh::Cfg<R>::kBlock),
                                          args, 0, c->stream));
-  if (c->profile) NH_HIP(c, hipEventRecord(e1, c->stream));
+  if (c->profile) {
+    NH_HIP(c, hipEventRecord(e1, c->stream));
+    c->ev_rec[slot_ev] = 1;
+  }
+  ++c->kernel_launches;
   (void)t_kernel;
   return NH_OK;
 }
@@ -328,13 +401,17 @@ nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) 
 // the elapsed times are collected (one stream sync) and the pool reused.
 constexpr int kEvPairs = 512;
 
+// Also launches any queued steps first (their events are among those collected).
 nh_status collect_events(nh_ctx* c, int used, double* acc) {
+  NH_TRY(flush_steps(c));
   if (!c->profile || used == 0) return NH_OK;
   NH_HIP(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i < used; ++i) {
+    if (!c->ev_rec[i]) continue;
     float ms = 0;
     NH_HIP(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
     *acc += ms * 1e-3;
+    c->ev_rec[i] = 0;
   }
   return NH_OK;
 }
@@ -342,6 +419,7 @@ nh_status collect_events(nh_ctx* c, int used, double* acc) {
 nh_status ensure_events(nh_ctx* c) {
   if (!c->profile || !c->ev.empty()) return NH_OK;
   c->ev.resize(2 * kEvPairs);
+  c->ev_rec.assign(kEvPairs, 0);
   for (auto& e : c->ev) NH_HIP(c, hipEventCreate(&e));
   return NH_OK;
 }
@@ -681,6 +759,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
   c->st.fwd_iters = 0;
   c->st.fwd_steps = nsteps;
   c->st.launches_fwd = 0;
+  const long long kl0 = c->kernel_launches;
   c->st.t_kernel_fwd_s = 0;
   double tk = 0;
   int used = 0;
@@ -697,10 +776,11 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     if (ckpt) ck = (R*)c->traj.p + (size_t)(n / k - 1) * 3 * g.ng;
     NH_TRY(forward_step<R>(c, n, h, x, qsrc, dt, q_t[n - 1], T_surf + (size_t)(n - 1) * g.nxy,
                            ck, 0, used));
-    if (ckpt)
+    if (ckpt) {
+      NH_TRY(flush_steps(c));               // queued steps precede the copies on the stream
       for (int d = 1; d <= 2 && n - d >= 1; ++d)
         NH_HIP(c, hipMemcpyAsync(ck + (size_t)d * g.ng, state(n - d), vb, hipMemcpyDeviceToDevice, c->stream));
-    ++c->st.launches_fwd;
+    }
     if (c->profile && ++used == kEvPairs) {
       NH_TRY(collect_events(c, used, &tk));
       used = 0;
@@ -709,6 +789,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
   NH_TRY(collect_events(c, used, &tk));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   c->st.t_kernel_fwd_s = tk;
+  c->st.launches_fwd = c->kernel_launches - kl0;
   NH_TRY(check_flag(c));
 
   int max_it = 0, any = 0;
@@ -757,6 +838,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   c->st.adj_steps = N;
   c->st.recompute_steps = 0;
   c->st.launches_adj = 0;
+  const long long kl0 = c->kernel_launches;
   double tk = 0;
   int used = 0;
   double bytes = 0;
@@ -780,7 +862,6 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
     S.out_relres = o.relres;
     S.out_status = o.status;
     NH_TRY(launch_step<R>(c, S, used, nullptr));
-    ++c->st.launches_adj;
     if (c->profile && ++used == kEvPairs) {
       NH_TRY(collect_events(c, used, &tk));
       used = 0;
@@ -808,7 +889,6 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
         const R* const h[3] = {state(n - 1), state(n - 2), state(n - 3)};
         NH_TRY(forward_step<R>(c, n, h, seg + (size_t)(n - s - 1) * g.ng, qxy, dt,
                                c->saved_qt[n - 1], nullptr, nullptr, 2, used));
-        ++c->st.launches_adj;
         ++c->st.recompute_steps;
         if (c->profile && ++used == kEvPairs) {
           NH_TRY(collect_events(c, used, &tk));
@@ -818,9 +898,11 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
       for (int n = e; n >= s + 1; --n) NH_TRY(adj_step(n, seg + (size_t)(n - s - 1) * g.ng));
     }
   }
+  NH_TRY(flush_steps(c));                   // queued steps precede the copy on the stream
   if (dT0) NH_HIP(c, hipMemcpyAsync(dT0, M[1 & 3], vb, hipMemcpyDeviceToDevice, c->stream));   // mu^1
   NH_TRY(collect_events(c, used, &tk));
   NH_HIP(c, hipStreamSynchronize(c->stream));
+  c->st.launches_adj = c->kernel_launches - kl0;
   c->st.t_kernel_adj_s = tk;
   NH_TRY(check_flag(c));
 

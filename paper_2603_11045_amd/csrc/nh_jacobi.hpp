@@ -51,10 +51,14 @@ __device__ StepResult jacobi_tb_step(const StepArgs<float>& S, const StepVar<flo
                                      float* bs, float* rds, Smem<float>& sh, ResRed* rs) {
   constexpr int C = kJacCols;
   const Geom& g = S.g;
-  const int tid = threadIdx.x;
+  // a caller that loops over steps must not keep one step's per-thread
+  // geometry live into the next: laundered, it is recomputed per step
+  int tid = threadIdx.x, rank_l = rank;
+  asm volatile("" : "+v"(tid));
+  asm volatile("" : "+s"(rank_l));
   const int c = tid % C, k0 = (tid / C) * H;
   const int lx = c % kJacEX, ly = c / kJacEX;
-  const int tx = rank % S.jtx, ty = rank / S.jtx;
+  const int tx = rank_l % S.jtx, ty = rank_l / S.jtx;
   const int ux = tx * kJacIX - kJacS + lx, uy = ty * kJacIY - kJacS + ly;   // unwrapped grid column
   int gx = ux, gy = uy;
   bool valid;
@@ -134,7 +138,7 @@ __device__ StepResult jacobi_tb_step(const StepArgs<float>& S, const StepVar<flo
 #pragma unroll
       for (int i = 0; i < H; ++i) x[i] = (V.xprev && valid && k0 + i < nz) ? V.xprev[base + i * nxy] : 0.f;
     } else {
-      const unsigned tag = S.jtag + (unsigned)(ph - 1);
+      const unsigned tag = V.jtag + (unsigned)(ph - 1);
       unsigned long long* src = S.jt[(ph - 1) & 1];
 #pragma unroll
       for (int i = 0; i < H; ++i) {
@@ -228,7 +232,7 @@ __device__ StepResult jacobi_tb_step(const StepArgs<float>& S, const StepVar<flo
       bb = v2[0];
       rr = v2[1];
     } else if (inner) {
-      const unsigned long long tag = (unsigned long long)(S.jtag + (unsigned)ph) << 32;
+      const unsigned long long tag = (unsigned long long)(V.jtag + (unsigned)ph) << 32;
       unsigned long long* dst = S.jt[ph & 1];
 #pragma unroll
       for (int i = 0; i < H; ++i)
@@ -251,6 +255,31 @@ __global__ void __launch_bounds__(kJacBlock, 1) jacobi_step_kernel(StepArgs<floa
   __shared__ float bs[2 * H * kJacCols];
   __shared__ float rds[2 * H * kJacCols];
   jacobi_tb_step<H>(S, step_var(S), blockIdx.x, xs, bs, rds, sh, &rs);
+}
+
+// Several consecutive steps of one sweep in one launch: step i takes its
+// per-step fields from tab.v[i] (the rest of S is the same for all of them).
+// Each step ends with a team reduction and an acquire fence, so the next
+// step reads its predecessor's state complete; the host gives step i the
+// epoch base B + i with B even, so consecutive steps' reductions alternate
+// between the two slot banks and a workgroup one step ahead never
+// overwrites a slot another still reads. This saves the ~25 us between two
+// cooperative launches per step.
+constexpr int kJacBatch = 12;               // steps per launch (their fields travel as kernel arguments)
+
+struct JacSteps {
+  StepVar<float> v[kJacBatch];
+  int count;
+};
+
+template <int H>
+__global__ void __launch_bounds__(kJacBlock, 1) jacobi_steps_kernel(StepArgs<float> S, JacSteps tab) {
+  __shared__ Smem<float> sh;
+  __shared__ ResRed rs;
+  __shared__ float xs[2 * H * kJacCols];
+  __shared__ float bs[2 * H * kJacCols];
+  __shared__ float rds[2 * H * kJacCols];
+  for (int i = 0; i < tab.count; ++i) jacobi_tb_step<H>(S, tab.v[i], blockIdx.x, xs, bs, rds, sh, &rs);
 }
 
 }  // namespace nh

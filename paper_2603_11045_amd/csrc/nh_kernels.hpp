@@ -819,6 +819,7 @@ struct StepVar {
   double* out_relres;
   int* out_status;
   unsigned long long epoch_base;
+  unsigned jtag;                            // blocked fixed-K kernel: tag of the step's first phase
 };
 
 // The CG initial guess of a step: x0 = h1 (order 0), the linear
@@ -843,7 +844,7 @@ __device__ __forceinline__ int guess_order(const StepVar<R>& V) {
 }
 
 template <typename R>
-__device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
+__host__ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   StepVar<R> V;
   V.x = S.x;
   V.xprev = S.xprev;
@@ -864,6 +865,7 @@ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
   V.out_relres = S.out_relres;
   V.out_status = S.out_status;
   V.epoch_base = S.epoch_base;
+  V.jtag = S.jtag;
   return V;
 }
 
