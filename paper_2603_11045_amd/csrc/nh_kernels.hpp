@@ -795,6 +795,7 @@ struct StepResult {
   int iters;
   int status;
   double relres;                            // ||r|| / ||b|| at exit (0 when b = 0)
+  unsigned long long epoch_end;             // epoch of the step's last team reduction
 };
 
 // The fields of a step that change from step to step; run_step takes them
@@ -906,7 +907,7 @@ __device__ StepResult step_epilogue(const StepArgs<R>& S, const StepVar<R>& V, i
     V.out_relres[0] = relres;
     V.out_status[0] = status;
   }
-  return StepResult{it, status, relres};
+  return StepResult{it, status, relres, 0ull};
 }
 
 template <typename R>
@@ -1065,7 +1066,9 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
       }
     }
   }
-  return step_epilogue<R>(S, V, rank, ok, it, status, bb, rr, sh);
+  StepResult res = step_epilogue<R>(S, V, rank, ok, it, status, bb, rr, sh);
+  res.epoch_end = red;
+  return res;
 }
 
 template <typename R>

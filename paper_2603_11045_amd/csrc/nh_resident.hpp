@@ -633,11 +633,12 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     // The solution was stored with ordinary stores (the last part after the
     // final reduction): make it visible to the whole team before a following
     // step in the same launch reads its neighbours' cells. The barrier takes
-    // the last epoch of this step's range.
+    // the next epoch of the step's sequence, so that it and the reductions
+    // before and after it (the caller starts the next step from epoch_end)
+    // alternate between the two slot banks.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    unsigned long long e = V.epoch_base + 0xFFFEull;
     double none[1] = {0.0};
-    if (!team_sum_dev<1>(S, rank, e, none, rs)) status |= kTimeout;
+    if (!team_sum_dev<1>(S, rank, red, none, rs)) status |= kTimeout;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   const double relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
@@ -646,7 +647,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     V.out_relres[0] = relres;
     V.out_status[0] = status;
   }
-  return StepResult{it, status, relres};
+  return StepResult{it, status, relres, red};
 }
 
 template <int TXC>

@@ -62,7 +62,8 @@ struct JobProg {
   long long t0, t1;           // wall clock of rank 0 at the start and end of the slice
 };
 
-constexpr int kMaxSliceSteps = 255;       // steps per slice: epoch bits 16..23 of a launch
+constexpr int kMaxSliceSteps = 255;       // steps per slice (with max_iter <= 30000 its team
+                                           // reductions stay below the 2^24 epochs of a launch)
 
 // The slice of one job for one workgroup: steps of the job until its
 // iterations in this launch reach the budget. `step(S, V)` runs one step of
@@ -94,9 +95,13 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
   }
   const StepArgs<float>& S = (const StepArgs<float>&)J.S;
   const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
+  // one running epoch through the slice: each step starts from the epoch of
+  // its predecessor's last team reduction, so epochs stay unique within the
+  // launch and consecutive reductions alternate between the slot banks
+  unsigned long long ep = J.S.epoch_base;
   while (true) {
     StepVar<float> V;
-    V.epoch_base = J.S.epoch_base + ((unsigned long long)steps << 16);
+    V.epoch_base = ep;
     V.out_iters = nullptr;                  // per-step outputs are written below
     V.out_relres = nullptr;
     V.out_status = nullptr;
@@ -139,6 +144,7 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
     V.gi = nullptr;
     V.gp[0] = V.gp[1] = V.gp[2] = 0;
     const StepResult r = step(S, V);
+    ep = r.epoch_end;
     if (k < 3) pc[k] = r.iters;
     if (m.y == 0 && threadIdx.x == 0) {
       const int slot = (fwd ? 0 : J.nsteps) + n - 1;
