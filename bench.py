@@ -292,7 +292,7 @@ def main():
     if st["resident"]:
         kname = "nh::resident_step_kernel<64>"
     elif st["jacobi_blocked"]:
-        kname = "nh::jacobi_step_kernel<8>"
+        kname = "nh::jacobi_steps_kernel<8>"
     else:
         kname = "nh::step_kernel<float>" if w.precision == "f32" else "nh::step_kernel<double>"
     if not args.no_profile and (tk_f + tk_a) > 0:
