@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="OpenMP threads of the oracle timing (0 = all the host gives it)")
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
+    ap.add_argument("--guess", default="adaptive", choices=["previous", "extrapolate", "adaptive", "projection"],
+                    help="CG initial guess of the solves")
     ap.add_argument("--ckpt-overhead", action="store_true",
                     help="with checkpointing on: also time the same passes with full trajectory storage "
                          "and report peak device memory of both")
@@ -244,7 +246,8 @@ def main():
 
     solver = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=w.rtol, max_iter=2000, checkpoint_every=ck,
                     precision=w.precision, device=0, team_blocks_max=args.team, tile_z=args.tile_z,
-                    profile=not args.no_profile, periodic=w.periodic, robin=w.robin, jacobi_k=w.jacobi_k)
+                    profile=not args.no_profile, periodic=w.periodic, robin=w.robin, jacobi_k=w.jacobi_k,
+                    initial_guess=args.guess)
     alpha = torch.from_numpy(w.alpha).to(dev)
     q_xy = torch.from_numpy(w.q_xy).to(dev)
     # synthetic measurement: the surface of the target diffusivity
@@ -329,7 +332,8 @@ def main():
         "dtype": w.precision,
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "nsteps": w.nsteps, "dt": w.dt,
-                   "rtol": w.rtol, "checkpoint_every": ck, "team_blocks": st["team_blocks"],
+                   "rtol": w.rtol, "checkpoint_every": ck, "initial_guess": args.guess,
+                   "team_blocks": st["team_blocks"],
                    "tile": [st["tile_x"], st["tile_y"], st["tile_z"]]},
         "cg_iters_per_s": iters / elapsed,
         "voxel_iters_per_s": iters * float(w.ng) / elapsed,

@@ -212,13 +212,20 @@ nh_status nh_set_cg_variant(nh_ctx *ctx, int variant);
  * mu^{n+2}, mu^{n+3} (adjoint); the extrapolation of order 1 is 2 h1 - h2 and
  * of order 2 is 3 h1 - 3 h2 + h3 (limited by the states there are). mode 0
  * starts from h1 (order 0); mode 1 from the order-2 extrapolation; mode 2
- * (default) adaptively: in each period of 32 steps of a sweep the first three
- * steps start from orders 0, 1 and 2, and the rest from the order that took
- * the fewest CG iterations (chosen on the device, so nothing synchronises).
- * All modes converge to the same tolerance. With checkpointing the three
- * states below each checkpoint are kept and recomputed steps repeat the
- * forward's choices, so recomputation stays bit for bit. Drops any saved
- * forward. */
+ * (default) adaptively: in each period of 32 steps of a sweep the first three steps
+ * start from orders 0, 1 and 2, and the rest from the order that took the
+ * fewest CG iterations (chosen on the device, so nothing synchronises); mode 3
+ * as mode 2 in the forward sweep, while every adjoint solve after
+ * the first starts from the projection of its right-hand side onto the last
+ * (up to 6) adjoint solutions, x0 = W (W^T A W)^-1 W^T c: the point of their
+ * span closest to the solution in the A-norm (Fischer's method for successive
+ * right-hand sides), computed on the device after each adjoint step (about
+ * 2k + 5 vector passes for a window of k, no host synchronisation; needs 8
+ * adjoint state buffers instead of 4 and one more vector). Fixed-K Jacobi
+ * sweeps ignore the projection. All modes converge to the same tolerance. With
+ * checkpointing the three states below each checkpoint are kept and
+ * recomputed steps repeat the forward's choices, so recomputation stays bit
+ * for bit. Drops any saved forward. */
 nh_status nh_set_initial_guess(nh_ctx *ctx, int mode);
 
 /* Time limit of the device-side team barrier in seconds (default 20). A

@@ -13,6 +13,7 @@
 #include "nh_resident.hpp"
 #include "nh_jacobi.hpp"
 #include "nh_tv.hpp"
+#include "nh_proj.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -78,9 +79,12 @@ struct nh_ctx {
   nh::StepArgs<float> jq_base{};
   int jq_ev = -1;                            // event slot of the first queued step (-1: none)
   unsigned long long jq_epoch = 0;
-  Buf mu[4];                                 // adjoint states, mu^n in mu[n & 3]
+  Buf mu[nh::kProjRing];                     // adjoint states, mu^n in mu[n % ring] (ring 4, or 8 with
+                                             //   the projected guess)
+  Buf pguess, ppart, pstate;                 // projected guess: A v, then x0; dot partials; ProjState
   Buf w[4];                                  // checkpointed forward: T^n in w[n & 3]
-  int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive
+  int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive,
+                                             //   3 adaptive forward, projected adjoint
   int variant = 2;                           // 0 two reductions per iteration, 1 one, 2 one + register-resident
   bool resident = false;                     // the current plan uses nh::resident_step_kernel
   bool jac_tb = false;                       // the current plan uses nh::jacobi_step_kernel
@@ -604,7 +608,8 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
 
 // The previous states h1..h3 and the CG initial-guess policy (c->guess): 0
 // x0 = h1; 1 the quadratic extrapolation 3 h1 - 3 h2 + h3 (linear with two
-// states); 2 adaptive: the steps of a sweep are taken in periods of
+// states); 2 and 3 (3 projects the adjoint's guesses instead, see
+// proj_prepare) adaptive: the steps of a sweep are taken in periods of
 // kGuessPeriod; its first three steps probe orders 0, 1 and 2, and the others
 // use the order whose probe needed the fewest iterations (the kernel compares
 // the counts in gi, written by earlier launches). j is the step's position in
@@ -619,7 +624,7 @@ void set_guess(const nh_ctx* c, StepArgs<R>& S, const R* const (&h)[3], int j, c
   S.xprev3 = h[2];
   S.gi = nullptr;
   S.gp[0] = S.gp[1] = S.gp[2] = 0;
-  if (c->guess != 2) {
+  if (c->guess < 2) {
     S.gmode = c->guess == 0 ? 0 : 2;
     return;
   }
@@ -818,6 +823,38 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
   return status_to_code(c, any);
 }
 
+// The projected initial guess of adjoint step n - 1, once mu^n (in M[n % ring])
+// is solved: A mu^n, the new row of the window's Gram matrix and the
+// right-hand-side projections, the small solve, and x0 into c->pguess. gnext
+// is the top-plane source of step n - 1. Queued on the context's stream after
+// step n; no host synchronisation.
+template <typename R>
+nh_status proj_prepare(nh_ctx* c, int n, int N, R* const* M, const R* gnext, double dt) {
+  const Geom& g = c->geom;
+  nh::ProjWin<R> W{};
+  W.k = std::min(nh::kProjMax, N - n + 1);
+  for (int j = 0; j < W.k; ++j) {
+    W.slot[j] = (n + j) % nh::kProjRing;
+    W.w[j] = M[W.slot[j]];
+  }
+  R* y = (R*)c->pguess.p;
+  double* part = (double*)c->ppart.p;
+  nh::ProjState* st = (nh::ProjState*)c->pstate.p;
+  const nh::Coef<R> cf{(R)(2.0 * dt / (c->hx * c->hx)), (R)(2.0 * dt / (c->hy * c->hy)),
+                       (R)(2.0 * dt / (c->hz * c->hz)), (R)(dt * c->robin / c->hz), g.nz - 1};
+  const long long blocks = (g.ng + nh::kProjBlock - 1) / nh::kProjBlock;
+  hipLaunchKernelGGL(nh::proj_apply_kernel<R>, dim3((unsigned)blocks), dim3(nh::kProjBlock), 0, c->stream, g,
+                     (const R*)c->alpha.p, W.w[0], y, cf);
+  hipLaunchKernelGGL(nh::proj_dots_kernel<R>, dim3(nh::kProjDotBlocks), dim3(nh::kProjBlock), 0, c->stream, W,
+                     (const R*)y, gnext, g.ng, g.nxy, part);
+  hipLaunchKernelGGL(nh::proj_solve_kernel<R>, dim3(1), dim3(nh::kProjBlock), 0, c->stream, W,
+                     (const double*)part, nh::kProjDotBlocks, st);
+  hipLaunchKernelGGL(nh::proj_combine_kernel<R>, dim3((unsigned)blocks), dim3(nh::kProjBlock), 0, c->stream, W,
+                     (const nh::ProjState*)st, y, g.ng);
+  NH_HIP(c, hipGetLastError());
+  return NH_OK;
+}
+
 template <typename R>
 nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   auto t0 = std::chrono::steady_clock::now();
@@ -829,9 +866,20 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   const int N = c->saved_nsteps, k = c->ckpt_every;
   const double dt = c->saved_dt;
   const size_t vb = sizeof(R) * (size_t)g.ng;
-  for (Buf& b : c->mu) NH_TRY(ensure(c, b, vb));
-  R* const M[4] = {(R*)c->mu[0].p, (R*)c->mu[1].p, (R*)c->mu[2].p, (R*)c->mu[3].p};
-  auto mu_state = [&](int m) -> const R* { return m > N ? nullptr : M[m & 3]; };   // mu^{N+1} = 0
+  // guess mode 3 projects the adjoint solves' initial guesses (CG only)
+  const bool proj = c->guess == 3 && c->jacobi_k == 0;
+  const int ring = proj ? nh::kProjRing : 4;
+  R* M[nh::kProjRing] = {};
+  for (int i = 0; i < ring; ++i) {
+    NH_TRY(ensure(c, c->mu[i], vb));
+    M[i] = (R*)c->mu[i].p;
+  }
+  if (proj) {
+    NH_TRY(ensure(c, c->pguess, vb));
+    NH_TRY(ensure(c, c->ppart, sizeof(double) * nh::kProjVals * nh::kProjDotBlocks));
+    NH_TRY(ensure(c, c->pstate, sizeof(nh::ProjState)));
+  }
+  auto mu_state = [&](int m) -> const R* { return m > N ? nullptr : M[m % ring]; };   // mu^{N+1} = 0
   NH_TRY(fill<double>(c, G, g.ng, 0.0));
   NH_TRY(ensure_events(c));
 
@@ -848,11 +896,18 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
     StepArgs<R> S;
     base_args<R>(c, S, dt);
     S.mode = nh::kAdjoint;
-    S.x = M[n & 3];
+    S.x = M[n % ring];
     S.surf_out = dq ? dq + (size_t)(n - 1) * g.nxy : nullptr;   // dL/dq^n = dt mu^n on k = 0
     S.surf_scale = (R)dt;
     const R* const h[3] = {mu_state(n + 1), mu_state(n + 2), mu_state(n + 3)};
     set_guess<R>(c, S, h, N - n, step_out(c, 1, 0).iters, [N](int jj) { return N - jj; });
+    if (proj && n < N) {
+      // x0 = the projection that proj_prepare left in pguess; b still from mu^{n+1}
+      S.gmode = 3;
+      S.xprev2 = (const R*)c->pguess.p;
+      S.xprev3 = nullptr;
+      S.gi = nullptr;
+    }
     S.top_src = gsurf + (size_t)(n - 1) * g.nxy;
     S.top_scale = R(1);
     S.T_grad = Tn;
@@ -866,6 +921,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
       NH_TRY(collect_events(c, used, &tk));
       used = 0;
     }
+    if (proj && n > 1) NH_TRY(proj_prepare<R>(c, n, N, M, gsurf + (size_t)(n - 2) * g.nxy, dt));
     return NH_OK;
   };
 
@@ -899,7 +955,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
     }
   }
   NH_TRY(flush_steps(c));                   // queued steps precede the copy on the stream
-  if (dT0) NH_HIP(c, hipMemcpyAsync(dT0, M[1 & 3], vb, hipMemcpyDeviceToDevice, c->stream));   // mu^1
+  if (dT0) NH_HIP(c, hipMemcpyAsync(dT0, M[1 % ring], vb, hipMemcpyDeviceToDevice, c->stream));   // mu^1
   NH_TRY(collect_events(c, used, &tk));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   c->st.launches_adj = c->kernel_launches - kl0;
@@ -1056,6 +1112,7 @@ nh_status nh_set_grid(nh_ctx* c, int nx, int ny, int nz, double hx, double hy, d
   NH_TRY(release(c, c->p0));
   NH_TRY(release(c, c->p1));
   for (Buf& b : c->mu) NH_TRY(release(c, b));
+  NH_TRY(release(c, c->pguess));
   plan(c, c->occ_f32, nh::Cfg<float>::kBlock);
   return NH_OK;
 }
@@ -1194,7 +1251,7 @@ nh_status nh_get_step_iters(const nh_ctx* c, int sweep, int* iters) {
 
 nh_status nh_set_initial_guess(nh_ctx* c, int mode) {
   if (!c) return NH_EINVAL;
-  if (mode < 0 || mode > 2) return fail(c, NH_EINVAL, "initial guess mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 3) return fail(c, NH_EINVAL, "initial guess mode must be 0, 1, 2 or 3");
   drop_forward(c);
   c->guess = mode;
   return NH_OK;
@@ -1226,7 +1283,7 @@ void nh_destroy(nh_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
                  &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart,
-                 &c->jt[0], &c->jt[1]};
+                 &c->jt[0], &c->jt[1], &c->pguess, &c->ppart, &c->pstate};
   for (Buf* b : bufs) release(c, *b);
   for (Buf& b : c->mu) release(c, b);
   for (Buf& b : c->w) release(c, b);

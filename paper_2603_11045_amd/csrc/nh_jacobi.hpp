@@ -112,7 +112,7 @@ __device__ StepResult jacobi_tb_step(const StepArgs<float>& S, const StepVar<flo
     const int k = k0 + i;
     const float czm = i > 0 ? cz[i - 1] : czb;
     const float sk = k == nz - 1 ? S.sb : 0.f;
-    const float D = 1.f + ((((cxm[i] + cxp[i]) + (cym[i] + cyp[i])) + (czm + cz[i])) + sk);
+    const float D = diag_of<float>(cxm[i], cxp[i], cym[i], cyp[i], czm, cz[i], sk);
     rds[k * C + c] = (valid && k < nz) ? rcp<float>(D) : 1.f;
     float bk = 0.f;
     if (valid && k < nz) {

@@ -123,6 +123,18 @@ __device__ __forceinline__ void st_out(T* p, T v) { __hip_atomic_store(p, v, __A
 template <typename R>
 __device__ __forceinline__ R face(R s, R a, R b) { return s * (a * b) * rcp<R>(a + b); }
 
+// The diagonal of A: 1 + the six face terms (+ the sink term), summed in this
+// order by every kernel, so that kernels computing the same faces obtain the
+// same bits.
+template <typename R>
+__device__ __forceinline__ R diag_of(R c0, R c1, R c2, R c3, R c4, R c5) {
+  return R(1) + (((c0 + c1) + (c2 + c3)) + (c4 + c5));
+}
+template <typename R>
+__device__ __forceinline__ R diag_of(R c0, R c1, R c2, R c3, R c4, R c5, R sk) {
+  return R(1) + ((((c0 + c1) + (c2 + c3)) + (c4 + c5)) + sk);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -496,7 +508,7 @@ __device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, const Coef<R>
   s += c6 * (v - P.v[k][6]);
   s += sk * v;
   Av = v + s;
-  D = R(1) + ((((c1 + c2) + (c3 + c4)) + (c5 + c6)) + sk);
+  D = diag_of<R>(c1, c2, c3, c4, c5, c6, sk);
 }
 
 // ---------------------------------------------------------------------------
@@ -828,9 +840,12 @@ struct StepVar {
 // (order 2) of the states at the preceding time levels, limited by the states
 // there are. In mode -1 the order is the one whose probe step took the fewest
 // iterations (ties: the higher order); every workgroup reads the same counts,
-// written by earlier launches, so the choice is uniform over the team.
+// written by earlier launches, so the choice is uniform over the team. Mode 3
+// takes x0 from xprev2 as given (a projected guess); b still uses h1. Every
+// order is one form x0 = e1 h1 + e2 h2 (+ h3) of guess_coef.
 template <typename R>
 __device__ __forceinline__ int guess_order(const StepVar<R>& V) {
+  if (V.gmode == 3) return (V.xprev && V.xprev2) ? 3 : 0;
   int o = V.gmode;
   if (o < 0) {
     const int c0 = V.gi[V.gp[0]], c1 = V.gi[V.gp[1]], c2 = V.gi[V.gp[2]];
@@ -842,6 +857,14 @@ __device__ __forceinline__ int guess_order(const StepVar<R>& V) {
   if (!V.xprev || !V.xprev2) return 0;
   if (o == 2 && !V.xprev3) o = 1;
   return o;
+}
+
+// (e1, e2) of x0 = e1 h1 + e2 h2 (+ h3) for guess orders 1..3 (order 3: 0 h1 + h2
+// = h2 exactly, h3 unused).
+template <typename R>
+__device__ __forceinline__ void guess_coef(int order, R& e1, R& e2) {
+  e1 = order == 3 ? R(0) : (order == 2 ? R(3) : R(2));
+  e2 = order == 3 ? R(1) : (order == 2 ? R(-3) : R(-1));
 }
 
 template <typename R>
@@ -967,8 +990,7 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
     const int order = guess_order(V);
     init.h2 = order >= 1 ? V.xprev2 : nullptr;
     init.h3 = order == 2 ? V.xprev3 : nullptr;
-    init.e1 = R(order == 2 ? 3 : 2);
-    init.e2 = R(order == 2 ? -3 : -1);
+    guess_coef<R>(order, init.e1, init.e2);
     init.e3 = R(1);
     init.xw = (V.xprev == V.x) ? nullptr : V.x;
     sweep<R>(g, rank, S.team, S.xcd_order, init, sh);

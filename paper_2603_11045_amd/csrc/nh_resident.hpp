@@ -182,7 +182,7 @@ __device__ __forceinline__ Nb faces_at(const float* la, const ResPos& q, int z, 
   n.c[3] = face<float>(sy, a, pl[G::PW]);
   n.c[4] = face<float>(sz, a, pl[-G::PL]);
   n.c[5] = face<float>(sz, a, pl[G::PL]);
-  n.D = 1.f + (((n.c[0] + n.c[1]) + (n.c[2] + n.c[3])) + (n.c[4] + n.c[5]));
+  n.D = diag_of<float>(n.c[0], n.c[1], n.c[2], n.c[3], n.c[4], n.c[5]);
   return n;
 }
 
@@ -354,7 +354,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   const int order = guess_order(V);
   const float* h2 = order >= 1 ? V.xprev2 : nullptr;
   const float* h3 = order == 2 ? V.xprev3 : nullptr;
-  const float e1 = order == 2 ? 3.f : 2.f, e2 = order == 2 ? -3.f : -1.f;
+  float e1, e2;
+  guess_coef<float>(order, e1, e2);
   auto x0_at = [&](int i) -> float {
     if (!h2) return x0src[i];
     float v = e2 * h2[i];
@@ -428,19 +429,17 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     fill_ring<G>(g, q, lring, [&](int i) { return ld_dev(ub[0] + i); });
     __syncthreads();
     double acc1[1] = {0.0};
+    // w0 / D on the tile's faces is published as each plane is done (no
+    // global loads in the sweep, so the stores never hold up a wait)
     plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
                    [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                      const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                      const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                      wr[z] = w * rcp<float>(n.D);
                      acc1[0] += (double)ur[z] * (double)w;
+                     if (q.edge || z == 0 || z + 1 == q.tzn) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
                    });
     stamp();
-    if (q.own) {
-#pragma unroll
-      for (int z = 0; z < TZ; ++z)
-        if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
-    }
     ok &= team_sum_dev<1>(S, rank, red, acc1, rs);
     stamp();
     double a_cg = gam / acc1[0], b_cg = 0.0;
@@ -511,6 +510,13 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       __syncthreads();
       if (S.trace_detail) stamp();
       double acc[3] = {0.0, 0.0, 0.0};
+      // u, w/D, s/D on the tile's faces are published for the next iteration
+      // as each plane is done. The other bank, written here, was last read by
+      // the neighbours before the previous reduction, which this workgroup
+      // has passed.
+      float* uo_n = ub[cur ^ 1];
+      float* wo_n = wb[cur ^ 1];
+      float* so_n = sb[cur ^ 1];
       plane_sweep<G, 1>(g, q, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
                      [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                        const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
@@ -520,20 +526,14 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                        acc[0] += rd * ud;
                        acc[1] += (double)w * ud;
                        acc[2] += rd * rd;
+                       if (q.edge || z == 0 || z + 1 == q.tzn) {
+                         const int i = col_l + (T.z0 + z) * nxy_l;
+                         st_dev(uo_n + i, ur[z]);
+                         st_dev(wo_n + i, wr[z]);
+                         st_dev(so_n + i, sr[z]);
+                       }
                      });
       stamp();
-      // publish u, w/D, s/D on the tile's faces for the next iteration
-      if (q.own) {
-#pragma unroll
-        for (int z = 0; z < TZ; ++z) {
-          if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) {
-            const int i = col_l + (T.z0 + z) * nxy_l;
-            st_dev(ub[cur ^ 1] + i, ur[z]);
-            st_dev(wb[cur ^ 1] + i, wr[z]);
-            st_dev(sb[cur ^ 1] + i, sr[z]);
-          }
-        }
-      }
       if (S.trace_detail) stamp();
       ok &= team_sum_dev<3>(S, rank, red, acc, rs);
       stamp();

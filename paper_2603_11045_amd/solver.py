@@ -46,8 +46,10 @@ class Solver:
     selects the CG form: 0 two reductions per iteration, 1 one reduction
     (streaming kernel), 2 one reduction with the register-resident kernel
     where the grid fits on the chip, else as 1. ``initial_guess`` is the CG
-    starting point of each solve: ``"adaptive"`` (default), ``"extrapolate"``
-    from the last three states, or ``"previous"`` state alone. ``periodic``
+    starting point of each solve: ``"adaptive"`` (default), ``"projection"``
+    (adaptive in the forward sweep, projected onto the last adjoint solutions
+    in the adjoint), ``"extrapolate"`` from the last three states, or
+    ``"previous"`` state alone. ``periodic``
     wraps the lateral faces, ``robin`` is the back-face Robin coefficient and
     ``jacobi_k > 0`` replaces CG by the paper's fixed-K Jacobi sweeps (App. D.2).
     """
@@ -112,9 +114,11 @@ class Solver:
 
     def set_initial_guess(self, mode: str):
         """``"previous"`` (the last state), ``"extrapolate"`` (from the last
-        three states) or ``"adaptive"`` (per period of steps, whichever of the
-        two needed fewer iterations)."""
-        modes = {"previous": 0, "extrapolate": 1, "adaptive": 2}
+        three states), ``"adaptive"`` (per period of steps, whichever order
+        needed the fewest iterations) or ``"projection"`` (adaptive forward;
+        each adjoint solve starts from the A-norm projection of its
+        right-hand side onto the last adjoint solutions)."""
+        modes = {"previous": 0, "extrapolate": 1, "adaptive": 2, "projection": 3}
         if mode not in modes:
             raise ValueError(f"initial_guess must be one of {sorted(modes)}")
         _check(self.lib.nh_set_initial_guess(self._ctx, modes[mode]), self._ctx, "nh_set_initial_guess")

@@ -113,6 +113,26 @@ def test_small_forward_adjoint(case, precision, variant):
     assert es <= tol_s and eg <= tol_g
 
 
+@pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}x{c[2]}_t{c[5]}_z{c[6]}" for c in SMALL])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_small_projected_adjoint(case, precision):
+    """The projected initial guess of the adjoint solves (guess mode 3) on the
+    same cases, resident and streaming kernels, FP32 and FP64."""
+    nx, ny, nz, nsteps, seed, team, tz = case
+    say("small projected", case, precision)
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=seed, dt=2.5, precision=precision,
+                         rtol=1e-12 if precision == "f64" else 1e-7)
+    gs = wl.random_surface_weights(nsteps, ny, nx, seed=100 + seed)
+    src = orc.source_series(w.q_xy, w.q_t)
+    S_o, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt)
+    out = run_gpu(w, team=team, tile_z=tz, gs=gs, guess="projection")
+    tol_s, tol_g = (1e-9, 1e-8) if precision == "f64" else (1e-5, 1e-4)
+    es, eg = rel_l2(out["S"], S_o), rel_l2(out["G"], G_o)
+    say("  rel-L2 S", es, "G", eg, "adjoint iterations", out["stats_adj"]["adj_iters"])
+    assert es <= tol_s and eg <= tol_g
+
+
 def test_plain_fp64_16x16x8():
     """16x16x8, 50 steps, dt=2, FP64 at rtol 1e-12, MSE against the alpha=0.2 target."""
     w = wl.plain_fp64_16x16x8()
@@ -153,7 +173,7 @@ def test_initial_guess_modes(mixed_ref):
     fewer iterations on this smooth trajectory, the adaptive choice too."""
     w, ref = mixed_ref
     its = {}
-    for guess in ("previous", "extrapolate", "adaptive"):
+    for guess in ("previous", "extrapolate", "adaptive", "projection"):
         out = run_gpu(w, gs=ref["gs"].astype(np.float32), guess=guess)
         es, eg = rel_l2(out["S"], ref["S"]), rel_l2(out["G"], ref["G"])
         its[guess] = (out["stats_fwd"]["fwd_iters"], out["stats_adj"]["adj_iters"])
@@ -163,19 +183,23 @@ def test_initial_guess_modes(mixed_ref):
     assert its["extrapolate"][0] < its["previous"][0]
     assert its["extrapolate"][1] < its["previous"][1]
     assert sum(its["adaptive"]) < sum(its["previous"])
+    # the projection leaves the forward as it is and shortens the adjoint
+    assert its["projection"][0] == its["adaptive"][0]
+    assert its["projection"][1] < its["adaptive"][1]
 
 
 # ------------------------------------------------------------------ checkpointing, determinism
-@pytest.mark.parametrize("variant", [2, 1, 0])
-def test_checkpoint_recompute_is_bitwise(variant):
+@pytest.mark.parametrize("variant,guess", [(2, "adaptive"), (1, "adaptive"), (0, "adaptive"),
+                                           (2, "projection"), (1, "projection")])
+def test_checkpoint_recompute_is_bitwise(variant, guess):
     w = wl.small_problem(40, 24, 10, 20, seed=9, dt=3.0, precision="f32", rtol=1e-6)
     gs = wl.random_surface_weights(20, 24, 40, seed=19).astype(np.float32)
-    say("checkpoint full")
+    say("checkpoint full", variant, guess)
     team, tz = (0, 0) if variant == 2 else (4, 3)
-    full = run_gpu(w, gs=gs, team=team, tile_z=tz, variant=variant)
+    full = run_gpu(w, gs=gs, team=team, tile_z=tz, variant=variant, guess=guess)
     for k in (1, 2, 3, 7, 64):
         say("checkpoint k", k)
-        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=team, tile_z=tz, variant=variant)
+        ck = run_gpu(w, gs=gs, checkpoint_every=k, team=team, tile_z=tz, variant=variant, guess=guess)
         assert np.array_equal(ck["S"], full["S"])
         assert np.array_equal(ck["G"], full["G"])
         if k < 20:
@@ -202,6 +226,28 @@ def test_runs_are_bitwise_deterministic():
     a = run_gpu(w, gs=gs, team=6, tile_z=4)
     b = run_gpu(w, gs=gs, team=6, tile_z=4)
     assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["G"], b["G"])
+
+
+@pytest.mark.parametrize("guess", ["adaptive", "projection"])
+def test_resident_and_streaming_kernels_agree_bitwise(guess):
+    """Both FP32 kernels of the single-reduction iteration build the operator
+    from the same rounded face terms (the resident sweep carries each cell's
+    -z face from the plane below rather than recomputing it, and D is summed
+    without fused multiply-adds) and cast the FP64 scalars to FP32: on the same
+    problem, tiled differently, they give identical surface frames, gradient
+    and iteration counts."""
+    w = wl.small_problem(96, 24, 40, 6, seed=23, dt=4.0, precision="f32", rtol=1e-6)
+    gs = wl.random_surface_weights(6, 24, 96, seed=24).astype(np.float32)
+    res = run_gpu(w, gs=gs, guess=guess)
+    stm = run_gpu(w, gs=gs, tile_z=40, guess=guess)   # columns longer than a resident tile holds
+    assert res["stats_fwd"]["resident"] == 1 and stm["stats_fwd"]["resident"] == 0
+    say("resident vs streaming: S", rel_l2(res["S"], stm["S"]), "G", rel_l2(res["G"], stm["G"]),
+        "iters", res["stats_fwd"]["fwd_iters"], res["stats_adj"]["adj_iters"],
+        stm["stats_fwd"]["fwd_iters"], stm["stats_adj"]["adj_iters"])
+    assert np.array_equal(res["S"], stm["S"])
+    assert np.array_equal(res["G"], stm["G"])
+    assert res["stats_fwd"]["fwd_iters"] == stm["stats_fwd"]["fwd_iters"]
+    assert res["stats_adj"]["adj_iters"] == stm["stats_adj"]["adj_iters"]
 
 
 def test_get_state_conserves_heat():
