@@ -133,6 +133,27 @@ def test_small_projected_adjoint(case, precision):
     assert es <= tol_s and eg <= tol_g
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_projected_adjoint_degenerate_sources(precision):
+    """Projected guesses with degenerate windows: a zero adjoint source (every
+    window vector is zero and is dropped, the gradient is exactly zero) and a
+    source on one step only (the window then holds one decaying direction)."""
+    nx, ny, nz, nsteps = 40, 24, 10, 9
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=31, dt=2.0, precision=precision,
+                         rtol=1e-12 if precision == "f64" else 1e-7)
+    out = run_gpu(w, gs=np.zeros((nsteps, ny, nx)), guess="projection")
+    assert not np.any(out["G"])
+    gs = np.zeros((nsteps, ny, nx))
+    gs[nsteps - 1] = wl.random_surface_weights(1, ny, nx, seed=32)[0]
+    src = orc.source_series(w.q_xy, w.q_t)
+    S_o, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt)
+    out = run_gpu(w, gs=gs, guess="projection")
+    eg = rel_l2(out["G"], G_o)
+    say("one-step source: rel-L2 G", eg, "adjoint iterations", out["stats_adj"]["adj_iters"])
+    assert eg <= (1e-8 if precision == "f64" else 1e-4)
+
+
 def test_plain_fp64_16x16x8():
     """16x16x8, 50 steps, dt=2, FP64 at rtol 1e-12, MSE against the alpha=0.2 target."""
     w = wl.plain_fp64_16x16x8()
