@@ -43,6 +43,8 @@ def make_workload(name: str, nsteps: int = 0):
 
     if name == "stiff_256x256x64":
         w = wl.stiff_256x256x64(nsteps=nsteps or 1000)
+    elif name == "contrast_256x256x64":
+        w = wl.contrast_256x256x64(nsteps=nsteps or 100)
     elif name == "long_512x512x64":
         w = wl.long_512x512x64(nsteps=nsteps or 2000)
     elif name == "mixed_64x64x32":
@@ -197,6 +199,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip per-launch HIP event timing")
     ap.add_argument("--guess", default="adaptive", choices=["previous", "extrapolate", "adaptive", "projection"],
                     help="CG initial guess of the solves")
+    ap.add_argument("--cheb", type=int, default=1,
+                    help="preconditioner: 1 Jacobi, m >= 2 Chebyshev polynomial of degree m (CG variant 0)")
+    ap.add_argument("--variant", type=int, default=2, help="CG variant (0 two reductions, 1 one, 2 resident)")
     ap.add_argument("--ckpt-overhead", action="store_true",
                     help="with checkpointing on: also time the same passes with full trajectory storage "
                          "and report peak device memory of both")
@@ -247,7 +252,7 @@ def main():
     solver = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=w.rtol, max_iter=2000, checkpoint_every=ck,
                     precision=w.precision, device=0, team_blocks_max=args.team, tile_z=args.tile_z,
                     profile=not args.no_profile, periodic=w.periodic, robin=w.robin, jacobi_k=w.jacobi_k,
-                    initial_guess=args.guess)
+                    initial_guess=args.guess, cg_variant=args.variant, preconditioner_degree=args.cheb)
     alpha = torch.from_numpy(w.alpha).to(dev)
     q_xy = torch.from_numpy(w.q_xy).to(dev)
     # synthetic measurement: the surface of the target diffusivity
@@ -333,6 +338,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "nsteps": w.nsteps, "dt": w.dt,
                    "rtol": w.rtol, "checkpoint_every": ck, "initial_guess": args.guess,
+                   "cg_variant": solver.cg_variant, "preconditioner_degree": solver.preconditioner_degree,
                    "team_blocks": st["team_blocks"],
                    "tile": [st["tile_x"], st["tile_y"], st["tile_z"]]},
         "cg_iters_per_s": iters / elapsed,

@@ -75,7 +75,8 @@ typedef struct {
     double bytes_alg_adj;       /* same for the last adjoint, 10R + 16 per voxel and step for the state load
                                    and the FP64 gradient (recomputed forward steps counted as forward).
                                    With fixed-K Jacobi sweeps: 4R per voxel and sweep, plus 3R + 16 per
-                                   voxel and adjoint step for the gradient */
+                                   voxel and adjoint step for the gradient. A degree-m Chebyshev
+                                   preconditioner adds 5R (m - 1) per voxel and CG iteration */
     double t_fwd_s, t_adj_s;    /* host wall time of the last forward / adjoint call */
     double t_kernel_fwd_s;      /* summed HIP-event durations of the forward step kernels
                                    (only when profiling is enabled, else 0) */
@@ -200,12 +201,31 @@ nh_status nh_tv_f64(nh_ctx *ctx, const double *alpha, double eps, double weight,
  * profile != 0 times every step kernel with HIP events (nh_stats.t_kernel_*). */
 nh_status nh_set_launch(nh_ctx *ctx, int team_blocks_max, int tile_z, int profile);
 
-/* Form of the preconditioned CG iteration (both reach the same fixed point):
+/* Form of the preconditioned CG iteration (all reach the same fixed point):
  * 0 = the textbook form with two team reductions per iteration (p.Ap, then
- * r.z and |r|^2); 1 (default) = the single-reduction form of Chronopoulos and
- * Gear, which carries A u and A p as extra vectors so that r.z, u.Au and
- * |r|^2 are reduced together once per iteration. Frees the saved forward. */
+ * r.z and |r|^2); 1 = the single-reduction form of Chronopoulos and Gear,
+ * which carries A u and A p as extra vectors so that r.z, u.Au and |r|^2 are
+ * reduced together once per iteration; 2 (default) = form 1 with the whole CG
+ * state of a tile in registers where the grid fits on the device (FP32,
+ * zero-flux walls), else form 1. A variant other than 0 resets the
+ * preconditioner to Jacobi. Frees the saved forward. */
 nh_status nh_set_cg_variant(nh_ctx *ctx, int variant);
+
+/* Preconditioner of the CG solves (the paper leaves preconditioned solvers to
+ * future work, Sec. 6). degree 1 (default) = Jacobi, M = D = diag(A) (App.
+ * D.2). degree m in 2..16 = a Chebyshev polynomial in D^-1 A: z = y_m of m
+ * steps of the Chebyshev iteration for D^-1 A y = D^-1 r from y_0 = 0 over the
+ * interval [max(1/max D, hi/(2 m^2)), hi], hi = 2 - 1/max D. hi bounds the
+ * spectrum of D^-1 A from above for any diffusivity (A <= 2D - I), so the
+ * preconditioned eigenvalues lie in (0, 2), M is symmetric positive definite
+ * and CG converges to the same fixed point. It costs m - 1 more operator
+ * sweeps and team reductions per iteration and takes about m times fewer
+ * iterations. max D is reduced on the device once per forward (one host
+ * synchronisation).
+ * degree >= 2 selects CG variant 0 (the form with z = M^-1 r explicit); it is
+ * ignored by fixed-K Jacobi sweeps. EINVAL outside 1..16. Frees the saved
+ * forward. */
+nh_status nh_set_preconditioner(nh_ctx *ctx, int degree);
 
 /* CG initial guess of every solve. The states of the preceding time levels
  * are h1 = T^{n-1}, h2 = T^{n-2}, h3 = T^{n-3} (forward) or mu^{n+1},

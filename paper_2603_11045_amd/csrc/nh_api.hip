@@ -86,6 +86,9 @@ struct nh_ctx {
   int guess = 2;                             // initial guess: 0 previous state, 1 extrapolated, 2 adaptive,
                                              //   3 adaptive forward, projected adjoint
   int variant = 2;                           // 0 two reductions per iteration, 1 one, 2 one + register-resident
+  int cheb_m = 1;                            // preconditioner: 1 Jacobi, >= 2 Chebyshev polynomial (variant 0)
+  double cheb_dmax = 1.0;                    // max D of the saved forward's operator (Chebyshev interval)
+  Buf dmaxb;                                 // device result of nh::dmax_kernel
   bool resident = false;                     // the current plan uses nh::resident_step_kernel
   bool jac_tb = false;                       // the current plan uses nh::jacobi_step_kernel
   int jtx = 0, jty = 0;                      //   with this many interior tiles per axis
@@ -458,6 +461,31 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.err_flag = (int*)c->flag.p;
   S.timeout_ticks = (long long)(c->barrier_timeout_s * (double)c->wallclock_khz * 1000.0);
   S.trace = nullptr;
+  S.cheb_m = 1;
+  if (c->variant == 0 && c->cheb_m >= 2 && c->jacobi_k == 0) {
+    // Chebyshev interval [lo, hi] of D^-1 A: hi = 2 - 1 / max D bounds the
+    // spectrum from above (A <= 2 D - I); lo = max(1 / max D, hi / (2 m^2))
+    // targets the upper part, where a degree-m polynomial damps well (a lower
+    // bound of the spectrum, 1 / max D, is far below its bulk when the
+    // diffusivity contrast is high). Below lo the preconditioned eigenvalues
+    // 1 - P_m stay in (0, 1), so M stays symmetric positive definite.
+    const int m = c->cheb_m;
+    const double dmax = std::max(c->cheb_dmax, 1.0);
+    const double hi = 2.0 - 1.0 / dmax, lo = std::max(1.0 / dmax, hi / (2.0 * m * m));
+    const double theta = 0.5 * (hi + lo), delta = std::max(0.5 * (hi - lo), 1e-6 * theta);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int k = 1; k < m; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      S.cheb_c1[k] = (R)(rn * rho);
+      S.cheb_c2[k] = (R)(2.0 * rn / delta);
+      rho = rn;
+    }
+    S.cheb_m = m;
+    S.cheb_s = (R)(1.0 / theta);
+    S.cheb_y[0] = (R*)c->vw0.p;
+    S.cheb_y[1] = (R*)c->vw1.p;
+  }
 }
 
 // Per-step device outputs: [3][nsteps] iterations (forward, adjoint, recompute),
@@ -555,14 +583,19 @@ nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
 // state and writes the new x (4R per voxel and sweep); the last sweep writes
 // the state itself, and an adjoint step adds the gradient pass (T, mu,
 // alpha: 3R; the FP64 accumulator: 16 bytes).
-double step_bytes(const Geom& g, int R, int mode, int iters, bool jacobi) {
+double step_bytes(const Geom& g, int R, int mode, int iters, bool jacobi, int cheb_m = 1) {
   double per_voxel;
   if (jacobi)
     per_voxel = 4.0 * R * iters + (mode == nh::kForward ? 0.0 : 3.0 * R + 16.0);
   else
-    per_voxel = 12.0 * R * iters + (mode == nh::kForward ? 6.0 * R : 10.0 * R + 16.0);
+    // a Chebyshev preconditioner is applied once per iteration (after the
+    // set-up and after every iteration but the last): cheb_m - 1 sweeps, each
+    // reading y_k, y_{k-1}, z, alpha and writing y_{k+1}
+    per_voxel = (12.0 * R + 5.0 * R * (cheb_m - 1)) * iters + (mode == nh::kForward ? 6.0 * R : 10.0 * R + 16.0);
   return per_voxel * (double)g.ng;
 }
+
+int cheb_degree(const nh_ctx* c) { return (c->variant == 0 && c->jacobi_k == 0) ? c->cheb_m : 1; }
 
 template <typename R>
 nh_status ensure_common(nh_ctx* c, int nsteps) {
@@ -573,8 +606,13 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   if (c->variant == 0) {
     NH_TRY(ensure(c, c->p1, vb));
     NH_TRY(release(c, c->u1));
-    NH_TRY(release(c, c->vw0));
-    NH_TRY(release(c, c->vw1));
+    if (c->cheb_m >= 2 && c->jacobi_k == 0) {   // the Chebyshev preconditioner's y buffers
+      NH_TRY(ensure(c, c->vw0, vb));
+      NH_TRY(ensure(c, c->vw1, vb));
+    } else {
+      NH_TRY(release(c, c->vw0));
+      NH_TRY(release(c, c->vw1));
+    }
     NH_TRY(release(c, c->vs0));
     NH_TRY(release(c, c->vs1));
   } else {
@@ -743,6 +781,24 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
   if (v == NH_EINVAL) return fail(c, NH_EINVAL, "q_xy holds a non-finite value");
   NH_TRY(v);
   NH_HIP(c, hipMemcpyAsync(c->alpha.p, alpha, vb, hipMemcpyDeviceToDevice, c->stream));
+  if (c->variant == 0 && c->cheb_m >= 2 && c->jacobi_k == 0) {
+    // the largest diagonal entry of A, for the Chebyshev preconditioner's interval
+    NH_TRY(ensure(c, c->dmaxb, sizeof(unsigned long long)));
+    NH_HIP(c, hipMemsetAsync(c->dmaxb.p, 0, sizeof(unsigned long long), c->stream));
+    const nh::Coef<R> cf{(R)(2.0 * dt / (c->hx * c->hx)), (R)(2.0 * dt / (c->hy * c->hy)),
+                         (R)(2.0 * dt / (c->hz * c->hz)), (R)(dt * c->robin / c->hz), g.nz - 1};
+    const long long blocks = (g.ng + 255) / 256;
+    hipLaunchKernelGGL(nh::dmax_kernel<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, (const R*)c->alpha.p,
+                       cf, (unsigned long long*)c->dmaxb.p);
+    NH_HIP(c, hipGetLastError());
+    unsigned long long bits = 0;
+    NH_HIP(c, hipMemcpyAsync(&bits, c->dmaxb.p, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+    NH_HIP(c, hipStreamSynchronize(c->stream));
+    double d;
+    std::memcpy(&d, &bits, sizeof(d));
+    if (!(d >= 1.0) || !std::isfinite(d)) return fail(c, NH_EINVAL, "operator diagonal is not finite");
+    c->cheb_dmax = d;
+  }
   NH_TRY(ensure(c, c->qxy, sizeof(R) * (size_t)g.nxy));
   NH_HIP(c, hipMemcpyAsync(c->qxy.p, q_xy, sizeof(R) * (size_t)g.nxy, hipMemcpyDeviceToDevice, c->stream));
   const R* qsrc = (const R*)c->qxy.p;
@@ -811,7 +867,7 @@ nh_status do_forward(nh_ctx* c, const R* alpha, const R* q_xy, const double* q_t
     NH_HIP(c, hipStreamSynchronize(c->stream));
     double bytes = 0;
     for (int n = 1; n <= nsteps; ++n)
-      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1], c->jacobi_k > 0);
+      bytes += step_bytes(g, sizeof(R), nh::kForward, it[n - 1], c->jacobi_k > 0, cheb_degree(c));
     c->st.bytes_alg_fwd = bytes;
   }
   c->saved_prec = sizeof(R);
@@ -973,7 +1029,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   NH_HIP(c, hipMemcpyAsync(it.data(), step_out(c, 1, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
   NH_HIP(c, hipStreamSynchronize(c->stream));
   for (int n = 1; n <= N; ++n)
-    bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1], c->jacobi_k > 0);
+    bytes += step_bytes(g, sizeof(R), nh::kAdjoint, it[n - 1], c->jacobi_k > 0, cheb_degree(c));
   c->st.recompute_iters = 0;
   if (k > 0) {
     long long rsum = 0;
@@ -986,7 +1042,7 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
     NH_HIP(c, hipMemcpyAsync(ir.data(), step_out(c, 2, 0).iters, sizeof(int) * N, hipMemcpyDeviceToHost, c->stream));
     NH_HIP(c, hipStreamSynchronize(c->stream));
     for (int n = 1; n <= N; ++n)
-      bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1], c->jacobi_k > 0);
+      bytes += step_bytes(g, sizeof(R), nh::kForward, ir[n - 1], c->jacobi_k > 0, cheb_degree(c));
   }
   c->st.bytes_alg_adj = bytes;
   c->st.workspace_bytes = c->ws_bytes;
@@ -1233,6 +1289,17 @@ nh_status nh_set_cg_variant(nh_ctx* c, int variant) {
   if (variant < 0 || variant > 2) return fail(c, NH_EINVAL, "variant must be 0, 1 or 2");
   drop_forward(c);
   c->variant = variant;
+  if (variant != 0) c->cheb_m = 1;           // the polynomial preconditioner needs the two-reduction form
+  return NH_OK;
+}
+
+nh_status nh_set_preconditioner(nh_ctx* c, int degree) {
+  if (!c) return NH_EINVAL;
+  if (degree < 1 || degree > nh::kChebMax)
+    return fail(c, NH_EINVAL, "preconditioner degree must be between 1 and 16");
+  drop_forward(c);
+  c->cheb_m = degree;
+  if (degree >= 2) c->variant = 0;
   return NH_OK;
 }
 
@@ -1283,7 +1350,7 @@ void nh_destroy(nh_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
                  &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart,
-                 &c->jt[0], &c->jt[1], &c->pguess, &c->ppart, &c->pstate};
+                 &c->jt[0], &c->jt[1], &c->pguess, &c->ppart, &c->pstate, &c->dmaxb};
   for (Buf* b : bufs) release(c, *b);
   for (Buf& b : c->mu) release(c, b);
   for (Buf& b : c->w) release(c, b);

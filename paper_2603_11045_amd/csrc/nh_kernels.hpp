@@ -43,6 +43,7 @@ constexpr int kMaxBlock = 1024;
 constexpr int kMaxWaves = kMaxBlock / 64;
 constexpr int kMaxPlane = 1188;             // max (TX+2)*(TY+2) with TX*TY <= 1024: 66*18
 constexpr int kNumRed = 4;                  // doubles per workgroup partial slot
+constexpr int kChebMax = 16;                // highest degree of the Chebyshev preconditioner
 
 enum StepMode : int { kForward = 0, kAdjoint = 1 };
 enum StepStatus : int { kOk = 0, kNoConv = 1, kNonFinite = 2, kTimeout = 4 };
@@ -104,6 +105,15 @@ struct StepArgs {
   int trace_rank;                           // workgroup whose thread 0 writes the stamps
   int trace_cap;                            // capacity of trace in entries
   int trace_detail;                         // resident kernel: extra stamps inside an iteration
+  // Chebyshev polynomial preconditioner of the two-reduction form (cheb_m >= 2;
+  // 1 = plain Jacobi): y_1 = cheb_s z, y_{k+1} = y_k + cheb_c1[k] (y_k - y_{k-1})
+  // + cheb_c2[k] (z - A y_k / D) for k = 1..cheb_m-1, z = r / D; cheb_y the two
+  // buffers of y_2.. (y_j in cheb_y[j & 1])
+  int cheb_m;
+  R cheb_s;
+  R cheb_c1[kChebMax];
+  R cheb_c2[kChebMax];
+  R* cheb_y[2];
 };
 
 // ---------------------------------------------------------------------------
@@ -554,6 +564,42 @@ struct InitOp {
     acc[0] += bd * bd;
     acc[1] += rd * (double)zz;
     acc[2] += rd * rd;
+  }
+};
+
+// One step of the Chebyshev iteration for D^-1 A y = z from y_0 = 0 over an
+// interval [a, b] of the spectrum of D^-1 A (Y. Saad, Iterative
+// Methods for Sparse Linear Systems, 2nd ed., Alg. 12.1, in its three-term
+// form):  y_{k+1} = y_k + c1 (y_k - y_{k-1}) + c2 (z - A y_k / D).  y_1 = s z
+// and y_0 = 0 are not stored: yk == null stages s z, ykm1 == null gives 0
+// (k = 1) or s z (k = 2). The last step also accumulates r . y_m = (D z) . y_m.
+template <typename R>
+struct ChebOp {
+  static constexpr int NV = 1;
+  static constexpr int NO = 2;
+  using OT = R;
+  const R* alpha;
+  const R* z;
+  const R* yk;
+  const R* ykm1;
+  R* ynext;
+  R s, c1, c2;
+  int k;
+  int last;
+  Coef<R> cf;
+  double acc[1];
+  __device__ R load(int, long long i) const { return yk ? yk[i] : s * z[i]; }
+  __device__ R own(int j, long long i) const {
+    if (j == 0) return z[i];
+    return ykm1 ? ykm1[i] : (k == 1 ? R(0) : s * z[i]);
+  }
+  __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int kz) {
+    R Ay, D;
+    stencil<R, 1>(P, 0, cf, kz, Ay, D);
+    const R y = P.v[0][0];
+    const R yn = y + c1 * (y - o[1]) + c2 * (o[0] - Ay * rcp<R>(D));
+    st_out(ynext + i, yn);
+    if (last) acc[0] += ((double)D * (double)o[0]) * (double)yn;
   }
 };
 
@@ -1012,10 +1058,36 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
       R* pc = S.p0;
       R* pn = S.p1;
       double rz_old = 1.0;
+      // Chebyshev preconditioner: z_c = y_m from z = r / D in cheb_m - 1
+      // sweeps, each followed by a team reduction (the barrier before the
+      // next sweep reads halos); the last reduction returns r . z_c
+      const bool cheb = S.cheb_m >= 2;
+      const R* zc = cheb ? S.cheb_y[S.cheb_m & 1] : S.z;
+      auto cheb_apply = [&]() {
+        for (int k = 1; ok && k < S.cheb_m; ++k) {
+          ChebOp<R> C;
+          C.alpha = S.alpha; C.z = S.z;
+          C.yk = k == 1 ? nullptr : S.cheb_y[k & 1];
+          C.ykm1 = k <= 2 ? nullptr : S.cheb_y[(k - 1) & 1];
+          C.ynext = S.cheb_y[(k + 1) & 1];
+          C.s = S.cheb_s; C.c1 = S.cheb_c1[k]; C.c2 = S.cheb_c2[k];
+          C.k = k;
+          C.last = k + 1 == S.cheb_m;
+          C.cf = cf;
+          C.acc[0] = 0.0;
+          sweep<R>(g, rank, S.team, S.xcd_order, C, sh);
+          stamp();
+          double vc[1] = {C.acc[0]};
+          ok &= team_sum<R, 1>(S, rank, red, vc, sh);
+          stamp();
+          if (C.last) rz = vc[0];
+        }
+      };
+      if (cheb && rr > S.rtol2 * bb) cheb_apply();
       while (ok && rr > S.rtol2 * bb) {
         if (it >= S.max_iter) { status |= kNoConv; break; }
         DirOp<R> A;
-        A.alpha = S.alpha; A.z = S.z; A.pold = pc; A.pnew = pn;
+        A.alpha = S.alpha; A.z = zc; A.pold = pc; A.pnew = pn;
         A.first = (it == 0);
         A.beta = (R)(it == 0 ? 0.0 : rz / rz_old);
         A.cf = cf;
@@ -1043,6 +1115,7 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
         rr = v2[1];
         ++it;
         R* t = pc; pc = pn; pn = t;
+        if (cheb && rr > S.rtol2 * bb) cheb_apply();
       }
     } else if (ok && rr > S.rtol2 * bb) {
       // single-reduction form: w_0 = A u_0, then one fused sweep per iteration
@@ -1107,6 +1180,46 @@ __global__ void __launch_bounds__(Cfg<R>::kBlock, 1) apply_kernel(Geom g, const 
   op.alpha = alpha; op.xin = x; op.y = y;
   op.cf = cf;
   sweep<R>(g, blockIdx.x, gridDim.x, 0, op, sh);
+}
+
+// The largest diagonal entry D of A over the grid, as the bit pattern of a
+// positive double (ordered like the integers) in *out (cleared by the caller).
+// 1 / max D bounds the spectrum of D^-1 A from below (A >= I), 2 - 1 / max D
+// from above (A <= 2 D - I); the Chebyshev preconditioner's interval derives
+// from them.
+template <typename R>
+__global__ void __launch_bounds__(256) dmax_kernel(Geom g, const R* __restrict__ alpha, Coef<R> cf,
+                                                   unsigned long long* out) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double d = 0.0;
+  if (i < g.ng) {
+    const int kz = (int)(i / g.nxy);
+    const long long col = i - (long long)kz * g.nxy;
+    const int iy = (int)(col / g.nx), ix = (int)(col - (long long)iy * g.nx);
+    const R a = alpha[i];
+    const long long rowx = i - ix, base = i - col;
+    R c[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (ix > 0) c[0] = face<R>(cf.sx, a, alpha[i - 1]);
+    else if (g.periodic) c[0] = face<R>(cf.sx, a, alpha[rowx + g.nx - 1]);
+    if (ix + 1 < g.nx) c[1] = face<R>(cf.sx, a, alpha[i + 1]);
+    else if (g.periodic) c[1] = face<R>(cf.sx, a, alpha[rowx]);
+    if (iy > 0) c[2] = face<R>(cf.sy, a, alpha[i - g.nx]);
+    else if (g.periodic) c[2] = face<R>(cf.sy, a, alpha[base + (long long)(g.ny - 1) * g.nx + ix]);
+    if (iy + 1 < g.ny) c[3] = face<R>(cf.sy, a, alpha[i + g.nx]);
+    else if (g.periodic) c[3] = face<R>(cf.sy, a, alpha[base + ix]);
+    if (kz > 0) c[4] = face<R>(cf.sz, a, alpha[i - g.nxy]);
+    if (kz + 1 < g.nz) c[5] = face<R>(cf.sz, a, alpha[i + g.nxy]);
+    d = (double)diag_of<R>(c[0], c[1], c[2], c[3], c[4], c[5], kz == cf.zb ? cf.sb : R(0));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off, 64));
+  __shared__ double wmax[4];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // flag |= 1 if some alpha is not finite and positive

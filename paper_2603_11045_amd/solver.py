@@ -52,6 +52,8 @@ class Solver:
     ``"previous"`` state alone. ``periodic``
     wraps the lateral faces, ``robin`` is the back-face Robin coefficient and
     ``jacobi_k > 0`` replaces CG by the paper's fixed-K Jacobi sweeps (App. D.2).
+    ``preconditioner_degree`` m >= 2 replaces the Jacobi preconditioner by a
+    degree-m Chebyshev polynomial in D^-1 A (CG variant 0).
     """
 
     def __init__(self, nx: int, ny: int, nz: int, h: Sequence[float] = (1.0, 1.0, 1.0),
@@ -60,7 +62,7 @@ class Solver:
                  stream: Optional[torch.cuda.Stream] = None, team_blocks_max: int = 0,
                  tile_z: int = 0, profile: bool = False, cg_variant: int = 2,
                  initial_guess: str = "adaptive", periodic: bool = False, robin: float = 0.0,
-                 jacobi_k: int = 0):
+                 jacobi_k: int = 0, preconditioner_degree: int = 1):
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.lib = _lib.load()
@@ -78,6 +80,7 @@ class Solver:
         self.set_boundary(periodic, robin)
         self.set_jacobi_sweeps(jacobi_k)
         self.set_cg_variant(cg_variant)
+        self.set_preconditioner(preconditioner_degree)
         self.set_initial_guess(initial_guess)
         self.set_solver(rtol, max_iter, checkpoint_every)
         if team_blocks_max or tile_z or profile:
@@ -111,6 +114,16 @@ class Solver:
     def set_cg_variant(self, variant: int):
         _check(self.lib.nh_set_cg_variant(self._ctx, int(variant)), self._ctx, "nh_set_cg_variant")
         self.cg_variant = int(variant)
+        if self.cg_variant != 0:
+            self.preconditioner_degree = 1
+
+    def set_preconditioner(self, degree: int = 1):
+        """1: Jacobi (default); 2..16: a Chebyshev polynomial of that degree in
+        D^-1 A (selects CG variant 0)."""
+        _check(self.lib.nh_set_preconditioner(self._ctx, int(degree)), self._ctx, "nh_set_preconditioner")
+        self.preconditioner_degree = int(degree)
+        if self.preconditioner_degree >= 2:
+            self.cg_variant = 0
 
     def set_initial_guess(self, mode: str):
         """``"previous"`` (the last state), ``"extrapolate"`` (from the last

@@ -194,6 +194,23 @@ def stiff_256x256x64(seed: int = 3, nsteps: int = 1000, nx: int = 256, ny: int =
                     _cast(at, "f32"), rtol=1e-6)
 
 
+def contrast_256x256x64(seed: int = 3, nsteps: int = 100, nx: int = 256, ny: int = 256, nz: int = 64,
+                        n_incl: int = 16) -> Workload:
+    """The 256x256x64 background (lognormal sigma=0.3, median 1, dt=10, uniform
+    pulse on step 1, rtol 1e-6) with 16 highly conductive ellipsoids
+    alpha~U(100,1000): a contrast up to 1:1000, where Jacobi-PCG needs many
+    iterations. Target: inclusions redrawn with seed+1000."""
+    rng = np.random.default_rng(seed)
+    base = lognormal_field((nz, ny, nx), 0.3, rng)
+    a = base.copy()
+    add_ellipsoids(a, n_incl, 100.0, 1000.0, 2.0, 8.0, rng)
+    at = base.copy()
+    add_ellipsoids(at, n_incl, 100.0, 1000.0, 2.0, 8.0, np.random.default_rng(seed + 1000))
+    return Workload(f"contrast_{nx}x{ny}x{nz}", nx, ny, nz, 10.0, nsteps, _cast(a, "f32"),
+                    uniform_pulse(ny, nx).astype(np.float32), first_step_schedule(nsteps),
+                    _cast(at, "f32"), rtol=1e-6)
+
+
 def long_512x512x64(seed: int = 4, nsteps: int = 2000, checkpoint_every: int = 64,
                     nx: int = 512, ny: int = 512, nz: int = 64) -> Workload:
     """512x512x64, 2000 steps, dt=10, lognormal sigma=0.2 plus 64 boxes

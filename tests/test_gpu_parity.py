@@ -40,13 +40,13 @@ def to_dev(a, dtype):
 
 
 def run_gpu(w, rtol=None, checkpoint_every=0, team=0, tile_z=0, gs=None, precision=None, variant=2,
-            guess="adaptive"):
+            guess="adaptive", cheb=1):
     """Forward (and adjoint when gs is given) of workload w on the GPU."""
     prec = precision or w.precision
     dt_t = torch.float32 if prec == "f32" else torch.float64
     s = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=rtol or w.rtol, max_iter=5000,
                checkpoint_every=checkpoint_every, precision=prec, team_blocks_max=team, tile_z=tile_z,
-               cg_variant=variant, initial_guess=guess)
+               cg_variant=variant, initial_guess=guess, preconditioner_degree=cheb)
     S = s.forward(to_dev(w.alpha, dt_t), to_dev(w.q_xy, dt_t), w.q_t, w.dt, w.nsteps)
     out = dict(S=S.cpu().numpy().astype(np.float64), stats_fwd=s.stats(), solver=s)
     if gs is not None:
@@ -152,6 +152,72 @@ def test_projected_adjoint_degenerate_sources(precision):
     eg = rel_l2(out["G"], G_o)
     say("one-step source: rel-L2 G", eg, "adjoint iterations", out["stats_adj"]["adj_iters"])
     assert eg <= (1e-8 if precision == "f64" else 1e-4)
+
+
+CHEB_CASES = [SMALL[1], SMALL[2], SMALL[5], SMALL[7], SMALL[9]]
+
+
+@pytest.mark.parametrize("case", CHEB_CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}_t{c[5]}_z{c[6]}" for c in CHEB_CASES])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("degree", [2, 4, 7])
+def test_chebyshev_preconditioner_matches_oracle(case, precision, degree):
+    """CG with the Chebyshev polynomial preconditioner reaches the oracle's
+    fixed point (same tolerances as Jacobi-PCG)."""
+    nx, ny, nz, nsteps, seed, team, tz = case
+    say("chebyshev", degree, case, precision)
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=seed, dt=2.5, precision=precision,
+                         rtol=1e-12 if precision == "f64" else 1e-7)
+    gs = wl.random_surface_weights(nsteps, ny, nx, seed=100 + seed)
+    src = orc.source_series(w.q_xy, w.q_t)
+    S_o, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt)
+    out = run_gpu(w, team=team, tile_z=tz, gs=gs, variant=0, cheb=degree)
+    assert out["solver"].cg_variant == 0 and out["solver"].preconditioner_degree == degree
+    tol_s, tol_g = (1e-9, 1e-8) if precision == "f64" else (1e-5, 1e-4)
+    es, eg = rel_l2(out["S"], S_o), rel_l2(out["G"], G_o)
+    say("  rel-L2 S", es, "G", eg, "iterations", out["stats_fwd"]["fwd_iters"], out["stats_adj"]["adj_iters"])
+    assert es <= tol_s and eg <= tol_g
+
+
+def test_chebyshev_preconditioner_cuts_iterations_at_high_contrast():
+    """A 1:1000 inclusion: the degree-4 polynomial needs well under half the
+    Jacobi-PCG iterations, and its result agrees with the oracle."""
+    nx, ny, nz, nsteps = 48, 40, 16, 6
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=41, dt=4.0, precision="f64", rtol=1e-12)
+    w.alpha[4:12, 10:30, 12:36] *= 1000.0
+    gs = wl.random_surface_weights(nsteps, ny, nx, seed=42)
+    src = orc.source_series(w.q_xy, w.q_t)
+    S_o, T_o, _ = orc.forward(w.alpha, src, w.dt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt)
+    its = {}
+    for degree in (1, 4):
+        out = run_gpu(w, gs=gs, variant=0, cheb=degree)
+        its[degree] = out["stats_fwd"]["fwd_iters"] + out["stats_adj"]["adj_iters"]
+        es, eg = rel_l2(out["S"], S_o), rel_l2(out["G"], G_o)
+        say("  degree", degree, "iterations", its[degree], "rel-L2 S", es, "G", eg)
+        assert es <= 1e-6 and eg <= 1e-5
+    assert its[4] < 0.5 * its[1]
+
+
+@pytest.mark.parametrize("degree", [3, 6])
+def test_chebyshev_checkpointing_is_bitwise(degree):
+    w = wl.small_problem(40, 24, 10, 12, seed=9, dt=3.0, precision="f32", rtol=1e-6)
+    gs = wl.random_surface_weights(12, 24, 40, seed=19).astype(np.float32)
+    full = run_gpu(w, gs=gs, variant=0, cheb=degree)
+    ck = run_gpu(w, gs=gs, checkpoint_every=5, variant=0, cheb=degree)
+    assert np.array_equal(ck["S"], full["S"]) and np.array_equal(ck["G"], full["G"])
+
+
+def test_preconditioner_settings():
+    s = Solver(8, 8, 4)
+    assert s.cg_variant == 2 and s.preconditioner_degree == 1
+    s.set_preconditioner(5)
+    assert s.cg_variant == 0
+    s.set_cg_variant(1)
+    assert s.preconditioner_degree == 1
+    for bad in (0, 17):
+        with pytest.raises(Exception):
+            s.set_preconditioner(bad)
 
 
 def test_plain_fp64_16x16x8():
