@@ -310,8 +310,10 @@ def main():
         alg_per_launch = (bytes_f + bytes_a) / max(launches, 1)
         tr_path = os.path.join(ROOT, "profiles", f"traffic_{kname.split('::')[1].split('<')[0]}_{w.name}.json")
         tr = profiling.load_traffic(tr_path, kname)
+        m = solver.preconditioner_degree
+        it_bytes = "48" if m < 2 else f"{48 + 20 * (m - 1)} (Chebyshev degree {m})"
         model = ("16 B/voxel/Jacobi sweep + 28 (adj) B/voxel/step" if w.jacobi_k
-                 else "48 B/voxel/CG iteration + 24 (fwd) or 52 (adj) B/voxel/step")
+                 else f"{it_bytes} B/voxel/CG iteration + 24 (fwd) or 52 (adj) B/voxel/step")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr["traffic_bytes_per_launch"] if tr else None,
