@@ -103,6 +103,30 @@ def test_closures_forward_adjoint_match_oracle(case, periodic, robin, precision)
     assert eg <= tol_g
 
 
+@pytest.mark.parametrize("case", CASES[1:4], ids=[f"{c[0]}x{c[1]}x{c[2]}" for c in CASES[1:4]])
+@pytest.mark.parametrize("periodic,robin", CLOSURES)
+def test_closures_chebyshev_preconditioner_matches_oracle(case, periodic, robin):
+    """The Chebyshev preconditioner with the paper's closures: its interval
+    (from the largest diagonal, sink included) still bounds the spectrum, and
+    the solves reach the oracle's fixed point (FP64)."""
+    nx, ny, nz, nsteps, seed, team, tz = case
+    say("closure chebyshev", case, "periodic", periodic, "robin", robin)
+    h = (0.8, 1.0, 0.5)
+    w = wl.small_problem(nx, ny, nz, nsteps, seed=seed, dt=1.5, precision="f64", rtol=1e-12)
+    gs = wl.random_surface_weights(nsteps, ny, nx, seed=200 + seed)
+    src = orc.source_series(w.q_xy, w.q_t)
+    opt = dict(h=h, periodic=periodic, robin=robin)
+    S_o, T_o, _ = orc.forward(w.alpha, src, w.dt, **opt)
+    G_o, _, _, _ = orc.adjoint(w.alpha, T_o, gs, w.dt, **opt)
+    s = Solver(nx, ny, nz, h=h, rtol=w.rtol, max_iter=5000, precision="f64", team_blocks_max=team,
+               tile_z=tz, periodic=periodic, robin=robin, preconditioner_degree=5)
+    S = s.forward(dev(w.alpha, torch.float64), dev(w.q_xy, torch.float64), w.q_t, w.dt, nsteps).cpu().numpy()
+    G = s.adjoint(dev(gs, torch.float64)).cpu().numpy()
+    es, eg = rel_l2(S, S_o), rel_l2(G, G_o)
+    say("  S", es, "G", eg, "iterations", s.stats()["adj_iters"])
+    assert es <= 1e-9 and eg <= 1e-8
+
+
 # ------------------------------------------------------------------ fixed-K Jacobi
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("layered,robin", [(False, 0.0), (True, 0.0), (False, 0.5)])
