@@ -159,7 +159,7 @@ CHEB_CASES = [SMALL[1], SMALL[2], SMALL[5], SMALL[7], SMALL[9]]
 
 @pytest.mark.parametrize("case", CHEB_CASES, ids=[f"{c[0]}x{c[1]}x{c[2]}_t{c[5]}_z{c[6]}" for c in CHEB_CASES])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("degree", [2, 4, 7])
+@pytest.mark.parametrize("degree", [2, 4, 7, 16])
 def test_chebyshev_preconditioner_matches_oracle(case, precision, degree):
     """CG with the Chebyshev polynomial preconditioner reaches the oracle's
     fixed point (same tolerances as Jacobi-PCG)."""
