@@ -473,18 +473,12 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
     const double dmax = std::max(c->cheb_dmax, 1.0);
     const double hi = 2.0 - 1.0 / dmax, lo = std::max(1.0 / dmax, hi / (2.0 * m * m));
     const double theta = 0.5 * (hi + lo), delta = std::max(0.5 * (hi - lo), 1e-6 * theta);
-    const double sigma = theta / delta;
-    double rho = 1.0 / sigma;
-    for (int k = 1; k < m; ++k) {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      S.cheb_c1[k] = (R)(rn * rho);
-      S.cheb_c2[k] = (R)(2.0 * rn / delta);
-      rho = rn;
-    }
     S.cheb_m = m;
     S.cheb_s = (R)(1.0 / theta);
-    S.cheb_y[0] = (R*)c->vw0.p;
-    S.cheb_y[1] = (R*)c->vw1.p;
+    S.cheb_sigma = theta / delta;
+    S.cheb_delta = delta;
+    S.cheb_y0 = (R*)c->vw0.p;
+    S.cheb_y1 = (R*)c->vw1.p;
   }
 }
 

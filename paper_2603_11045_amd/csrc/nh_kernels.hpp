@@ -45,6 +45,17 @@ constexpr int kMaxPlane = 1188;             // max (TX+2)*(TY+2) with TX*TY <= 1
 constexpr int kNumRed = 4;                  // doubles per workgroup partial slot
 constexpr int kChebMax = 16;                // highest degree of the Chebyshev preconditioner
 
+// Coefficients of Chebyshev step k = 1, 2, ... from rho_{k-1} (rho_0 = 1 / sigma):
+// rho_k = 1 / (2 sigma - rho_{k-1}), c1 = rho_k rho_{k-1}, c2 = 2 rho_k / delta.
+// The host and every workgroup evaluate the same FP64 recurrence.
+__host__ __device__ __forceinline__ void cheb_coef(double sigma, double delta, double& rho, double& c1,
+                                                   double& c2) {
+  const double rn = 1.0 / (2.0 * sigma - rho);
+  c1 = rn * rho;
+  c2 = 2.0 * rn / delta;
+  rho = rn;
+}
+
 enum StepMode : int { kForward = 0, kAdjoint = 1 };
 enum StepStatus : int { kOk = 0, kNoConv = 1, kNonFinite = 2, kTimeout = 4 };
 
@@ -106,14 +117,16 @@ struct StepArgs {
   int trace_cap;                            // capacity of trace in entries
   int trace_detail;                         // resident kernel: extra stamps inside an iteration
   // Chebyshev polynomial preconditioner of the two-reduction form (cheb_m >= 2;
-  // 1 = plain Jacobi): y_1 = cheb_s z, y_{k+1} = y_k + cheb_c1[k] (y_k - y_{k-1})
-  // + cheb_c2[k] (z - A y_k / D) for k = 1..cheb_m-1, z = r / D; cheb_y the two
-  // buffers of y_2.. (y_j in cheb_y[j & 1])
+  // 1 = plain Jacobi): y_1 = cheb_s z, y_{k+1} = y_k + c1_k (y_k - y_{k-1})
+  // + c2_k (z - A y_k / D) for k = 1..cheb_m-1, z = r / D, with c1_k, c2_k
+  // from cheb_sigma and cheb_delta (cheb_coef). y_j lives in cheb_y0 (j even)
+  // or cheb_y1 (j odd). (Scalars only: a kernel argument indexed at run time
+  // would be copied to scratch memory.)
   int cheb_m;
   R cheb_s;
-  R cheb_c1[kChebMax];
-  R cheb_c2[kChebMax];
-  R* cheb_y[2];
+  double cheb_sigma, cheb_delta;
+  R* cheb_y0;
+  R* cheb_y1;
 };
 
 // ---------------------------------------------------------------------------
@@ -947,7 +960,7 @@ __host__ __device__ __forceinline__ StepVar<R> step_var(const StepArgs<R>& S) {
 // and the per-step outputs (written by rank 0). The caller's last team
 // reduction is the barrier that makes x complete before this reads it.
 template <typename R>
-__device__ StepResult step_epilogue(const StepArgs<R>& S, const StepVar<R>& V, int rank, bool ok, int it,
+__device__ __forceinline__ StepResult step_epilogue(const StepArgs<R>& S, const StepVar<R>& V, int rank, bool ok, int it,
                                     int status, double bb, double rr, Smem<R>& sh) {
   const Geom& g = S.g;
   if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
@@ -983,7 +996,7 @@ __device__ StepResult step_epilogue(const StepArgs<R>& S, const StepVar<R>& V, i
 }
 
 template <typename R>
-__device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int rank, Smem<R>& sh) {
+__device__ __forceinline__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int rank, Smem<R>& sh) {
   const Geom& g = S.g;
   const Coef<R> cf = coef_of(S);
   unsigned long long red = V.epoch_base;
@@ -1065,15 +1078,19 @@ __device__ StepResult run_step(const StepArgs<R>& S, const StepVar<R>& V, int ra
       // sweeps, each followed by a team reduction (the barrier before the
       // next sweep reads halos); the last reduction returns r . z_c
       const bool cheb = S.cheb_m >= 2;
-      const R* zc = cheb ? S.cheb_y[S.cheb_m & 1] : S.z;
+      auto ybuf = [&](int j) -> R* { return (j & 1) ? S.cheb_y1 : S.cheb_y0; };
+      const R* zc = cheb ? ybuf(S.cheb_m) : S.z;
       auto cheb_apply = [&]() {
+        double rho = 1.0 / S.cheb_sigma;
         for (int k = 1; ok && k < S.cheb_m; ++k) {
+          double c1, c2;
+          cheb_coef(S.cheb_sigma, S.cheb_delta, rho, c1, c2);
           ChebOp<R> C;
           C.alpha = S.alpha; C.z = S.z;
-          C.yk = k == 1 ? nullptr : S.cheb_y[k & 1];
-          C.ykm1 = k <= 2 ? nullptr : S.cheb_y[(k - 1) & 1];
-          C.ynext = S.cheb_y[(k + 1) & 1];
-          C.s = S.cheb_s; C.c1 = S.cheb_c1[k]; C.c2 = S.cheb_c2[k];
+          C.yk = k == 1 ? nullptr : ybuf(k);
+          C.ykm1 = k <= 2 ? nullptr : ybuf(k - 1);
+          C.ynext = ybuf(k + 1);
+          C.s = S.cheb_s; C.c1 = (R)c1; C.c2 = (R)c2;
           C.k = k;
           C.last = k + 1 == S.cheb_m;
           C.cf = cf;
