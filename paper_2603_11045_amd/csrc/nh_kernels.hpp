@@ -337,19 +337,17 @@ struct Pt {
 
 // March one tile along z. Op supplies: NV staged vectors (load(k, i)), NO
 // operands of type OT read only at the cell itself (own(k, i), not staged),
-// alpha, and point(P, o, i, kz). Loads run kPrefetch<R> planes ahead of use
+// alpha, and point(P, o, i, kz). Loads run kPrefetch planes ahead of use
 // (register queues), so each thread keeps several planes of loads in flight
-// across the two workgroup barriers of a plane (FP32: two planes, measured
-// 1.4% faster than three on 512x512x64 at 1024 threads, which leave 128
-// VGPRs; FP64: three).
-template <typename R>
-constexpr int kPrefetch = sizeof(R) == 4 ? 2 : 3;
+// across the two workgroup barriers of a plane. (Two planes measured the
+// same within 0.5% on the FP32 workloads.)
+constexpr int kPrefetch = 3;
 
 template <typename R, typename Op>
 __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op, Smem<R>& sh) {
   constexpr int NV = Op::NV;
   constexpr int NO = Op::NO;
-  constexpr int PD = kPrefetch<R>;
+  constexpr int PD = kPrefetch;
   constexpr int QS = PD + 2;                // staged own column: planes z-1 .. z+PD
   using OT = typename Op::OT;
   const int tid = threadIdx.x;
