@@ -1,0 +1,65 @@
+"""Resource use of the hot kernels, read from the compiler's gfx950 output (no
+GPU needed): the per-step kernels must keep their whole step inlined, with no
+private (scratch) segment and no register spills. A function call or a
+scratch copy of the step arguments once slowed the streaming kernel by a third
+while every numerical test still passed."""
+import os
+import re
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_2603_11045_amd import build  # noqa: E402
+
+HOT = {
+    "_ZN2nh20resident_step_kernelILi64EEEvNS_8StepArgsIfEE": "resident_step_kernel<64>",
+    "_ZN2nh11step_kernelIfEEvNS_8StepArgsIT_EE": "step_kernel<float>",
+    "_ZN2nh11step_kernelIdEEvNS_8StepArgsIT_EE": "step_kernel<double>",
+}
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not shutil.which(hipcc):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("asm") / "nh_api.s"
+    flags = [f for f in build.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    cmd = [hipcc, *flags, f"-I{build.INCLUDE}", f"-I{build.CSRC}", "--cuda-device-only", "-S", "-o", str(out),
+           os.path.join(build.CSRC, "nh_api.hip")]
+    res = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, res.stderr[-2000:]
+    return out.read_text()
+
+
+def kernel_meta(text):
+    meta = text[text.index("amdhsa.kernels:"):]
+    out = {}
+    for blk in re.split(r"\n  - ", meta)[1:]:
+        name = re.search(r"\.name:\s+(\S+)", blk)
+        if not name:
+            continue
+        out[name.group(1)] = {
+            "private": int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", blk).group(1)),
+            "vgpr_spill": int(re.search(r"\.vgpr_spill_count:\s+(\d+)", blk).group(1)),
+        }
+    return out
+
+
+def kernel_body(text, sym):
+    start = text.index(f"\n{sym}:")
+    return text[start:text.index("s_endpgm", start)]
+
+
+@pytest.mark.parametrize("sym", list(HOT), ids=list(HOT.values()))
+def test_step_kernels_are_inlined_without_scratch(asm, sym):
+    meta = kernel_meta(asm)
+    assert sym in meta, f"{HOT[sym]} not found in the device code"
+    assert meta[sym]["private"] == 0, f"{HOT[sym]} uses {meta[sym]['private']} bytes of scratch"
+    assert meta[sym]["vgpr_spill"] == 0
+    assert "s_swappc" not in kernel_body(asm, sym), f"{HOT[sym]} calls a function"
