@@ -351,6 +351,10 @@ def main():
         "roofline": roof,
         "peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
     }
+    props = torch.cuda.get_device_properties(dev)
+    rec["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                     "compute_units": props.multi_processor_count, "memory_gb": props.total_memory / 1e9,
+                     "hbm_peak_gbs": HBM_PEAK_GBS}
     rec["memory"] = {"library_peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
                      "torch_peak_allocated_gb": torch.cuda.max_memory_allocated(dev) / 1e9,
                      "device_used_gb": (torch.cuda.mem_get_info(dev)[1] - torch.cuda.mem_get_info(dev)[0]) / 1e9}
