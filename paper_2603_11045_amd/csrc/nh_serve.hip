@@ -338,7 +338,7 @@ struct nh_server {
   int num_cu = 0, max_blocks = 0;
   double budget = 0;
   int resident = 1;        // 1: nh::batch_resident_kernel, 0: nh::batch_run_kernel
-  int slice_iters = 128;
+  int slice_iters = 512;
   int backfill = 1;        // 1: EASY backfilling, 0: strict arrival order
   std::map<long long, std::pair<double, long long>> shape_time;   // grid -> (seconds, steps) measured
   size_t used_bytes = 0;
