@@ -17,9 +17,11 @@ bytes per launch when a record taken on the same kernel sources is stored
 under profiles/. ``paper_fixed_k`` times the paper's own solver set-up
 (64x64x16, periodic lateral faces, K = 50 Jacobi sweeps; forward and
 backward apart, as in its Table 4); ``invert`` the time per iteration of
-the two inversion drivers on its training set-up (Table 9). ``serve`` runs the first jobs of the
+the two inversion drivers on its training set-up (Table 9). ``serve`` runs the 200 jobs of the
 Poisson serving stream through the batching server and, as the baseline,
-one by one through the single-problem path.
+one by one through the single-problem path. ``long`` times the 512x512x64
+long-horizon line (2000 steps) with a checkpoint every 64 steps against
+full trajectory storage, with the peak device workspace of each.
 """
 from __future__ import annotations
 
@@ -164,8 +166,10 @@ def invert_iterations(dev, iters: int):
 
 
 def serve_section(n_jobs: int) -> dict:
-    """The first n_jobs of the Poisson serving stream through the batching
-    server, and one by one through the single-problem path as the baseline."""
+    """The first n_jobs of the Poisson serving stream (all 200 by default)
+    through the batching server, and one by one through the single-problem
+    path as the baseline; also the largest relative difference between a
+    job's loss in the two runs."""
     from paper_2603_11045_amd import serve
 
     print(f"[bench] serving: first {n_jobs} jobs of the Poisson stream (20 jobs/s, seed 5)",
@@ -179,7 +183,53 @@ def serve_section(n_jobs: int) -> dict:
         "sequential": {"p50_ms": q["p50_ms"], "p99_ms": q["p99_ms"], "jobs_per_s": q["jobs_per_s"]},
         "speedup": {"throughput": sv["speedup_throughput"], "p50": sv["speedup_p50"],
                     "p99": sv["speedup_p99"]},
+        "max_rel_loss_diff_vs_sequential": sv["max_rel_loss_diff_vs_sequential"],
     }
+
+
+def long_section(dev, nsteps: int, k: int) -> dict:
+    """The long-horizon memory path: 512x512x64 (four times what the chip's
+    registers hold, so the streaming kernel runs it), `nsteps` steps, one
+    forward + adjoint pass with a checkpoint every k steps (segments
+    recomputed in the adjoint) and one with every state stored: time and the
+    library's peak device workspace of each."""
+    import torch
+
+    from paper_2603_11045_amd import workloads as wl
+    from paper_2603_11045_amd.solver import Solver
+
+    w = wl.long_512x512x64(nsteps=nsteps, checkpoint_every=k)
+    alpha = torch.from_numpy(w.alpha).to(dev)
+    q_xy = torch.from_numpy(w.q_xy).to(dev)
+    out = {"workload": w.name, "grid": [w.nx, w.ny, w.nz], "nsteps": nsteps, "dt": w.dt, "rtol": w.rtol,
+           "checkpoint_every": k}
+    target = None
+    for key, ck in (("checkpointed", k), ("full_storage", 0)):
+        s = Solver(w.nx, w.ny, w.nz, h=w.h, rtol=w.rtol, max_iter=2000, checkpoint_every=ck, device=0)
+        if target is None:
+            target = s.forward(torch.from_numpy(w.alpha_target).to(dev), q_xy, w.q_t, w.dt, nsteps).clone()
+        m = target.numel()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = s.forward(alpha, q_xy, w.q_t, w.dt, nsteps)
+        s.adjoint((2.0 / m) * (S - target))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = s.stats()
+        out[key] = {"s_per_pass": el, "voxel_steps_per_s": w.ng * nsteps / el,
+                    "peak_workspace_gb": st["peak_workspace_bytes"] / 1e9,
+                    "cg_iters": {"fwd": st["fwd_iters"], "adj": st["adj_iters"],
+                                 "recompute": st["recompute_iters"]},
+                    "kernel": "nh::resident_step_kernel<64>" if st["resident"] else "nh::step_kernel<float>"}
+        print(f"[bench] long {key}: {el:.2f} s per pass, peak workspace "
+              f"{st['peak_workspace_bytes'] / 1e9:.1f} GB", file=sys.stderr, flush=True)
+        s.close()
+        del S
+        torch.cuda.empty_cache()
+    c, f = out["checkpointed"], out["full_storage"]
+    out["time_overhead"] = c["s_per_pass"] / f["s_per_pass"] - 1.0
+    out["memory_saving"] = 1.0 - c["peak_workspace_gb"] / f["peak_workspace_gb"]
+    return out
 
 
 def main():
@@ -205,8 +255,10 @@ def main():
     ap.add_argument("--ckpt-overhead", action="store_true",
                     help="with checkpointing on: also time the same passes with full trajectory storage "
                          "and report peak device memory of both")
-    ap.add_argument("--serve-jobs", type=int, default=40,
+    ap.add_argument("--serve-jobs", type=int, default=200,
                     help="jobs of the Poisson serving stream to serve (0 = skip the serving run)")
+    ap.add_argument("--long-steps", type=int, default=2000,
+                    help="steps of the 512x512x64 long-horizon line, checkpointed vs full storage (0 = skip)")
     ap.add_argument("--paper-reps", type=int, default=5,
                     help="repetitions of the paper-shaped fixed-K timing (0 = skip)")
     ap.add_argument("--invert-iters", type=int, default=20,
@@ -325,6 +377,10 @@ def main():
         if tr:
             roof["traffic_over_alg"] = round(tr["traffic_bytes_per_launch"] / alg_per_launch, 4)
             roof["traffic_source"] = os.path.relpath(tr_path, ROOT)
+            # the HBM bandwidth the counters show, beside the algorithmic figure
+            counter_gbs = tr["traffic_bytes_per_launch"] / ((tk_f + tk_a) / max(launches, 1)) / 1e9
+            roof["counter_achieved"] = round(counter_gbs, 1)
+            roof["counter_frac"] = round(counter_gbs / HBM_PEAK_GBS, 4)
     rec = {
         "metric": "fwd+adjoint voxel-steps/s",
         "value": value,
@@ -384,7 +440,22 @@ def main():
             "memory_saving": 1.0 - st["peak_workspace_bytes"] / sf["peak_workspace_bytes"],
         }
         full.close()
+    # the GPU on the oracle's sample (the first steps of the same workload,
+    # which need more CG iterations than the average step), for a like-for-like ratio
+    gpu_sample = None
+    if not args.no_cpu_baseline and not (args.ckpt_overhead and ck > 0):
+        ns = min(args.cpu_sample_steps, w.nsteps)
+        solver.forward(alpha, q_xy, w.q_t[:ns], w.dt, ns)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S = solver.forward(alpha, q_xy, w.q_t[:ns], w.dt, ns)
+        solver.adjoint((2.0 / target[:ns].numel()) * (S - target[:ns]))
+        torch.cuda.synchronize()
+        gpu_sample = float(w.ng) * ns / (time.perf_counter() - t1)
+    # release the library's device objects before the run's end, rather than at interpreter teardown
+    solver.close()
     del solver, alpha, q_xy, target
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
     def section(name, fn):
         # the extra sections never cost the main line: a failure is recorded instead
@@ -400,11 +471,17 @@ def main():
         section("invert", lambda: invert_iterations(dev, args.invert_iters))
     if args.serve_jobs > 0:
         section("serve", lambda: serve_section(args.serve_jobs))
+    if args.long_steps > 0 and args.workload == "stiff_256x256x64":
+        section("long", lambda: long_section(dev, args.long_steps, 64))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         section("cpu_baseline", lambda: {k: v for k, v in cpu_baseline(w, min(args.cpu_sample_steps, w.nsteps),
                                                                          args.cpu_threads).items()
                                          if k in ("value", "unit", "cores", "kind", "sample")})
+        if gpu_sample and "value" in rec["cpu_baseline"]:
+            rec["cpu_baseline"]["gpu_value_same_sample"] = gpu_sample
+            rec["cpu_baseline"]["gpu_over_cpu_same_sample"] = gpu_sample / rec["cpu_baseline"]["value"]
+    torch.cuda.synchronize()
     print(json.dumps(rec), flush=True)
 
 

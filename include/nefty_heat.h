@@ -72,8 +72,10 @@ typedef struct {
     double worst_rel_res;       /* largest final ||r||/||b|| over those solves */
     double bytes_alg_fwd;       /* algorithmic bytes of the last forward: 12R per voxel and CG iteration, 6R
                                    per voxel and step (textbook two-pass Jacobi-PCG, vectors in HBM) */
-    double bytes_alg_adj;       /* same for the last adjoint, 10R + 16 per voxel and step for the state load
-                                   and the FP64 gradient (recomputed forward steps counted as forward).
+    double bytes_alg_adj;       /* same for the last adjoint, with 9R + 16 per voxel and step: the set-up and
+                                   state store (6R) plus the gradient pass, which reads T^n, mu^n and alpha
+                                   (3R) and the FP64 accumulator (16) (recomputed forward steps counted as
+                                   forward).
                                    With fixed-K Jacobi sweeps: 4R per voxel and sweep, plus 3R + 16 per
                                    voxel and adjoint step for the gradient. A degree-m Chebyshev
                                    preconditioner adds 5R (m - 1) per voxel and CG iteration */
@@ -166,6 +168,21 @@ nh_status nh_adjoint_f64(nh_ctx *ctx, const double *dL_dTsurf, double *dL_dalpha
 nh_status nh_adjoint_vjp(nh_ctx *ctx, const float *dL_dTsurf, double *dL_dalpha, float *dL_dq, float *dL_dT0);
 nh_status nh_adjoint_vjp_f64(nh_ctx *ctx, const double *dL_dTsurf, double *dL_dalpha, double *dL_dq,
                              double *dL_dT0);
+
+/* The adjoint sweep with the gradients of the separable source
+ * q^n = q_t[n-1] * q_xy of the last forward (App. D.3, dL/dq^n = dt * mu^n on
+ * the top plane, chained through the product):
+ *   dL_dqxy [ny][nx] FP64 device: sum_n q_t[n-1] * dL/dq^n (n ascending);
+ *   dL_dqt  [nsteps] FP64 device: entry n-1 = sum_ij dL/dq^n_ij * q_xy_ij
+ *           (fixed summation order, bit-reproducible).
+ * dL/dq^n is rounded to the forward's precision before the sums. Either
+ * output may be NULL; dL_dalpha as in nh_adjoint. Same precision rules and
+ * errors as nh_adjoint / nh_adjoint_f64 (NH_ENOCONV still writes every
+ * output). The context keeps an nsteps x ny x nx workspace for the series. */
+nh_status nh_adjoint_source_grad(nh_ctx *ctx, const float *dL_dTsurf, double *dL_dalpha, double *dL_dqxy,
+                                 double *dL_dqt);
+nh_status nh_adjoint_source_grad_f64(nh_ctx *ctx, const double *dL_dTsurf, double *dL_dalpha,
+                                     double *dL_dqxy, double *dL_dqt);
 
 /* Copy the saved state T^n (1 <= n <= nsteps, full storage; or a checkpoint
  * step when checkpointing) of the last forward into `out` ([nz][ny][nx],

@@ -72,6 +72,7 @@ struct nh_ctx {
   // workspaces
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
   Buf tvpart;                                // per-workgroup partial sums of the TV regulariser
+  Buf srcq, srcqt;                           // source gradients: dL/dq^n series, q_t on the device
   Buf jt[2];                                 // tagged iterates of the blocked fixed-K kernel
   unsigned jt_tag = 1;                       // tag of the next launch's first phase (0: cleared)
   // steps of the blocked fixed-K kernel waiting to be launched together
@@ -570,8 +571,8 @@ nh_status check_positive(nh_ctx* c, const R* a, long long n, bool positive) {
 // reads r, p, alpha and writes p, q (5R) and the update pass reads x, p, r,
 // q, 1/D and writes x, r (7R): 12R. Per step the residual set-up reads the
 // previous state, alpha and the source and writes r, z (5R) and the state is
-// stored (R); an adjoint step also loads T^n (R) and accumulates the gradient
-// (T, mu, alpha read: 3R; the FP64 accumulator read and written: 16 bytes).
+// stored (R); an adjoint step adds the gradient pass, which reads T^n, mu^n
+// and alpha (3R) and reads and writes the FP64 accumulator (16 bytes).
 // FP32: 48 bytes per voxel-iteration, 24 per forward step, 52 per adjoint step.
 // With the fixed-K Jacobi solver a sweep reads x, alpha and the previous
 // state and writes the new x (4R per voxel and sweep); the last sweep writes
@@ -585,7 +586,7 @@ double step_bytes(const Geom& g, int R, int mode, int iters, bool jacobi, int ch
     // a Chebyshev preconditioner is applied once per iteration (after the
     // set-up and after every iteration but the last): cheb_m - 1 sweeps, each
     // reading y_k, y_{k-1}, z, alpha and writing y_{k+1}
-    per_voxel = (12.0 * R + 5.0 * R * (cheb_m - 1)) * iters + (mode == nh::kForward ? 6.0 * R : 10.0 * R + 16.0);
+    per_voxel = (12.0 * R + 5.0 * R * (cheb_m - 1)) * iters + (mode == nh::kForward ? 6.0 * R : 9.0 * R + 16.0);
   return per_voxel * (double)g.ng;
 }
 
@@ -1045,6 +1046,42 @@ nh_status do_adjoint(nh_ctx* c, const R* gsurf, double* G, R* dq, R* dT0) {
   return status_to_code(c, any);
 }
 
+// dL/dq_xy and dL/dq_t of the separable source q^n = q_t[n-1] q_xy (either
+// output may be null): the adjoint sweep with its dL/dq^n series, then
+// the chain rule through the product on the device (FP64, fixed order).
+template <typename R>
+nh_status do_source_grad(nh_ctx* c, const R* gsurf, double* G, double* d_qxy, double* d_qt) {
+  if (!c) return NH_EINVAL;
+  if (!gsurf || !G) return fail(c, NH_EINVAL, "null pointer argument");
+  if (c->saved_prec != (int)sizeof(R))
+    return fail(c, NH_ESTATE, "no saved forward of this precision (call the matching nh_forward first)");
+  const int N = c->saved_nsteps;
+  const long long nxy = c->geom.nxy;
+  R* dq = nullptr;
+  if (d_qxy || d_qt) {
+    NH_TRY(ensure(c, c->srcq, sizeof(R) * (size_t)N * (size_t)nxy));
+    dq = (R*)c->srcq.p;
+  }
+  nh_status st = do_adjoint<R>(c, gsurf, G, dq, nullptr);
+  if (st != NH_OK && st != NH_ENOCONV) return st;
+  if (d_qxy) {
+    NH_TRY(ensure(c, c->srcqt, sizeof(double) * (size_t)N));
+    NH_HIP(c, hipMemcpyAsync(c->srcqt.p, c->saved_qt.data(), sizeof(double) * (size_t)N, hipMemcpyHostToDevice,
+                             c->stream));
+    const int blocks = (int)std::min<long long>((nxy + nh::kSrcBlock - 1) / nh::kSrcBlock, 4096);
+    hipLaunchKernelGGL(nh::qxy_grad_kernel<R>, dim3(blocks), dim3(nh::kSrcBlock), 0, c->stream, (const R*)dq,
+                       (const double*)c->srcqt.p, N, nxy, d_qxy);
+    NH_HIP(c, hipGetLastError());
+  }
+  if (d_qt) {
+    hipLaunchKernelGGL(nh::qt_grad_kernel<R>, dim3(N), dim3(nh::kSrcBlock), 0, c->stream, (const R*)dq,
+                       (const R*)c->qxy.p, nxy, d_qt);
+    NH_HIP(c, hipGetLastError());
+  }
+  NH_HIP(c, hipStreamSynchronize(c->stream));
+  return st;
+}
+
 template <typename R>
 nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* value, double* grad,
                 int accumulate) {
@@ -1057,6 +1094,7 @@ nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* va
   const long long ng = (long long)c->nx * c->ny * c->nz;
   const int blocks = (int)std::min<long long>((ng + nh::kTvBlock - 1) / nh::kTvBlock, nh::kTvMaxBlocks);
   NH_TRY(ensure(c, c->tvpart, sizeof(double) * (size_t)blocks));
+  double* partial = (double*)c->tvpart.p;
   nh::TvArgs<R> A;
   A.alpha = alpha;
   A.nx = c->nx;
@@ -1071,7 +1109,7 @@ nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* va
   A.scale = weight * c->hx * c->hy * c->hz;
   A.grad = grad;
   A.accumulate = accumulate;
-  A.partial = (double*)c->tvpart.p;
+  A.partial = partial;
   hipLaunchKernelGGL(nh::tv_kernel<R>, dim3(blocks), dim3(nh::kTvBlock), 0, c->stream, A);
   NH_HIP(c, hipGetLastError());
   hipLaunchKernelGGL(nh::tv_finish_kernel, dim3(1), dim3(nh::kTvBlock), 0, c->stream, (const double*)A.partial,
@@ -1204,6 +1242,16 @@ nh_status nh_adjoint_vjp(nh_ctx* c, const float* dL_dTsurf, double* dL_dalpha, f
 nh_status nh_adjoint_vjp_f64(nh_ctx* c, const double* dL_dTsurf, double* dL_dalpha, double* dL_dq,
                              double* dL_dT0) {
   return do_adjoint<double>(c, dL_dTsurf, dL_dalpha, dL_dq, dL_dT0);
+}
+
+nh_status nh_adjoint_source_grad(nh_ctx* c, const float* dL_dTsurf, double* dL_dalpha, double* dL_dqxy,
+                                 double* dL_dqt) {
+  return do_source_grad<float>(c, dL_dTsurf, dL_dalpha, dL_dqxy, dL_dqt);
+}
+
+nh_status nh_adjoint_source_grad_f64(nh_ctx* c, const double* dL_dTsurf, double* dL_dalpha, double* dL_dqxy,
+                                     double* dL_dqt) {
+  return do_source_grad<double>(c, dL_dTsurf, dL_dalpha, dL_dqxy, dL_dqt);
 }
 
 nh_status nh_get_state(nh_ctx* c, int n, void* out) {
@@ -1343,7 +1391,7 @@ void nh_destroy(nh_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
-                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart,
+                 &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart, &c->srcq, &c->srcqt,
                  &c->jt[0], &c->jt[1], &c->pguess, &c->ppart, &c->pstate, &c->dmaxb};
   for (Buf* b : bufs) release(c, *b);
   for (Buf& b : c->mu) release(c, b);

@@ -1278,4 +1278,42 @@ __global__ void copy_kernel(const T* __restrict__ s, T* __restrict__ d, long lon
     d[i] = s[i];
 }
 
+
+// ---------------------------------------------------------------------------
+// gradients of the separable source q^n = q_t[n-1] q_xy (App. D.3: the
+// adjoint gives dL/dq^n = dt mu^n on the top plane, here dq[n-1][ny][nx])
+
+constexpr int kSrcBlock = 256;
+
+// dL/dq_xy[c] = sum_n q_t[n-1] dq[n-1][c], summed over n in ascending order.
+template <typename R>
+__global__ void __launch_bounds__(kSrcBlock) qxy_grad_kernel(const R* __restrict__ dq, const double* __restrict__ qt,
+                                                             int nsteps, long long nxy, double* __restrict__ out) {
+  for (long long c = blockIdx.x * (long long)kSrcBlock + threadIdx.x; c < nxy; c += (long long)gridDim.x * kSrcBlock) {
+    double s = 0.0;
+    for (int n = 0; n < nsteps; ++n) s += qt[n] * (double)dq[(size_t)n * nxy + c];
+    out[c] = s;
+  }
+}
+
+// dL/dq_t[n-1] = sum_c dq[n-1][c] q_xy[c]: one workgroup per step, a fixed
+// summation order (strided per thread, wave butterfly, waves in order).
+template <typename R>
+__global__ void __launch_bounds__(kSrcBlock) qt_grad_kernel(const R* __restrict__ dq, const R* __restrict__ qxy,
+                                                            long long nxy, double* __restrict__ out) {
+  const int n = blockIdx.x;
+  const R* f = dq + (size_t)n * nxy;
+  double s = 0.0;
+  for (long long c = threadIdx.x; c < nxy; c += kSrcBlock) s += (double)f[c] * (double)qxy[c];
+  s = wave_sum(s);
+  __shared__ double red[kSrcBlock / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kSrcBlock / 64; ++w) t += red[w];
+    out[n] = t;
+  }
+}
+
 }  // namespace nh

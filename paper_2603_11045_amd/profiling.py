@@ -25,7 +25,9 @@ import sys
 from typing import Dict, List, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/nh_kernels.hpp", "csrc/nh_resident.hpp", "csrc/nh_api.hip", "csrc/nh_serve.hip"]
+# every source under csrc/ (one translation unit includes all the headers)
+KERNEL_SOURCES = sorted("csrc/" + f for f in os.listdir(os.path.join(HERE, "csrc"))
+                        if f.endswith((".hip", ".hpp", ".h")))
 CALIB_KERNEL = "nh::copy_kernel<float>"
 CALIB_BYTES = 4 << 28          # bytes read (and, separately, written) per calibration dispatch
 

@@ -195,6 +195,23 @@ class Solver:
         self.last_status = _check(code, self._ctx, "nh_adjoint_vjp", allow)
         return G, dq, dT0
 
+    def adjoint_source_grad(self, dL_dTsurf: torch.Tensor, want_qxy: bool = True, want_qt: bool = True,
+                            allow_noconv: bool = False):
+        """``(dL/dalpha, dL/dq_xy, dL/dq_t)`` of the last forward, all float64
+        on the device: the adjoint sweep, then the library's chain rule through
+        ``q^n = q_t[n-1] * q_xy`` (``[ny][nx]`` and ``[nsteps]``; ``None``
+        when not wanted)."""
+        _dev_tensor(dL_dTsurf, "dL_dTsurf", self.dtype, self.nsteps * self.nx * self.ny)
+        G = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        dqxy = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_qxy else None
+        dqt = torch.empty(self.nsteps, dtype=torch.float64, device=self.device) if want_qt else None
+        fn = self.lib.nh_adjoint_source_grad if self.precision == "f32" else self.lib.nh_adjoint_source_grad_f64
+        code = fn(self._ctx, dL_dTsurf.data_ptr(), G.data_ptr(), dqxy.data_ptr() if want_qxy else None,
+                  dqt.data_ptr() if want_qt else None)
+        allow = (_lib.NH_ENOCONV,) if allow_noconv else ()
+        self.last_status = _check(code, self._ctx, "nh_adjoint_source_grad", allow)
+        return G, dqxy, dqt
+
     def get_state(self, n: int) -> torch.Tensor:
         out = torch.empty((self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         _check(self.lib.nh_get_state(self._ctx, int(n), out.data_ptr()), self._ctx, "nh_get_state")
@@ -285,17 +302,14 @@ class HeatSolve(torch.autograd.Function):
         if solver.generation != ctx.gen:
             solver.forward(a, *ctx.args)
         gg = g.detach().to(solver.dtype).contiguous()
-        want_q = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        want_qxy, want_qt = ctx.needs_input_grad[2], ctx.needs_input_grad[3]
         d_qxy = d_qt = None
-        if want_q:
-            G, dq, _ = solver.adjoint_vjp(gg)
-            q, qt, _, nsteps = ctx.args
-            qt_t = torch.as_tensor(np.asarray(qt, dtype=np.float64), device=dq.device)
-            dq64 = dq.double()
-            if ctx.needs_input_grad[2]:
-                d_qxy = (qt_t[:, None, None] * dq64).sum(dim=0).to(ctx.dtypes[1])
-            if ctx.needs_input_grad[3]:
-                d_qt = (dq64 * q.double()).sum(dim=(1, 2)).to(device=ctx.q_t_device, dtype=ctx.dtypes[2])
+        if want_qxy or want_qt:
+            G, d_qxy, d_qt = solver.adjoint_source_grad(gg, want_qxy, want_qt)
+            if d_qxy is not None:
+                d_qxy = d_qxy.to(ctx.dtypes[1])
+            if d_qt is not None:
+                d_qt = d_qt.to(device=ctx.q_t_device, dtype=ctx.dtypes[2])
         else:
             G = solver.adjoint(gg)
         return G.to(ctx.dtypes[0]), None, d_qxy, d_qt, None, None

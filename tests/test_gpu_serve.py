@@ -198,3 +198,129 @@ def test_stream_driver_and_sequential_baseline_agree(jobs):
     say("served", sa)
     say("sequential", sb)
     assert sa["jobs"] == sb["jobs"] == len(jobs)
+
+
+# The serving stream's own job shapes (the largest grids with 144- and
+# 64-workgroup resident teams, and the smallest with 4), drawn by the stream's
+# recipe (lognormal sigma 0.25, 1-8 boxes, uniform pulse on step 1, dt 5).
+# The oracle checks take short horizons for the two large grids (its FP64 CG
+# to 1e-13 costs seconds per step there); the 192x192x48 job of the long mix
+# runs 100 steps and is checked alone against the mix and against the
+# single-problem solver.
+C5_JOBS = [(192, 192, 48, 12, 51), (128, 128, 48, 12, 52), (32, 32, 16, 100, 53)]
+C5_RTOL = 1e-6
+
+
+def config5_job(nx, ny, nz, nsteps, seed):
+    (spec,) = wl.serving_stream(n_jobs=1, seed=seed, grids=[(nx, ny, nz)], steps=[nsteps])
+    return spec.workload
+
+
+@pytest.fixture(scope="module")
+def c5_jobs():
+    out = []
+    for spec in C5_JOBS:
+        w = config5_job(*spec)
+        src = orc.source_series(w.q_xy, w.q_t)
+        say(f"oracle for {w.name}, {w.nsteps} steps")
+        St, _, _ = orc.forward(w.alpha_target, src, w.dt, rtol=1e-10, keep_states=False)
+        target = St.astype(np.float32)
+        S, T_all, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-13)
+        L, gs = orc.mse_loss_and_grad(S, target)
+        G, _, _, _ = orc.adjoint(w.alpha, T_all, gs, w.dt, rtol=1e-13)
+        out.append(dict(w=w, target=target, L=L, G=G))
+    return out
+
+
+def submit_c5(srv, j):
+    w = j["w"]
+    return srv.submit(w.alpha, w.q_xy, w.q_t, j["target"], w.dt, 1.0, C5_RTOL, 2000)
+
+
+def test_serving_shapes_staggered_mix_matches_oracle_and_alone(c5_jobs):
+    """Each serving-stream shape alone and in a staggered mix (small slices,
+    so the large jobs span many ticks while others join and leave): bit for
+    bit the same, and each against the FP64 oracle."""
+    alone = []
+    for j in c5_jobs:
+        srv = Server(hbm_budget_bytes=200e9)
+        jid = submit_c5(srv, j)
+        srv.run_until_idle()
+        alone.append(srv.result(jid))
+        srv.close()
+    srv = Server(hbm_budget_bytes=200e9, slice_iters=8)
+    ids = [submit_c5(srv, c5_jobs[2])]
+    for _ in range(2):
+        srv.tick()
+    ids.append(submit_c5(srv, c5_jobs[0]))
+    for _ in range(5):
+        srv.tick()
+    ids.append(submit_c5(srv, c5_jobs[1]))
+    srv.run_until_idle()
+    ticks = srv.stats()["ticks"]
+    for jid, (La, Ga, ia), j in zip([ids[1], ids[2], ids[0]], alone, c5_jobs):
+        Lm, Gm, im = srv.result(jid)
+        eL, eG = abs(Lm - j["L"]) / j["L"], rel_l2(Gm, j["G"])
+        say(j["w"].name, "team", im["team_blocks"], "iters", im["fwd_iters"], im["adj_iters"], "loss rel", eL,
+            "G rel", eG, "alone==mix", Lm == La and np.array_equal(Gm, Ga))
+        assert im["state"] == _lib.NH_JOB_DONE and im["status"] == 0
+        assert eL <= 1e-5
+        assert eG <= 1e-4
+        assert Lm == La
+        assert np.array_equal(Gm, Ga)
+    assert [alone[0][2]["team_blocks"], alone[1][2]["team_blocks"], alone[2][2]["team_blocks"]] == [144, 64, 4]
+    say("mix ticks", ticks)
+    assert ticks > 20
+    srv.close()
+
+
+def test_long_serving_job_alone_equals_mix():
+    """A 192x192x48 job of 100 steps: alone with the default slice, and with
+    8-iteration slices among a stream of smaller jobs arriving during its
+    forward and adjoint sweeps; bit for bit the same loss and gradient, and the
+    same loss as the single-problem solver within the FP32 tolerance."""
+    from paper_2603_11045_amd.solver import Solver
+
+    big = config5_job(192, 192, 48, 100, 61)
+    others = [config5_job(*s) for s in [(64, 64, 32, 100, 62), (96, 96, 32, 100, 63), (32, 32, 16, 300, 64)]]
+    # measurements from the single-problem solver (any fixed series serves:
+    # both runs of the job see the same one)
+    sv = Solver(big.nx, big.ny, big.nz, rtol=C5_RTOL)
+    a = torch.from_numpy(big.alpha_target).cuda()
+    q = torch.from_numpy(big.q_xy).cuda()
+    target = sv.forward(a, q, big.q_t, big.dt, big.nsteps).cpu().numpy()
+    sa = sv.forward(torch.from_numpy(big.alpha).cuda(), q, big.q_t, big.dt, big.nsteps)
+    d = sa.double() - torch.from_numpy(target).cuda().double()
+    L_single = float((d * d).sum() / d.numel())
+    sv.close()
+
+    def sub(srv, w, t):
+        return srv.submit(w.alpha, w.q_xy, w.q_t, t, w.dt, 1.0, C5_RTOL, 2000)
+
+    srv = Server(hbm_budget_bytes=200e9)
+    jid = sub(srv, big, target)
+    srv.run_until_idle()
+    La, Ga, ia = srv.result(jid)
+    srv.close()
+    zeros = [np.zeros((w.nsteps, w.ny, w.nx), np.float32) for w in others]
+    srv = Server(hbm_budget_bytes=200e9, slice_iters=8)
+    jid = sub(srv, big, target)
+    n = 0
+    k = 0
+    while True:
+        na, nq, _ = srv.tick()
+        n += 1
+        if n % 15 == 0 and k < len(others):
+            sub(srv, others[k], zeros[k])
+            k += 1
+        if na == 0 and nq == 0:
+            break
+    Lm, Gm, im = srv.result(jid)
+    say("192x192x48 x 100 steps: ticks", n, "iters", im["fwd_iters"], im["adj_iters"], "alone==mix",
+        Lm == La and np.array_equal(Gm, Ga), "loss vs single-problem", abs(Lm - L_single) / L_single)
+    assert k == len(others)
+    assert im["state"] == _lib.NH_JOB_DONE and im["status"] == 0
+    assert Lm == La
+    assert np.array_equal(Gm, Ga)
+    assert abs(Lm - L_single) <= 1e-5 * L_single
+    srv.close()
