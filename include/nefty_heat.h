@@ -213,6 +213,23 @@ nh_status nh_tv(nh_ctx *ctx, const float *alpha, double eps, double weight, doub
 nh_status nh_tv_f64(nh_ctx *ctx, const double *alpha, double eps, double weight, double *value, double *grad,
                     int accumulate);
 
+/* nh_tv without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, result and errors as nh_tv (FP32 alpha), but
+ * the per-workgroup partial sums go to one static device array per GPU
+ * (4096 doubles, 32 KiB, held until the process ends; its address is
+ * resolved by nh_create) instead of a context workspace, and the call
+ * returns as soon as its two kernels are queued on the context's stream:
+ * value and grad are ready when that stream reaches them. Every workgroup
+ * writes its own partial before the finishing kernel reads it, so nothing
+ * carries over between calls; but all calls on one GPU share the array, so
+ * calls that overlap in time on one GPU (several streams or host threads)
+ * race and must be serialised by the caller. Grids needing more partial
+ * sums than the array holds are rejected with NH_EINVAL (the kernel's
+ * workgroup count is capped at the array's size, so none does today). */
+nh_status nh_tv_noalloc(nh_ctx *ctx, const float *alpha, double eps, double weight, double *value, double *grad,
+                        int accumulate);
+
 /* Launch tuning: team_blocks_max caps the workgroups of one step (0 = all
  * that fit on the device), tile_z sets the z extent of a tile (0 = auto).
  * profile != 0 times every step kernel with HIP events (nh_stats.t_kernel_*). */

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,30 @@ namespace {
 
 using nh::Geom;
 using nh::StepArgs;
+
+// Device scratch of the allocation-free TV entry point (nh_tv_noalloc): the
+// per-workgroup partial sums of the regulariser's value. One copy per GPU,
+// held until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the device (kept in scratch_ptr).
+constexpr int kScratchDoubles = nh::kTvMaxBlocks;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex scratch_mu;
+std::vector<double*> scratch_ptr;          // by device ordinal; null until resolved
+
+// The scratch address on `device`, which must be current. Resolved once per device.
+hipError_t scratch_of(int device, double** out) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if ((int)scratch_ptr.size() <= device) scratch_ptr.resize(device + 1, nullptr);
+  if (!scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[device] = (double*)p;
+  }
+  *out = scratch_ptr[device];
+  return hipSuccess;
+}
 
 struct Buf {
   void* p = nullptr;
@@ -73,6 +98,7 @@ struct nh_ctx {
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
   Buf tvpart;                                // per-workgroup partial sums of the TV regulariser
   Buf srcq, srcqt;                           // source gradients: dL/dq^n series, q_t on the device
+  double* scratch = nullptr;                 // this device's scratch array (nh_tv_noalloc)
   Buf jt[2];                                 // tagged iterates of the blocked fixed-K kernel
   unsigned jt_tag = 1;                       // tag of the next launch's first phase (0: cleared)
   // steps of the blocked fixed-K kernel waiting to be launched together
@@ -1082,9 +1108,12 @@ nh_status do_source_grad(nh_ctx* c, const R* gsurf, double* G, double* d_qxy, do
   return st;
 }
 
+// noalloc: use the device's static scratch for the partial sums instead of a
+// context workspace, and return once the work is queued (no allocation, no
+// synchronisation).
 template <typename R>
 nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* value, double* grad,
-                int accumulate) {
+                int accumulate, bool noalloc = false) {
   if (!c) return NH_EINVAL;
   if (!c->grid_set) return fail(c, NH_ESTATE, "nh_set_grid has not been called");
   if (!alpha || !value || !grad) return fail(c, NH_EINVAL, "null pointer argument");
@@ -1093,8 +1122,17 @@ nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* va
   if (accumulate != 0 && accumulate != 1) return fail(c, NH_EINVAL, "accumulate must be 0 or 1");
   const long long ng = (long long)c->nx * c->ny * c->nz;
   const int blocks = (int)std::min<long long>((ng + nh::kTvBlock - 1) / nh::kTvBlock, nh::kTvMaxBlocks);
-  NH_TRY(ensure(c, c->tvpart, sizeof(double) * (size_t)blocks));
-  double* partial = (double*)c->tvpart.p;
+  double* partial = nullptr;
+  if (noalloc) {
+    if (!c->scratch) return fail(c, NH_ESTATE, "the device scratch array was not resolved");
+    if (blocks > kScratchDoubles)
+      return fail(c, NH_EINVAL, "grid needs " + std::to_string(blocks) + " partial sums, the scratch holds " +
+                                    std::to_string(kScratchDoubles));
+    partial = c->scratch;
+  } else {
+    NH_TRY(ensure(c, c->tvpart, sizeof(double) * (size_t)blocks));
+    partial = (double*)c->tvpart.p;
+  }
   nh::TvArgs<R> A;
   A.alpha = alpha;
   A.nx = c->nx;
@@ -1115,7 +1153,7 @@ nh_status do_tv(nh_ctx* c, const R* alpha, double eps, double weight, double* va
   hipLaunchKernelGGL(nh::tv_finish_kernel, dim3(1), dim3(nh::kTvBlock), 0, c->stream, (const double*)A.partial,
                      blocks, A.scale, value);
   NH_HIP(c, hipGetLastError());
-  NH_HIP(c, hipStreamSynchronize(c->stream));
+  if (!noalloc) NH_HIP(c, hipStreamSynchronize(c->stream));
   return NH_OK;
 }
 
@@ -1131,6 +1169,11 @@ nh_status nh_tv(nh_ctx* c, const float* alpha, double eps, double weight, double
 nh_status nh_tv_f64(nh_ctx* c, const double* alpha, double eps, double weight, double* value, double* grad,
                     int accumulate) {
   return do_tv<double>(c, alpha, eps, weight, value, grad, accumulate);
+}
+
+nh_status nh_tv_noalloc(nh_ctx* c, const float* alpha, double eps, double weight, double* value, double* grad,
+                        int accumulate) {
+  return do_tv<float>(c, alpha, eps, weight, value, grad, accumulate, true);
 }
 
 nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
@@ -1177,6 +1220,10 @@ nh_status nh_create(nh_ctx** out, int hip_device, void* hip_stream) {
                                                      nh::kJacBlock, 0) == hipSuccess)
       c->jac_occ = jo;
     (void)hipGetLastError();
+  }
+  if (scratch_of(hip_device, &c->scratch) != hipSuccess) {
+    delete c;
+    return NH_EHIP;
   }
   if (const char* e = std::getenv("NH_TRACE_STEP")) c->trace_step = std::atoi(e);
   if (const char* e = std::getenv("NH_TRACE_RANK")) c->trace_rank = std::atoi(e);
