@@ -48,7 +48,9 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        # NH_ORACLE_LIB names another build of heat_oracle.c to use instead (the
+        # sanitizer tier's instrumented build)
+        lib = ctypes.CDLL(os.environ.get("NH_ORACLE_LIB") or build())
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
         ip = P(ctypes.c_int)

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnefty_heat.so")
-SOURCES = ["nh_api.hip", "nh_serve.hip"]
+SOURCES = ["nh_api.hip", "nh_serve.hip", "nh_policy.cpp"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -120,6 +120,7 @@ struct nh_ctx {
   bool jac_tb = false;                       // the current plan uses nh::jacobi_step_kernel
   int jtx = 0, jty = 0;                      //   with this many interior tiles per axis
   unsigned long long launch_ctr = 0;         // makes every launch's reduction epochs unique
+  int slot_layout = 0;                       // slots hold: 0 zeros, 1 tagged words (team_sum_dev), 2 team_sum's
   size_t ws_bytes = 0, ws_peak = 0;
 
   Geom geom{};
@@ -331,10 +332,26 @@ int occupancy(nh_ctx* c) {
   return sizeof(R) == 4 ? c->occ_f32 : c->occ_f64;
 }
 
+// Make the reduction slots ready for a launch whose reductions use the
+// tagged words of team_sum_dev (tagged) or team_sum's layout, with epochs from
+// epoch_base on. Tags are the low 32 bits of the epochs, which repeat every
+// 256 launches: the slots are zeroed when a tagged launch starts a new round
+// of 256, and whenever the layout changes, so no stale word can carry the
+// tag a reader waits for.
+nh_status prepare_slots(nh_ctx* c, bool tagged, unsigned long long epoch_base) {
+  const int want = tagged ? 1 : 2;
+  const bool new_round = tagged && ((epoch_base >> 24) & 0xFF) == 0;
+  if (new_round || (c->slot_layout != 0 && c->slot_layout != want))
+    NH_TRY(fill<unsigned long long>(c, (unsigned long long*)c->slots.p, (long long)(c->slots.bytes / 8), 0ull));
+  c->slot_layout = want;
+  return NH_OK;
+}
+
 // Launch the queued steps of the blocked fixed-K kernel as one launch, timed
 // with the event pair of the first of them.
 nh_status flush_steps(nh_ctx* c) {
   if (c->jq.count == 0) return NH_OK;
+  NH_TRY(prepare_slots(c, true, c->jq_epoch));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profile && c->jq_ev >= 0) {
     e0 = c->ev[2 * c->jq_ev];
@@ -395,6 +412,7 @@ nh_status launch_step(nh_ctx* c, StepArgs<R>& S, int slot_ev, double* t_kernel) 
     }
   }
   NH_TRY(flush_steps(c));
+  NH_TRY(prepare_slots(c, sizeof(R) == 4 && (c->resident || c->jac_tb), S.epoch_base));
   void* args[] = {(void*)&S};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profile) {
@@ -648,6 +666,7 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
   if (c->slots.bytes < slot_bytes || !c->slots.p) {
     NH_TRY(ensure(c, c->slots, slot_bytes));
     NH_HIP(c, hipMemsetAsync(c->slots.p, 0, c->slots.bytes, c->stream));  // epoch 0 is never used
+    c->slot_layout = 0;
   }
   if (!c->flag.p) {
     NH_TRY(ensure(c, c->flag, 64));

@@ -180,19 +180,29 @@ __device__ __forceinline__ double ld_val(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Shared state of one workgroup.
+// Shared state of one workgroup: two buffers of a staged plane (alpha and up
+// to two vectors; march_tile alternates them), and red, two buffers of
+// per-wave partial sums, which the two block sums of a team reduction use in
+// turn.
 template <typename R>
 struct Smem {
-  R a[kMaxPlane];
-  R v[2][kMaxPlane];
-  double red[kMaxWaves][kNumRed];
+  R a[2][kMaxPlane];
+  R v[2][2][kMaxPlane];
+  double red[2][kMaxWaves][kNumRed];
   double bc[kNumRed];
   int flag;
 };
 
-// Sum NV doubles over the workgroup of WAVES wave64; the result lands in every thread's v.
+// Sum NV doubles over the workgroup of WAVES wave64; the result lands in every
+// thread's v. Each wave sums its lanes with a butterfly; after one barrier
+// every wave loads the waves' sums (lane w holds wave w's) and sums them with
+// the same butterfly, so all threads hold the same bits. red must not be
+// written again before every thread has passed the next workgroup barrier:
+// callers alternate two buffers between consecutive block sums, with a
+// barrier in each.
 template <int NV, int WAVES>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed], double* bc) {
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed]) {
+  static_assert(WAVES <= 64, "one lane per wave");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
@@ -201,18 +211,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
     for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0.0;
-      for (int w = 0; w < WAVES; ++w) s += red[w][i];
-      bc[i] = s;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = bc[i];
-  __syncthreads();
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(lane < WAVES ? red[lane][i] : 0.0);
 }
 
 // Team all-reduce of NV doubles; also the team's barrier. Every workgroup
@@ -225,8 +225,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
 template <typename R, int NV, int BLOCK = Cfg<R>::kBlock>
 __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigned long long& epoch,
                                          double (&v)[NV], Smem<R>& sh) {
-  block_sum<NV, BLOCK / 64>(v, sh.red, sh.bc);
-  if (S.team == 1) return true;
+  block_sum<NV, BLOCK / 64>(v, sh.red[0]);
+  if (S.team == 1) {
+    __syncthreads();                        // red[0] is free again
+    return true;
+  }
   const unsigned long long e = ++epoch;
   Slot* slots = (Slot*)S.slots;
   Slot* res = slots + S.team;
@@ -271,7 +274,7 @@ __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigne
       for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
     }
     ok = __syncthreads_and(ok);
-    block_sum<NV, BLOCK / 64>(s, sh.red, sh.bc);
+    block_sum<NV, BLOCK / 64>(s, sh.red[1]);
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
@@ -463,33 +466,39 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
       }
     }
 
-    __syncthreads();
-    sh.a[oslot] = qa[1];
+    // planes alternate between two LDS buffers, so one barrier per plane
+    // suffices: a buffer is written again two planes later, after the next
+    // plane's barrier, which every wave passes only once it has finished
+    // reading this plane
+    const int bf = (z - T.z0) & 1;
+    R* la = sh.a[bf];
+    R (*lv)[kMaxPlane] = sh.v[bf];
+    la[oslot] = qa[1];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sh.v[k][oslot] = qv[1][k];
+    for (int k = 0; k < NV; ++k) lv[k][oslot] = qv[1][k];
     if (hslot >= 0) {
-      sh.a[hslot] = ha[0];
+      la[hslot] = ha[0];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) sh.v[k][hslot] = hv[0][k];
+      for (int k = 0; k < NV; ++k) lv[k][hslot] = hv[0][k];
     }
     __syncthreads();
 
     if (own) {
       Pt<R, NV> P;
       P.a[0] = qa[1];
-      P.a[1] = sh.a[oslot - 1];
-      P.a[2] = sh.a[oslot + 1];
-      P.a[3] = sh.a[oslot - PW];
-      P.a[4] = sh.a[oslot + PW];
+      P.a[1] = la[oslot - 1];
+      P.a[2] = la[oslot + 1];
+      P.a[3] = la[oslot - PW];
+      P.a[4] = la[oslot + PW];
       P.a[5] = qa[0];
       P.a[6] = qa[2];
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         P.v[k][0] = qv[1][k];
-        P.v[k][1] = sh.v[k][oslot - 1];
-        P.v[k][2] = sh.v[k][oslot + 1];
-        P.v[k][3] = sh.v[k][oslot - PW];
-        P.v[k][4] = sh.v[k][oslot + PW];
+        P.v[k][1] = lv[k][oslot - 1];
+        P.v[k][2] = lv[k][oslot + 1];
+        P.v[k][3] = lv[k][oslot - PW];
+        P.v[k][4] = lv[k][oslot + PW];
         P.v[k][5] = qv[0][k];
         P.v[k][6] = qv[2][k];
       }
@@ -512,6 +521,7 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
       for (int k = 0; k < NO; ++k) qo[j][k] = qo[j + 1][k];
     }
   }
+  __syncthreads();                          // both plane buffers are free for the next tile
 }
 
 // A v and the diagonal D of A at one cell, from staged alpha and v (row k of P).

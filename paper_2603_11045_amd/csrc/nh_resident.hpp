@@ -34,8 +34,25 @@ __device__ __forceinline__ float ld_dev(const float* p) {
 }
 constexpr int kCpolSc1 = 16;                // cache policy of a device-coherent load (sc1), as ld_dev
 
+// Buffer access to one FP32 vector of n elements: a lane's element offset
+// (bytes, per lane) plus a plane offset (bytes, uniform) -- no per-lane 64-bit
+// address arithmetic. A lane whose offset is kNoLane reads 0 and writes
+// nothing (out of the buffer's range), which replaces a lane condition.
+constexpr unsigned kNoLane = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const float* p, long long n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, (int)(n * 4), 0x00020000);
+}
+template <int CPOL = 0>
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CPOL));
+}
+template <int CPOL = 0>
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, CPOL);
+}
+
 struct ResRed {
-  double red[kMaxWaves][kNumRed];
+  double red[2][kMaxWaves][kNumRed];        // two buffers of per-wave partials (block_sum)
   double bc[kNumRed];
   int flag;
 };
@@ -47,51 +64,113 @@ constexpr size_t kResRingFloats = 3 * (size_t)kResTZ * kRing;          // [3 vec
 constexpr size_t kResLdsBytes =
     (kResAlphaFloats + kResPlaneFloats + kResRingFloats) * sizeof(float) + sizeof(ResRed) + 64;
 
-// Team reduction for the resident kernel. Every workgroup stores its sum in
-// its own slot and publishes it with the reduction's epoch; then EVERY
-// workgroup gathers all slots and sums them in the same fixed order, so all
-// obtain bit-identical results after one exchange (no master round trip).
-// Slots alternate between two banks by epoch parity: a workgroup can be at
-// most one reduction ahead of the slowest reader (the next reduction needs
-// every workgroup's slot), so a bank is never rewritten while still read.
-// Every value another workgroup reads was written with device-scope stores,
-// so the publication needs only the completion of this workgroup's stores (a
-// full s_waitcnt in every wave) and no cache maintenance. Slots: 2 * team.
-template <int NV, int BLOCK = kResBlock>
+// Team reduction of the resident and blocked kernels. Every workgroup stores
+// its sum in its own slot, then EVERY workgroup gathers all slots and sums them
+// in the same fixed order, so all obtain bit-identical results after one
+// exchange (no master round trip). Each FP64 value travels as two 64-bit words
+// (tag << 32 | one half of its bits), the tag being the low 32 bits of the
+// reduction's epoch: a reader takes a slot's values and their validity in one
+// load round trip, and the writer issues its words without waiting between
+// them. Tags are unique between clears of the slots: an epoch is
+// (launch << 24) + k with k < 2^24 reductions per launch, and the host zeroes
+// the slots every 256 launches (tag 0 is never used) and whenever the slots
+// held the untagged layout of team_sum. Slots alternate between two banks by
+// epoch parity: a workgroup can be at most one reduction ahead of the slowest
+// reader (the next reduction needs every workgroup's slot), so a bank is
+// never rewritten while still read. Every value another workgroup reads was
+// written with device-scope stores, and every wave waits for its own stores
+// before the workgroup's block sum, so the tags are issued after the
+// workgroup's earlier stores have completed: the reduction doubles as the
+// team's barrier with no cache maintenance. Slots: 2 * team.
+struct alignas(64) TSlot {
+  unsigned long long w[2 * kNumRed];
+};
+static_assert(sizeof(TSlot) == sizeof(Slot), "the slot buffers are sized for either layout");
+
+__device__ __forceinline__ void st_tag(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// No work to start once the neighbours have published (see team_sum_dev).
+struct NoNeighbours {
+  __device__ int rank(int) const { return -1; }
+  __device__ void ready() const {}
+};
+
+// nbr.rank(k), k < 6, gives the ranks of the workgroups whose tiles share a
+// face with this one (-1: none); once every one of them has published its slot
+// for this reduction -- so their earlier stores are visible -- every wave calls
+// nbr.ready(), which may start loads of what the neighbours published, before
+// it gathers slots. (Keeping those loads to the waves that gather no slots
+// measured slower.)
+template <int NV, int BLOCK = kResBlock, class Nbr = NoNeighbours>
 __device__ __forceinline__ bool team_sum_dev(const StepArgs<float>& S, int rank, unsigned long long& epoch,
-                                             double (&v)[NV], ResRed* rs) {
+                                             double (&v)[NV], ResRed* rs, const Nbr& nbr = Nbr()) {
+  static_assert(NV <= kNumRed, "slot too small");
   __builtin_amdgcn_s_waitcnt(0);
-  block_sum<NV, BLOCK / 64>(v, rs->red, rs->bc);
-  if (S.team == 1) return true;
+  block_sum<NV, BLOCK / 64>(v, rs->red[0]);
+  if (S.team == 1) {
+    __syncthreads();                        // red[0] is free again
+    return true;
+  }
   const unsigned long long e = ++epoch;
-  Slot* slots = (Slot*)S.slots + (size_t)(e & 1) * S.team;
+  const unsigned tag = (unsigned)e;
+  const unsigned long long th = (unsigned long long)tag << 32;
+  TSlot* slots = (TSlot*)S.slots + (size_t)(e & 1) * S.team;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
-      __hip_atomic_store(&slots[rank].v[i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_s_waitcnt(0);
-    __hip_atomic_store(&slots[rank].epoch, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = 0; i < NV; ++i) {
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(v[i]);
+      st_tag(&slots[rank].w[2 * i], th | (bits & 0xffffffffull));
+      st_tag(&slots[rank].w[2 * i + 1], th | (bits >> 32));
+    }
+  }
+  int ok = 1;
+  {
+    // every wave waits (lanes 0-5) for the neighbours' slots, then starts its loads
+    const int k = threadIdx.x & 63;
+    const int b = k < 6 ? nbr.rank(k) : -1;
+    if (b >= 0 && b != rank) {
+      const long long t0 = wall_clock64();
+      while (true) {
+        bool all = true;
+#pragma unroll
+        for (int j = 0; j < 2 * NV; ++j) all &= (unsigned)(ld_epoch(&slots[b].w[j]) >> 32) == tag;
+        if (all) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
+      }
+    }
+    nbr.ready();
   }
   double s[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) s[i] = 0.0;
-  int ok = 1;
   for (int b = threadIdx.x; b < S.team; b += BLOCK) {
     if (b == rank) {
 #pragma unroll
       for (int i = 0; i < NV; ++i) s[i] += v[i];
       continue;
     }
+    unsigned long long w[2 * NV];
     const long long t0 = wall_clock64();
-    while (ld_epoch(&slots[b].epoch) != e) {
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int k = 0; k < 2 * NV; ++k) {
+        w[k] = ld_epoch(&slots[b].w[k]);
+        all &= (unsigned)(w[k] >> 32) == tag;
+      }
+      if (all) break;
       __builtin_amdgcn_s_sleep(1);
       if (wall_clock64() - t0 > S.timeout_ticks) { ok = 0; break; }
     }
 #pragma unroll
-    for (int i = 0; i < NV; ++i) s[i] += ld_val(&slots[b].v[i]);
+    for (int i = 0; i < NV; ++i)
+      s[i] += __longlong_as_double((long long)((w[2 * i + 1] << 32) | (w[2 * i] & 0xffffffffull)));
   }
   ok = __syncthreads_and(ok);
-  block_sum<NV, BLOCK / 64>(s, rs->red, rs->bc);
+  block_sum<NV, BLOCK / 64>(s, rs->red[1]);
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = s[i];
   if (!ok && threadIdx.x == 0) atomicOr(S.err_flag, (int)kTimeout);
@@ -108,6 +187,25 @@ struct RG {
   static constexpr int RING = 2 * (TX + TY);
   static_assert(PL <= kResPlane && RING <= kRing, "tile too large");
 };
+
+// LDS layout of a ring buffer (the values of one vector on the tile's halo
+// ring, every plane of the tile), side by side so that a wave's direct load
+// of 64 consecutive slots is one halo row of one plane (the -y and +y sides,
+// 64 cells each) or the 8 halo cells of the -x or +x side on 8 consecutive
+// planes: [-y: TZ][64] [+y: TZ][64] [-x: TZ][8] [+x: TZ][8].
+constexpr int kRingRowN = kResTZ * 64;                     // one row side
+constexpr int kRingColN = kResTZ * 8;                      // one column side
+constexpr int kRingYm = 0, kRingYp = kRingRowN, kRingXm = 2 * kRingRowN, kRingXp = 2 * kRingRowN + kRingColN;
+static_assert(2 * kRingRowN + 2 * kRingColN == kResTZ * kRing, "ring layout");
+
+// Ring cell h in the order of ring_cell (h < TX: -y row, then +y row, -x
+// column, +x column) at plane z: its slot in a ring buffer is base + z * stride.
+__device__ __forceinline__ void ring_slot(int h, int& base, int& stride) {
+  if (h < 64) { base = kRingYm + h; stride = 64; }
+  else if (h < 128) { base = kRingYp + h - 64; stride = 64; }
+  else if (h < 136) { base = kRingXm + h - 128; stride = 8; }
+  else { base = kRingXp + h - 136; stride = 8; }
+}
 
 // Where one thread of the resident workgroup sits in its tile.
 struct ResPos {
@@ -136,11 +234,12 @@ __device__ __forceinline__ void ring_cell(const Geom& g, const ResPos& q, int h,
   hcol = in ? hx + g.nx * hy : 0;
 }
 
-// Fill an LDS ring buffer for every plane of the tile: ring[z][h] =
+// Fill an LDS ring buffer for every plane of the tile: ring[slot(z, h)] =
 // val(global index) for in-grid ring cells, 0 outside. All loads of a thread
 // are issued before the first LDS store, so the fill costs one memory latency.
 template <class G, typename F>
 __device__ __forceinline__ void fill_ring(const Geom& g, const ResPos& q, float* ring, F val) {
+  static_assert(G::TX == 64 && G::TY == 8, "ring layout assumes 64 x 8 tiles");
   constexpr int kMaxPer = (G::RING * kResTZ + kResBlock - 1) / kResBlock;
   const int n = G::RING * q.tzn;
   float v[kMaxPer];
@@ -153,9 +252,10 @@ __device__ __forceinline__ void fill_ring(const Geom& g, const ResPos& q, float*
     if (e < n) {
       const int z = e / G::RING, h = e - z * G::RING;
       bool in;
-      int hcol, hslot;
+      int hcol, hslot, base, stride;
       ring_cell<G>(g, q, h, in, hcol, hslot);
-      slot[k] = z * kRing + h;
+      ring_slot(h, base, stride);
+      slot[k] = base + z * stride;
       if (in) v[k] = val(hcol + (q.z0 + z) * (int)g.nxy);
     }
   }
@@ -205,11 +305,18 @@ template <class G, int NV, typename OwnF, typename RingF, typename CellF>
 __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, float* lp, RingF ringv,
                                               OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
   // ring cells handled by this thread for the plane copy
+  // the ring cell this thread copies into the plane: its LDS plane slot, ring
+  // slot base and the log2 of the ring slot stride per plane, packed in one
+  // register (hslot < 1024, base < 8192)
   const int h = q.tid;
-  bool hin = false;
-  int hcol = 0;
-  int hslot = -1;
-  if (h < G::RING) ring_cell<G>(g, q, h, hin, hcol, hslot);
+  int hpack = -1;
+  if (h < G::RING) {
+    bool hin;
+    int hcol, hslot, rbase, rstride;
+    ring_cell<G>(g, q, h, hin, hcol, hslot);
+    ring_slot(h, rbase, rstride);
+    hpack = hslot | (rbase << 10) | ((rstride == 64 ? 6 : 3) << 23);
+  }
 #pragma unroll
   for (int z = 0; z < kResTZ; ++z) {
     if (z < q.tzn) {
@@ -219,7 +326,11 @@ __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, fl
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         pl[k][q.oslot] = q.own ? own(k, z) : 0.f;
-        if (hslot >= 0) pl[k][hslot] = ringv(k, z * kRing + h);
+        // (laundered per plane, so that the 32 planes' ring slots are not all
+        // precomputed into registers)
+        int hp = hpack;
+        asm volatile("" : "+v"(hp));
+        if (hp >= 0) pl[k][hp & 1023] = ringv(k, ((hp >> 10) & 8191) + (z << (hp >> 23)));
       }
       __syncthreads();
       if (q.own) {
@@ -236,7 +347,7 @@ __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, fl
   __syncthreads();
 }
 
-// Plane sweep whose halo ring values are stored in LDS, [NV][TZ][kRing].
+// Plane sweep whose halo ring values are stored in LDS (NV ring buffers).
 template <class G, int NV, typename OwnF, typename CellF>
 __device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, float* lp, const float* ring,
                                             OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
@@ -244,30 +355,82 @@ __device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, floa
                        zhi, cell);
 }
 
-// Start copying src's values at the tile's ring cells into an LDS ring
-// ([TZ][kRing]) with direct global-to-LDS loads (device-coherent), without
-// waiting: each wave writes 64 consecutive ring slots per load, so ring slot
-// = element index, which holds when the ring has exactly kRing cells. Ring
-// cells outside the grid are not loaded and must hold zeros already.
+// Rank of the workgroup owning face neighbour k (-x, +x, -y, +y, -z, +z) of
+// tile `tile`, or -1 at the grid's edge (first_tile inverted).
+__device__ __forceinline__ int neighbour_rank(const Geom& g, int tile, int team, int xcd, int k) {
+  const int itz = tile % g.ntz, rest = tile / g.ntz;
+  const int itx = rest % g.ntx, ity = rest / g.ntx;
+  int t = -1;
+  switch (k) {
+    case 0: t = itx > 0 ? tile - g.ntz : -1; break;
+    case 1: t = itx + 1 < g.ntx ? tile + g.ntz : -1; break;
+    case 2: t = ity > 0 ? tile - g.ntz * g.ntx : -1; break;
+    case 3: t = ity + 1 < g.nty ? tile + g.ntz * g.ntx : -1; break;
+    case 4: t = itz > 0 ? tile - 1 : -1; break;
+    default: t = itz + 1 < g.ntz ? tile + 1 : -1; break;
+  }
+  if (t < 0) return -1;
+  if (xcd && (team & 7) == 0) {             // the inverse of first_tile's XCD order
+    const int per = team >> 3;
+    return (t % per) * 8 + t / per;
+  }
+  return t;
+}
+
+// The tagged reduction's early hook of the resident step: the neighbours'
+// ranks and `ready`, which the reduction calls in every wave once they have
+// all published.
+template <typename F>
+struct ResNeighbours {
+  const Geom& g;
+  int tile, team, xcd;
+  F ready_f;
+  __device__ int rank(int k) const { return neighbour_rank(g, tile, team, xcd, k); }
+  __device__ void ready() const { ready_f(); }
+};
+template <typename F>
+__device__ __forceinline__ ResNeighbours<F> res_neighbours(const Geom& g, int tile, int team, int xcd, F f) {
+  return ResNeighbours<F>{g, tile, team, xcd, f};
+}
+
+// Start copying src's values at the tile's ring cells into an LDS ring buffer
+// with direct global-to-LDS loads (device-coherent), without waiting. Each
+// wave issues nine loads of 64 lanes: the -y and +y halo rows of planes w,
+// w + 8, w + 16, w + 24 (lane = x offset; coalesced) and one block of eight
+// planes of the -x (waves 0-3) or +x (waves 4-7) halo column (lane = 8 z + y),
+// landing in 64 consecutive slots of the side-by-side layout. Lanes on cells
+// outside the grid or below the tile's last plane load nothing: their slots
+// must hold zeros already. (Loading the rows 16 bytes per lane, four planes
+// per load, measured slower.)
 template <class G>
 __device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* ring, const float* src, int tid,
                                          int nxy) {
-  static_assert(G::RING == kRing, "ring slots must equal ring cells");
-  constexpr int kMaxPer = (G::RING * kResTZ + kResBlock - 1) / kResBlock;
-  const int n = G::RING * q.tzn;
+  static_assert(G::TX == 64 && G::TY == 8 && kResBlock == 512, "ring loads assume 64 x 8 tiles, 8 waves");
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  // rows: x = x0 + lane at y0 - 1 and y0 + 8
+  const int gx = q.x0 + lane;
+  const bool row_x = gx < g.nx;
+  const bool ym = row_x && q.y0 > 0, yp = row_x && q.y0 + G::TY < g.ny;
+  const float* bz = src + (long long)q.z0 * nxy;
 #pragma unroll
-  for (int k = 0; k < kMaxPer; ++k) {
-    const int e = tid + k * kResBlock;
-    if (e < n) {
-      const int z = e / G::RING, h = e - z * G::RING;
-      bool in;
-      int hcol, hslot;
-      ring_cell<G>(g, q, h, in, hcol, hslot);
-      if (in)
-        __builtin_amdgcn_global_load_lds(src + hcol + (q.z0 + z) * nxy,
-                                         ring + (tid & ~63) + k * kResBlock, 4, 0, kCpolSc1);
+  for (int j = 0; j < 4; ++j) {
+    const int z = wave + 8 * j;
+    if (z < q.tzn) {
+      const float* pz = bz + (long long)z * nxy;
+      if (ym) __builtin_amdgcn_global_load_lds(pz + (gx + g.nx * (q.y0 - 1)), ring + kRingYm + 64 * z, 4, 0, kCpolSc1);
+      if (yp) __builtin_amdgcn_global_load_lds(pz + (gx + g.nx * (q.y0 + G::TY)), ring + kRingYp + 64 * z, 4, 0,
+                                               kCpolSc1);
     }
   }
+  // columns: eight planes 8 b .. 8 b + 7 of side x0 - 1 (b = wave) or x0 + 64 (b = wave - 4)
+  const int b = wave & 3;
+  const bool xp = wave >= 4;
+  const int cx = xp ? q.x0 + G::TX : q.x0 - 1;
+  const int cz = 8 * b + (lane >> 3), cy = q.y0 + (lane & 7);
+  if (cz < q.tzn && cx >= 0 && cx < g.nx && cy < g.ny)
+    __builtin_amdgcn_global_load_lds(bz + ((long long)cz * nxy + cx + (long long)g.nx * cy),
+                                     ring + (xp ? kRingXp : kRingXm) + 64 * b, 4, 0, kCpolSc1);
 }
 
 // One implicit-Euler step of one team with the tile's CG state in registers
@@ -312,6 +475,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
 
   unsigned long long red = V.epoch_base;
   bool ok = true;
+  // phase stamps (NH_TRACE_STEP) only in the traced instance: the untraced
+  // one keeps no trace state live through the step
   int ntr = 0;
   const bool tr = S.trace && (rank == S.trace_rank || S.trace_rank < 0) && threadIdx.x == 0;
   long long* trace = S.trace ? S.trace + (S.trace_rank < 0 ? (long long)rank * S.trace_cap : 0) : nullptr;
@@ -440,10 +605,20 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                      if (q.edge || z == 0 || z + 1 == q.tzn) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
                    });
     stamp();
-    ok &= team_sum_dev<1>(S, rank, red, acc1, rs);
+    // the first iteration's halo rings (u0, w0/D; no s yet) start loading as
+    // soon as the neighbours have published
+    float* ring_u = lring;
+    float* ring_w = lring + kResTZ * kRing;
+    float* ring_s = lring + 2 * kResTZ * kRing;
+    ok &= team_sum_dev<1>(S, rank, red, acc1, rs, res_neighbours(g, tile, S.team, S.xcd_order, [&]() {
+                            int tid_l = threadIdx.x, nxy_l = nxy;
+                            asm volatile("" : "+v"(tid_l));
+                            asm volatile("" : "+s"(nxy_l));
+                            ring_dma<G>(g, q, ring_u, ub[0], tid_l, nxy_l);
+                            ring_dma<G>(g, q, ring_w, wb[0], tid_l, nxy_l);
+                          }));
     stamp();
     double a_cg = gam / acc1[0], b_cg = 0.0;
-    float a_prev = 0.f;
     int cur = 0;
     while (ok) {
       if (it >= S.max_iter) { status |= kNoConv; break; }
@@ -455,21 +630,15 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       asm volatile("" : "+v"(col_l));
       const float a = (float)a_cg, b = (float)b_cg;
       const bool first = it == 0;
-      // the neighbours' published u, w/D, s/D on the tile's ring start
-      // streaming into LDS now and land while the registers are updated
+      // the neighbours' published u, w/D, s/D on the tile's ring are on their
+      // way to LDS already (started inside the last reduction); the values
+      // below and above the tile are loaded now and land while the registers
+      // are updated
       const float* uo = ub[cur];
       const float* wo = wb[cur];
       const float* so = sb[cur];
-      float* ring_u = lring;
-      float* ring_w = lring + kResTZ * kRing;
-      float* ring_s = lring + 2 * kResTZ * kRing;
-      // (the thread index is laundered so that the ring addressing is
-      // recomputed here rather than hoisted out of the loop into registers)
       int tid_l = threadIdx.x;
       asm volatile("" : "+v"(tid_l));
-      ring_dma<G>(g, q, ring_u, uo, tid_l, nxy_l);
-      ring_dma<G>(g, q, ring_w, wo, tid_l, nxy_l);
-      if (!first) ring_dma<G>(g, q, ring_s, so, tid_l, nxy_l);
       float zl[3] = {0.f, 0.f, 0.f}, zh[3] = {0.f, 0.f, 0.f};
       if (q.own && q.bot_z) {
         const int i = col_l + (T.z0 - 1) * nxy_l;
@@ -479,34 +648,34 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
         const int i = col_l + T.z1 * nxy_l;
         zh[0] = ld_dev(uo + i); zh[1] = ld_dev(wo + i); zh[2] = first ? 0.f : ld_dev(so + i);
       }
-      // elementwise updates: s = w + b s, p = u + b p, u -= a s in registers.
-      // x (in memory) is advanced every second iteration by both pending
-      // steps, x += a_prev p_prev + a p, which halves its traffic.
-      const bool xstep = (it & 1) != 0;
+      // elementwise updates: s = w + b s, p = u + b p, u -= a s in registers
+      // (x += a p follows plane by plane in the sweep, where its memory
+      // traffic hides behind the stencil's arithmetic). In the first
+      // iteration b = 0 and s = 0, and p holds the finite x0, so the same
+      // fused forms give s = w and p = u exactly.
 #pragma unroll
       for (int z = 0; z < TZ; ++z) {
-        const float s_ = first ? wr[z] : fmaf(b, sr[z], wr[z]);
-        const float p_ = first ? ur[z] : fmaf(b, pr[z], ur[z]);
-        if (xstep && q.own && z < q.tzn) {
-          float* xp = V.x + col_l + (T.z0 + z) * nxy_l;
-          const float xn = fmaf(a, p_, fmaf(a_prev, pr[z], *xp));
-          *xp = xn;
-          if (z == 0) xtop = xn;
-        }
+        const float s_ = fmaf(b, sr[z], wr[z]);
+        const float p_ = fmaf(b, pr[z], ur[z]);
         pr[z] = p_;
         sr[z] = s_;
         ur[z] = fmaf(-a, s_, ur[z]);
       }
-      a_prev = a;
       // halo values of the new u from the neighbours' published u, w/D, s/D
-      auto unew = [&](float u_, float w_, float s_) { return fmaf(-a, first ? w_ : fmaf(b, s_, w_), u_); };
+      // (first iteration: b = 0 and the s values are zeros)
+      auto unew = [&](float u_, float w_, float s_) { return fmaf(-a, fmaf(b, s_, w_), u_); };
       zlo[0] = unew(zl[0], zl[1], zl[2]);
       zhi[0] = unew(zh[0], zh[1], zh[2]);
       if (S.trace_detail) stamp();
       __builtin_amdgcn_s_waitcnt(0);        // the ring loads have reached LDS
       __syncthreads();
       // the ring's new u, in place
-      for (int e = tid_l; e < G::RING * q.tzn; e += kResBlock) ring_u[e] = unew(ring_u[e], ring_w[e], ring_s[e]);
+      // (every slot: slots past the tile's planes and outside the grid hold zeros)
+#pragma unroll
+      for (int e0 = 0; e0 < kResTZ * kRing; e0 += kResBlock) {
+        const int e = e0 + tid_l;
+        ring_u[e] = unew(ring_u[e], ring_w[e], ring_s[e]);
+      }
       __syncthreads();
       if (S.trace_detail) stamp();
       double acc[3] = {0.0, 0.0, 0.0};
@@ -517,8 +686,24 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       float* uo_n = ub[cur ^ 1];
       float* wo_n = wb[cur ^ 1];
       float* so_n = sb[cur ^ 1];
+      // x += a p of this iteration, plane by plane; each plane's x is loaded
+      // two planes ahead of its update (only this workgroup touches its x).
+      // x and the published faces go through buffer accesses: a lane offset
+      // and a uniform plane offset, lanes off the grid (or, for the faces,
+      // inside the tile) out of range.
+      constexpr int kXAhead = 2;
+      const __amdgpu_buffer_rsrc_t rx = vec_rsrc(V.x, g.ng);
+      const __amdgpu_buffer_rsrc_t ru = vec_rsrc(uo_n, g.ng), rw = vec_rsrc(wo_n, g.ng), rs_ = vec_rsrc(so_n, g.ng);
+      const unsigned vown = q.own ? 4u * (unsigned)col_l : kNoLane;
+      const unsigned vedge = q.own && q.edge ? 4u * (unsigned)col_l : kNoLane;
+      const int pbytes = 4 * nxy_l;
+      float xq[kXAhead + 1];
+#pragma unroll
+      for (int z = 0; z < kXAhead; ++z) xq[z] = z < q.tzn ? buf_ld(rx, vown, (T.z0 + z) * pbytes) : 0.f;
       plane_sweep<G, 1>(g, q, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
                      [&](int z, float* const* pl, const float* vzm, const float* vzp) {
+                       if (z + kXAhead < q.tzn)
+                         xq[(z + kXAhead) % (kXAhead + 1)] = buf_ld(rx, vown, (T.z0 + z + kXAhead) * pbytes);
                        const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                        const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                        wr[z] = w * rcp<float>(n.D);
@@ -526,16 +711,27 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                        acc[0] += rd * ud;
                        acc[1] += (double)w * ud;
                        acc[2] += rd * rd;
-                       if (q.edge || z == 0 || z + 1 == q.tzn) {
-                         const int i = col_l + (T.z0 + z) * nxy_l;
-                         st_dev(uo_n + i, ur[z]);
-                         st_dev(wo_n + i, wr[z]);
-                         st_dev(so_n + i, sr[z]);
-                       }
+                       const unsigned vf = (z == 0 || z + 1 == q.tzn) ? vown : vedge;
+                       const int so = (T.z0 + z) * pbytes;
+                       buf_st<kCpolSc1>(ru, vf, so, ur[z]);
+                       buf_st<kCpolSc1>(rw, vf, so, wr[z]);
+                       buf_st<kCpolSc1>(rs_, vf, so, sr[z]);
+                       const float xn = fmaf(a, pr[z], xq[z % (kXAhead + 1)]);
+                       buf_st(rx, vown, so, xn);
+                       if (z == 0) xtop = xn;
                      });
       stamp();
       if (S.trace_detail) stamp();
-      ok &= team_sum_dev<3>(S, rank, red, acc, rs);
+      // the next iteration's halo rings start loading as soon as the
+      // neighbours have published this sweep's faces
+      ok &= team_sum_dev<3>(S, rank, red, acc, rs, res_neighbours(g, tile, S.team, S.xcd_order, [&]() {
+                              int tid_r = threadIdx.x, nxy_r = nxy;
+                              asm volatile("" : "+v"(tid_r));
+                              asm volatile("" : "+s"(nxy_r));
+                              ring_dma<G>(g, q, ring_u, uo_n, tid_r, nxy_r);
+                              ring_dma<G>(g, q, ring_w, wo_n, tid_r, nxy_r);
+                              ring_dma<G>(g, q, ring_s, so_n, tid_r, nxy_r);
+                            }));
       stamp();
       ++it;
       cur ^= 1;
@@ -546,18 +742,9 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       a_cg = gn / (dn - b_cg * gn / a_cg);
       gam = gn;
     }
-    if ((it & 1) && q.own) {
-      // the last iteration's step a p is still pending
-#pragma unroll
-      for (int z = 0; z < TZ; ++z) {
-        if (z < q.tzn) {
-          float* xp = V.x + q.col + (T.z0 + z) * nxy;
-          const float xn = fmaf(a_prev, pr[z], *xp);
-          *xp = xn;
-          if (z == 0) xtop = xn;
-        }
-      }
-    }
+    // the halo loads started in the last reduction land before LDS is reused
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   }
   if (!(bb < INFINITY) || !(rr < INFINITY) || rr != rr) status |= kNonFinite;
   if (!ok) status |= kTimeout;

@@ -17,6 +17,7 @@
 // bit-identical whether it runs alone or among others.
 #include "nefty_heat.h"
 #include "nh_kernels.hpp"
+#include "nh_policy.h"
 #include "nh_resident.hpp"
 
 #include <hip/hip_runtime.h>
@@ -74,12 +75,20 @@ typedef __attribute__((address_space(4))) const JobRun CJobRun;
 
 constexpr int kGuessPeriod = 32;
 
+// The loop state of a slice, kept in LDS between steps so that none of it is
+// live in registers through the (inlined) step: thread 0 writes it after a
+// step, and every thread reads it back after a barrier.
+struct SliceState {
+  long long t0;
+  long long iters;
+  unsigned long long ep;
+  int n, steps, status;
+  int pc[3];
+};
+
 template <typename StepF>
-__device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* prog, StepF step) {
-  const long long t0 = wall_clock64();
+__device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* prog, SliceState* ss, StepF step) {
   const bool fwd = J.mode == kForward;
-  int n = J.n0, steps = 0, status = 0;
-  long long iters = 0;
   // Adaptive initial guess: in each period of kGuessPeriod steps of a sweep
   // the first step starts from the previous state, the second from the
   // extrapolation, the rest from whichever needed fewer iterations. j is a
@@ -87,21 +96,27 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
   // come from the per-step record, later ones from this loop.
   auto pos = [&](int nn) { return fwd ? nn - 1 : J.nsteps - nn; };
   auto slot_of = [&](int jj) { return fwd ? jj : 2 * J.nsteps - 1 - jj; };
-  int pc[3] = {-1, -1, -1};
-  {
-    const int j0 = pos(n), base = j0 - j0 % kGuessPeriod;
-    for (int d = 0; d < 3; ++d)
-      if (base + d < j0) pc[d] = J.it_out[slot_of(base + d)];
+  if (threadIdx.x == 0) {
+    ss->t0 = wall_clock64();
+    ss->iters = 0;
+    ss->n = J.n0;
+    ss->steps = 0;
+    ss->status = 0;
+    // one running epoch through the slice: each step starts from the epoch of
+    // its predecessor's last team reduction, so epochs stay unique within the
+    // launch and consecutive reductions alternate between the slot banks
+    ss->ep = J.S.epoch_base;
+    const int j0 = pos(J.n0), base = j0 - j0 % kGuessPeriod;
+    for (int d = 0; d < 3; ++d) ss->pc[d] = base + d < j0 ? J.it_out[slot_of(base + d)] : -1;
   }
+  __syncthreads();
   const StepArgs<float>& S = (const StepArgs<float>&)J.S;
-  const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
-  // one running epoch through the slice: each step starts from the epoch of
-  // its predecessor's last team reduction, so epochs stay unique within the
-  // launch and consecutive reductions alternate between the slot banks
-  unsigned long long ep = J.S.epoch_base;
   while (true) {
+    const int n = ss->n;
+    const int k = pos(n) % kGuessPeriod;
+    const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
     StepVar<float> V;
-    V.epoch_base = ep;
+    V.epoch_base = ss->ep;
     V.out_iters = nullptr;                  // per-step outputs are written below
     V.out_relres = nullptr;
     V.out_status = nullptr;
@@ -127,46 +142,54 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
     }
     // initial guess: probes of orders 0, 1, 2 open each period, then the
     // order whose probe needed the fewest iterations (ties: the higher)
-    const int k = pos(n) % kGuessPeriod;
-    if (k == 0) pc[0] = pc[1] = pc[2] = -1;
-    V.xprev = h[0];
-    V.xprev2 = h[1];
-    V.xprev3 = h[2];
     int order = 2;
     if (k < 3) {
       order = k;
-    } else if (pc[0] >= 0 && pc[1] >= 0 && pc[2] >= 0) {
-      int best = pc[2];
-      if (pc[1] < best) { order = 1; best = pc[1]; }
-      if (pc[0] < best) order = 0;
+    } else {
+      const int p0 = ss->pc[0], p1 = ss->pc[1], p2 = ss->pc[2];
+      if (p0 >= 0 && p1 >= 0 && p2 >= 0) {
+        int best = p2;
+        if (p1 < best) { order = 1; best = p1; }
+        if (p0 < best) order = 0;
+      }
     }
+    V.xprev = h[0];
+    V.xprev2 = h[1];
+    V.xprev3 = h[2];
     V.gmode = order;
     V.gi = nullptr;
     V.gp[0] = V.gp[1] = V.gp[2] = 0;
     const StepResult r = step(S, V);
-    ep = r.epoch_end;
-    if (k < 3) pc[k] = r.iters;
-    if (m.y == 0 && threadIdx.x == 0) {
-      const int slot = (fwd ? 0 : J.nsteps) + n - 1;
-      J.it_out[slot] = r.iters;
-      J.rel_out[slot] = r.relres;
-      J.st_out[slot] = r.status;
+    __syncthreads();                        // every thread has read the state of this step
+    if (threadIdx.x == 0) {
+      if (m.y == 0) {
+        const int slot = (fwd ? 0 : J.nsteps) + n - 1;
+        J.it_out[slot] = r.iters;
+        J.rel_out[slot] = r.relres;
+        J.st_out[slot] = r.status;
+      }
+      ss->ep = r.epoch_end;
+      if (k == 0) ss->pc[0] = ss->pc[1] = ss->pc[2] = -1;
+      if (k < 3) ss->pc[k] = r.iters;
+      ss->iters += r.iters;
+      ss->status |= r.status;
+      ss->steps += 1;
+      ss->n = n + (fwd ? 1 : -1);
     }
-    iters += r.iters;
-    status |= r.status;
-    ++steps;
+    __syncthreads();
     const bool last = fwd ? n == J.nsteps : n == 1;
-    n += fwd ? 1 : -1;
+    const long long iters = ss->iters;
+    const int steps = ss->steps, status = ss->status;
     if (last || (status & (kNonFinite | kTimeout)) || steps >= kMaxSliceSteps) break;
     // the next step is expected to take about as many iterations as this one
     if ((iters + steps + r.iters + 1) * J.cost > J.budget) break;
   }
   if (m.y == 0 && threadIdx.x == 0) {
     JobProg p;
-    p.steps = steps;
-    p.status = status;
-    p.iters = iters;
-    p.t0 = t0;
+    p.steps = ss->steps;
+    p.status = ss->status;
+    p.iters = ss->iters;
+    p.t0 = ss->t0;
     p.t1 = wall_clock64();
     prog[m.x] = p;
   }
@@ -177,12 +200,13 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
 __global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const JobRun* jobs, const int2* map,
                                                                           JobProg* prog) {
   __shared__ Smem<float> sh;
+  __shared__ SliceState ss;
   const int2 m = map[blockIdx.x];
   if (m.x < 0) return;
   // The job table is not written during the launch: reading it through the
   // constant address space makes its loads scalar and invariant.
   const CJobRun& J = *(const CJobRun*)(jobs + m.x);
-  run_slice(J, m, prog, [&](const StepArgs<float>& S, const StepVar<float>& V) {
+  run_slice(J, m, prog, &ss, [&](const StepArgs<float>& S, const StepVar<float>& V) {
     return run_step<float>(S, V, m.y, sh);
   });
 }
@@ -192,10 +216,11 @@ __global__ void __launch_bounds__(Cfg<float>::kBlock, 1) batch_run_kernel(const 
 __global__ void __launch_bounds__(kResBlock, 1) batch_resident_kernel(const JobRun* jobs, const int2* map,
                                                                        JobProg* prog) {
   extern __shared__ __align__(16) unsigned char dsm[];
+  __shared__ SliceState ss;
   const int2 m = map[blockIdx.x];
   if (m.x < 0) return;
   const CJobRun& J = *(const CJobRun*)(jobs + m.x);
-  run_slice(J, m, prog, [&](const StepArgs<float>& S, const StepVar<float>& V) {
+  run_slice(J, m, prog, &ss, [&](const StepArgs<float>& S, const StepVar<float>& V) {
     return resident_step<64>(S, V, m.y, dsm, true);
   });
 }
@@ -232,13 +257,15 @@ __global__ void mse_finish_kernel(const double* partial, int n, double inv_m, do
 
 namespace {
 
-constexpr int kMseBlocks = 64;
-constexpr long long kVoxelsPerBlock = 32768;
+constexpr int kMseBlocks = nhp::kMseBlocks;
+constexpr long long kVoxelsPerBlock = nhp::kVoxelsPerBlock;
 constexpr long long kReductionCost = 8192;   // a team reduction, in voxel units of work
 constexpr long long kResCells = 16384;        // cells of a full resident tile
 constexpr long long kResFixedCost = 24576;    // per resident iteration: reduction and face exchange
-constexpr int kMaxIterLimit = 30000;          // reductions per step stay below 2^16
 constexpr int kBlock = nh::Cfg<float>::kBlock;
+static_assert(nhp::kBlock == kBlock && nhp::kResBlock == nh::kResBlock && nhp::kResTZ == nh::kResTZ &&
+                  nhp::kSlotBytes == sizeof(nh::Slot) && sizeof(nh::TSlot) == sizeof(nh::Slot),
+              "the host-side policy must size jobs as the kernels tile them");
 
 double now_s() {
   static const auto t0 = std::chrono::steady_clock::now();
@@ -247,60 +274,15 @@ double now_s() {
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Tiling of one job: x-y tiles as in the single-problem path, split in z so
-// that there are about ng / kVoxelsPerBlock tiles; one workgroup per tile up
-// to `cap` workgroups.
-void job_geom(int nx, int ny, int nz, int cap, nh::Geom& g, int& team) {
+// The kernels' tiling of a job from the host-side policy's.
+void job_geom_of(int nx, int ny, int nz, const nhp::JobGeom& p, nh::Geom& g, int& team) {
   g = nh::Geom{};
   g.nx = nx; g.ny = ny; g.nz = nz;
   g.nxy = (long long)nx * ny;
   g.ng = g.nxy * nz;
-  g.TX = nx > 32 ? 64 : (nx > 16 ? 32 : 16);
-  g.TY = kBlock / g.TX;
-  g.txs = g.TX == 64 ? 6 : (g.TX == 32 ? 5 : 4);
-  g.ntx = (nx + g.TX - 1) / g.TX;
-  g.nty = (ny + g.TY - 1) / g.TY;
-  const long long xy = (long long)g.ntx * g.nty;
-  const long long want = std::max<long long>(1, (g.ng + kVoxelsPerBlock - 1) / kVoxelsPerBlock);
-  const long long want_ntz = std::max<long long>(1, (want + xy - 1) / xy);
-  int tz = (int)((nz + want_ntz - 1) / want_ntz);
-  if (tz < 4) tz = std::min(4, nz);
-  g.TZ = tz;
-  g.ntz = (nz + tz - 1) / tz;
-  g.ntiles = (int)(xy * g.ntz);
-  team = std::max(1, std::min(g.ntiles, cap));
-}
-
-// Tiling of one job for the register-resident kernel: tiles of 64 x 8
-// columns and at most 32 cells in z, one workgroup per tile.
-void job_geom_res(int nx, int ny, int nz, nh::Geom& g, int& team) {
-  g = nh::Geom{};
-  g.nx = nx; g.ny = ny; g.nz = nz;
-  g.nxy = (long long)nx * ny;
-  g.ng = g.nxy * nz;
-  g.TX = 64;
-  g.TY = nh::kResBlock / 64;
-  g.txs = 6;
-  g.ntx = (nx + g.TX - 1) / g.TX;
-  g.nty = (ny + g.TY - 1) / g.TY;
-  g.ntz = (nz + nh::kResTZ - 1) / nh::kResTZ;
-  g.TZ = (nz + g.ntz - 1) / g.ntz;
-  g.ntiles = (int)((long long)g.ntx * g.nty * g.ntz);
-  team = g.ntiles;
-}
-
-size_t job_bytes(int nx, int ny, int nz, int nsteps, int team) {
-  const size_t ng = (size_t)nx * ny * nz, nxy = (size_t)nx * ny, N = (size_t)nsteps;
-  size_t b = 0;
-  b += align256(4 * ng) * 12;                               // alpha, z, p, u1, w0, w1, s0, s1, mu[4]
-  b += align256(4 * ng * N);                                // trajectory T^1..T^N
-  b += align256(8 * ng);                                    // dL/dalpha (FP64)
-  b += align256(4 * nxy) + 3 * align256(4 * nxy * N);       // q_xy, target, S, dL/dS
-  b += align256(4 * N);                                     // source scale per step
-  b += 2 * align256(4 * 2 * N) + align256(8 * 2 * N);       // per-step iterations, status, residuals
-  b += align256(sizeof(nh::Slot) * (2 * (size_t)team + 2)); // team reduction slots (2 banks)
-  b += align256(8 * kMseBlocks) + 256;                      // MSE partials, loss
-  return b;
+  g.TX = p.TX; g.TY = p.TY; g.TZ = p.TZ; g.txs = p.txs;
+  g.ntx = p.ntx; g.nty = p.nty; g.ntz = p.ntz; g.ntiles = p.ntiles;
+  team = p.team;
 }
 
 struct SJob {
@@ -525,91 +507,6 @@ nh_status ensure_tables(nh_server* s, size_t njobs) {
 
 extern "C" {
 
-int nh_serve_job_team(int nx, int ny, int nz, int max_blocks, int resident) {
-  if (nx < 1 || ny < 1 || nz < 1 || max_blocks < 1) return 0;
-  nh::Geom g;
-  int team = 0;
-  if (resident) {
-    job_geom_res(nx, ny, nz, g, team);
-    return team <= max_blocks ? team : 0;
-  }
-  job_geom(nx, ny, nz, std::max(1, max_blocks / 2), g, team);
-  return team;
-}
-
-size_t nh_serve_job_bytes(int nx, int ny, int nz, int nsteps, int team_blocks) {
-  if (nx < 1 || ny < 1 || nz < 1 || nsteps < 1 || team_blocks < 1) return 0;
-  return job_bytes(nx, ny, nz, nsteps, team_blocks);
-}
-
-int nh_serve_admit_select(const size_t* qbytes, const int* qteams, const double* qdur, int n_queued,
-                          const size_t* abytes, const int* ateams, const double* arem, int n_active,
-                          double budget_bytes, int max_blocks, int backfill, int* selected) {
-  if (!qbytes || !qteams || !selected || n_queued < 1) return 0;
-  if (n_active > 0 && (!abytes || !ateams || !arem)) return 0;
-  if (backfill && !qdur) return 0;
-  struct Act {
-    double rem;
-    size_t bytes;
-    int team;
-  };
-  std::vector<Act> act;
-  double used_m = 0.0;
-  long long used_b = 0;
-  for (int i = 0; i < n_active; ++i) {
-    act.push_back({arem[i], abytes[i], ateams[i]});
-    used_m += (double)abytes[i];
-    used_b += ateams[i];
-  }
-  int n = 0;
-  bool reserved = false;
-  double shadow = 0.0, extra_m = 0.0;
-  long long extra_b = 0;
-  for (int i = 0; i < n_queued; ++i) {
-    const bool fits = used_m + (double)qbytes[i] <= budget_bytes && used_b + qteams[i] <= max_blocks;
-    if (!reserved) {
-      if (fits) {
-        used_m += (double)qbytes[i];
-        used_b += qteams[i];
-        act.push_back({backfill ? qdur[i] : 0.0, qbytes[i], qteams[i]});
-        selected[n++] = i;
-        continue;
-      }
-      if (!backfill) break;
-      // the first job that does not fit holds a reservation: the shadow time
-      // is when enough running jobs have ended for it to fit, and the extra
-      // room is what it leaves free then
-      reserved = true;
-      std::sort(act.begin(), act.end(), [](const Act& x, const Act& y) { return x.rem < y.rem; });
-      double free_m = budget_bytes - used_m;
-      long long free_b = (long long)max_blocks - used_b;
-      for (const Act& x : act) {
-        if (free_m >= (double)qbytes[i] && free_b >= qteams[i]) break;
-        free_m += (double)x.bytes;
-        free_b += x.team;
-        shadow = x.rem;
-      }
-      extra_m = free_m - (double)qbytes[i];
-      extra_b = free_b - qteams[i];
-      continue;
-    }
-    // behind the reservation: jobs that fit now and either end before the
-    // shadow time or use only the extra room
-    if (!fits) continue;
-    const bool early = qdur[i] <= shadow;
-    const bool spare = qteams[i] <= extra_b && (double)qbytes[i] <= extra_m;
-    if (!early && !spare) continue;
-    if (!early) {
-      extra_b -= qteams[i];
-      extra_m -= (double)qbytes[i];
-    }
-    used_m += (double)qbytes[i];
-    used_b += qteams[i];
-    selected[n++] = i;
-  }
-  return n;
-}
-
 nh_status nh_server_create(nh_server** out, int hip_device, void* hip_stream, double hbm_budget_bytes,
                            int max_blocks, int resident) {
   if (!out) return NH_EINVAL;
@@ -678,18 +575,12 @@ nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, doubl
                            const float* target, long long* job_id) {
   if (!s) return NH_EINVAL;
   if (!job_id || !alpha || !q_xy || !q_t || !target) return sfail(s, NH_EINVAL, "null pointer argument");
-  if (nx < 1 || ny < 1 || nz < 1 || nsteps < 1 || !(dt > 0) || !std::isfinite(dt) || !(h > 0) ||
-      !std::isfinite(h) || !(rtol > 0) || !(rtol < 1) || max_iter < 1 || max_iter > kMaxIterLimit)
-    return sfail(s, NH_EINVAL, "bad job parameters");
+  if (!nhp::job_params_ok(nx, ny, nz, h, dt, nsteps, rtol, max_iter)) return sfail(s, NH_EINVAL, "bad job parameters");
   const size_t ng = (size_t)nx * ny * nz, nxy = (size_t)nx * ny, N = (size_t)nsteps;
-  for (size_t i = 0; i < ng; ++i)
-    if (!(alpha[i] > 0.f) || !std::isfinite(alpha[i])) return sfail(s, NH_EINVAL, "alpha must be finite and > 0");
-  for (size_t i = 0; i < nxy; ++i)
-    if (!std::isfinite(q_xy[i])) return sfail(s, NH_EINVAL, "q_xy holds a non-finite value");
-  for (size_t i = 0; i < N; ++i)
-    if (!std::isfinite(q_t[i])) return sfail(s, NH_EINVAL, "q_t holds a non-finite value");
-  for (size_t i = 0; i < nxy * N; ++i)
-    if (!std::isfinite(target[i])) return sfail(s, NH_EINVAL, "target holds a non-finite value");
+  if (nhp::first_bad(alpha, ng, true) >= 0) return sfail(s, NH_EINVAL, "alpha must be finite and > 0");
+  if (nhp::first_bad(q_xy, nxy, false) >= 0) return sfail(s, NH_EINVAL, "q_xy holds a non-finite value");
+  if (nhp::first_bad(q_t, N, false) >= 0) return sfail(s, NH_EINVAL, "q_t holds a non-finite value");
+  if (nhp::first_bad(target, nxy * N, false) >= 0) return sfail(s, NH_EINVAL, "target holds a non-finite value");
   auto j = std::make_unique<SJob>();
   j->nx = nx; j->ny = ny; j->nz = nz;
   j->h = h;
@@ -699,15 +590,15 @@ nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, doubl
   j->max_iter = max_iter;
   int team = 0;
   if (s->resident) {
-    job_geom_res(nx, ny, nz, j->g, team);
+    job_geom_of(nx, ny, nz, nhp::job_geom_res(nx, ny, nz), j->g, team);
     if (team > s->max_blocks) return sfail(s, NH_EINVAL, "job needs more tiles than fit on the device");
     j->cost = ((long long)ng + team - 1) / team + kResFixedCost;
   } else {
-    job_geom(nx, ny, nz, std::max(1, s->max_blocks / 2), j->g, team);
+    job_geom_of(nx, ny, nz, nhp::job_geom(nx, ny, nz, std::max(1, s->max_blocks / 2)), j->g, team);
     j->cost = ((long long)ng + team - 1) / team + (team > 1 ? kReductionCost : 0);
   }
   j->team = team;
-  j->bytes = job_bytes(nx, ny, nz, nsteps, team);
+  j->bytes = nhp::job_bytes(nx, ny, nz, nsteps, team);
   if ((double)j->bytes > s->budget) return sfail(s, NH_ENOMEM, "job larger than the HBM budget");
   j->h_alpha.assign(alpha, alpha + ng);
   j->h_qxy.assign(q_xy, q_xy + nxy);
@@ -778,6 +669,14 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
     nh_status ts = ensure_tables(s, na);
     if (ts != NH_OK) return ts;
     const unsigned long long base = (++s->launch_ctr) << 24;
+    if (s->resident && (s->launch_ctr & 0xFF) == 0) {
+      // the tagged reduction words repeat their tags every 256 launches:
+      // zero every admitted job's slots before a new round starts
+      for (size_t k = 0; k < na; ++k) {
+        const SJob* j = s->active[k];
+        SV_HIP(s, hipMemsetAsync(j->slots, 0, sizeof(nh::TSlot) * (2 * (size_t)j->team + 2), s->stream));
+      }
+    }
     int nb = 0;
     for (size_t k = 0; k < na; ++k) {
       const SJob* j = s->active[k];

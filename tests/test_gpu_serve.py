@@ -206,7 +206,12 @@ def test_stream_driver_and_sequential_baseline_agree(jobs):
 # The oracle checks take short horizons for the two large grids (its FP64 CG
 # to 1e-13 costs seconds per step there); the 192x192x48 job of the long mix
 # runs 100 steps and is checked alone against the mix and against the
-# single-problem solver.
+# single-problem solver. The measured series is half the surface series of
+# the job's target field: over the first steps the boxes of the target field
+# barely reach the surface, so against the target's own series the misfit
+# S - target would be a small difference of nearly equal series, and the
+# relative error of the loss and of dL/dalpha an amplified measure of the
+# surface error.
 C5_JOBS = [(192, 192, 48, 12, 51), (128, 128, 48, 12, 52), (32, 32, 16, 100, 53)]
 C5_RTOL = 1e-6
 
@@ -224,7 +229,7 @@ def c5_jobs():
         src = orc.source_series(w.q_xy, w.q_t)
         say(f"oracle for {w.name}, {w.nsteps} steps")
         St, _, _ = orc.forward(w.alpha_target, src, w.dt, rtol=1e-10, keep_states=False)
-        target = St.astype(np.float32)
+        target = (0.5 * St).astype(np.float32)
         S, T_all, _ = orc.forward(w.alpha, src, w.dt, rtol=1e-13)
         L, gs = orc.mse_loss_and_grad(S, target)
         G, _, _, _ = orc.adjoint(w.alpha, T_all, gs, w.dt, rtol=1e-13)
@@ -288,7 +293,7 @@ def test_long_serving_job_alone_equals_mix():
     sv = Solver(big.nx, big.ny, big.nz, rtol=C5_RTOL)
     a = torch.from_numpy(big.alpha_target).cuda()
     q = torch.from_numpy(big.q_xy).cuda()
-    target = sv.forward(a, q, big.q_t, big.dt, big.nsteps).cpu().numpy()
+    target = 0.5 * sv.forward(a, q, big.q_t, big.dt, big.nsteps).cpu().numpy()
     sa = sv.forward(torch.from_numpy(big.alpha).cuda(), q, big.q_t, big.dt, big.nsteps)
     d = sa.double() - torch.from_numpy(target).cuda().double()
     L_single = float((d * d).sum() / d.numel())

@@ -6,6 +6,7 @@ budget and the co-resident workgroup limit. These tests call the library's
 host-only helpers through the C ABI.
 """
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -16,7 +17,22 @@ from paper_2603_11045_amd import workloads as wl
 
 @pytest.fixture(scope="module")
 def lib():
-    return _lib.load()
+    # NH_POLICY_LIB names a standalone build of the host-side policy
+    # (csrc/nh_policy.cpp; the sanitizer tier's instrumented build) to test
+    # instead of the library
+    path = os.environ.get("NH_POLICY_LIB")
+    if not path:
+        return _lib.load()
+    pol = ctypes.CDLL(path)
+    ip, szp, dp = ctypes.c_int, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)
+    pol.nh_serve_job_team.argtypes = [ip, ip, ip, ip, ip]
+    pol.nh_serve_job_team.restype = ip
+    pol.nh_serve_job_bytes.argtypes = [ip, ip, ip, ip, ip]
+    pol.nh_serve_job_bytes.restype = ctypes.c_size_t
+    pol.nh_serve_admit_select.argtypes = [szp, ctypes.POINTER(ip), dp, ip, szp, ctypes.POINTER(ip), dp, ip,
+                                          ctypes.c_double, ip, ip, ctypes.POINTER(ip)]
+    pol.nh_serve_admit_select.restype = ip
+    return pol
 
 
 def select(lib, qbytes, qteams, budget, max_blocks, qdur=None, active=(), backfill=0):
