@@ -140,7 +140,23 @@ template <> __device__ __forceinline__ double rcp<double>(double v) { return 1.0
 // L2 write-back finds little dirty data. (Non-temporal stores were measured
 // slower: they bypass the last-level cache that the next sweep reads from.)
 template <typename T>
-__device__ __forceinline__ void st_out(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ void st_out(T* p, T v) {
+  __hip_atomic_store((__attribute__((address_space(1))) T*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A product and a sum rounded on their own, never fused into a multiply-add
+// (where two kernels must produce the same bits, the contraction must not
+// depend on how each compiles).
+template <typename R>
+__device__ __forceinline__ R mul_rn(R a, R b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+template <typename R>
+__device__ __forceinline__ R add_rn(R a, R b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
 
 // dt * c_f = s * a*b/(a+b) with s = 2 dt / h^2 (Prop. 1); b = 0 outside the grid gives 0.
 template <typename R>
@@ -225,6 +241,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[kNumRed
 template <typename R, int NV, int BLOCK = Cfg<R>::kBlock>
 __device__ __forceinline__ bool team_sum(const StepArgs<R>& S, int rank, unsigned long long& epoch,
                                          double (&v)[NV], Smem<R>& sh) {
+  // every wave's sweep stores (device-coherent) complete before the workgroup
+  // publishes its slot: the slot's release orders only the wave that writes it
+  __builtin_amdgcn_s_waitcnt(0);
   block_sum<NV, BLOCK / 64>(v, sh.red[0]);
   if (S.team == 1) {
     __syncthreads();                        // red[0] is free again
@@ -338,20 +357,48 @@ struct Pt {
   R v[NV][7];
 };
 
-// March one tile along z. Op supplies: NV staged vectors (load(k, i)), NO
-// operands of type OT read only at the cell itself (own(k, i), not staged),
-// alpha, and point(P, o, i, kz). Loads run kPrefetch planes ahead of use
-// (register queues), so each thread keeps several planes of loads in flight
-// across the two workgroup barriers of a plane. (Two planes measured the
-// same within 0.5% on the FP32 workloads.)
+// Buffer loads of one z plane of a vector. The resource covers the plane
+// (base p + zp nxy, nxy elements); a lane whose byte offset is kOffLane, a
+// null vector and a plane outside the range asked for all read 0, so the
+// plane loads need neither branches nor zero fills.
+constexpr unsigned kOffLane = 0x80000000u;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* p, long long zp, long long nxy, bool valid) {
+  valid = valid && p != nullptr;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p) + (valid ? zp * nxy : 0), 0,
+                                           valid ? (int)(nxy * (long long)sizeof(T)) : 0, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T plane_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float plane_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double plane_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+
+// March one tile along z. Op supplies: NL vectors loaded at the staged cells
+// (raw_ptr(k); null reads 0), combined into the NV staged vectors by
+// stage(raw, v) when a plane is staged; NO operands of type OT read at the
+// cell itself (own_ptr(k)); alpha; and point(P, rc, o, i, kz), which also
+// receives the cell's raw values rc. Loads are issued kPrefetch planes ahead
+// of their use; all queues are rings of Q plane slots with compile-time slot
+// numbers (the z loop is unrolled Q times), so no register moves, which would
+// wait for loads in flight, rotate them. Arithmetic on loaded values happens
+// in stage and point, once the data is needed.
 constexpr int kPrefetch = 3;
 
 template <typename R, typename Op>
 __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op, Smem<R>& sh) {
   constexpr int NV = Op::NV;
-  constexpr int NO = Op::NO;
+  constexpr int NL = Op::NL;
+  constexpr int NO = Op::NO > 0 ? Op::NO : 1;
   constexpr int PD = kPrefetch;
-  constexpr int QS = PD + 2;                // staged own column: planes z-1 .. z+PD
+  constexpr int Q = PD + 2;                 // plane slots: z-1 .. z+PD
   using OT = typename Op::OT;
   const int tid = threadIdx.x;
   const int TX = g.TX, TY = g.TY, PW = TX + 2;
@@ -384,141 +431,92 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
       if (hin) hcol = (long long)hx + (long long)g.nx * hy;
     }
   }
+  const unsigned vcol = ld ? (unsigned)lcol * (unsigned)sizeof(R) : kOffLane;
+  const unsigned vhalo = hin ? (unsigned)hcol * (unsigned)sizeof(R) : kOffLane;
+  const unsigned vown = own ? (unsigned)col * (unsigned)sizeof(OT) : kOffLane;
 
-  // register queues; index 0 is the oldest plane
-  R qa[QS], qv[QS][NV];                     // own column, planes z-1 .. z+PD
-  R ha[PD + 1], hv[PD + 1][NV];             // halo cell, planes z .. z+PD
-  OT qo[PD + 1][NO];                        // own-only operands, planes z .. z+PD
+  // rings; plane zp sits in slot (zp - (z0 - 1)) mod Q
+  R qa[Q], ql[Q][NL];                       // staged column: alpha, raw values
+  R qv[Q][NV];                              // staged column: staged vectors
+  R ha[Q], hl[Q][NL];                       // halo cell: alpha, raw values
+  OT qo[Q][NO];                             // own operands
+  // staged column of plane zp (inside the grid)
+  auto load_col = [&](int s, int zp) {
+    const bool v = zp >= 0 && zp < g.nz;
+    qa[s] = plane_ld<R>(plane_rsrc(op.alpha, zp, g.nxy, v), vcol);
 #pragma unroll
-  for (int j = 0; j < QS; ++j) {
-    qa[j] = 0;
+    for (int k = 0; k < NL; ++k) ql[s][k] = plane_ld<R>(plane_rsrc(op.raw_ptr(k), zp, g.nxy, v), vcol);
+  };
+  // own operands and halo cell of plane zp (inside the tile)
+  auto load_cell = [&](int s, int zp) {
+    const bool v = zp < T.z1;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) qv[j][k] = 0;
-  }
+    for (int k = 0; k < NO; ++k)
+      qo[s][k] = k < Op::NO ? plane_ld<OT>(plane_rsrc(op.own_ptr(k), zp, g.nxy, v), vown) : OT(0);
+    const __amdgpu_buffer_rsrc_t ra = plane_rsrc(op.alpha, zp, g.nxy, v);
+    ha[s] = plane_ld<R>(ra, vhalo);
 #pragma unroll
-  for (int j = 0; j <= PD; ++j) {
-    ha[j] = 0;
+    for (int k = 0; k < NL; ++k) hl[s][k] = plane_ld<R>(plane_rsrc(op.raw_ptr(k), zp, g.nxy, v), vhalo);
+  };
+  // fill: staged column z0-1 .. z0+PD-1, own operands and halo z0 .. z0+PD-1
 #pragma unroll
-    for (int k = 0; k < NV; ++k) hv[j][k] = 0;
+  for (int j = 0; j < Q - 1; ++j) load_col(j, T.z0 - 1 + j);
 #pragma unroll
-    for (int k = 0; k < NO; ++k) qo[j][k] = 0;
-  }
-  // fill: own planes z0-1 .. z0+PD-1, own-only and halo planes z0 .. z0+PD-1
+  for (int j = 0; j < PD; ++j) load_cell(j + 1, T.z0 + j);
+  op.stage(ql[0], qv[0]);
+  op.stage(ql[1], qv[1]);
+
+  for (int zb = T.z0; zb < T.z1; zb += Q) {
 #pragma unroll
-  for (int j = 0; j < QS - 1; ++j) {
-    const int z = T.z0 - 1 + j;
-    if (ld && z >= 0 && z < g.nz) {
-      const long long i = lcol + (long long)z * g.nxy;
-      qa[j] = op.alpha[i];
+    for (int u = 0; u < Q; ++u) {
+      const int z = zb + u;
+      if (z >= T.z1) break;
+      const int sm = u % Q, s0 = (u + 1) % Q, sp = (u + 2) % Q, sn = (u + Q - 1) % Q;
+      // issue the loads of plane z+PD into the slot plane z-2 has left
+      load_col(sn, z + PD);
+      load_cell(sn, z + PD);
+
+      // planes alternate between two LDS buffers, so one barrier per plane
+      // suffices: a buffer is written again two planes later, after the next
+      // plane's barrier, which every wave passes only once it has finished
+      // reading this plane
+      const int bf = (z - T.z0) & 1;
+      R* la = sh.a[bf];
+      R (*lv)[kMaxPlane] = sh.v[bf];
+      la[oslot] = qa[s0];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) qv[j][k] = op.load(k, i);
-    }
-  }
+      for (int k = 0; k < NV; ++k) lv[k][oslot] = qv[s0][k];
+      if (hslot >= 0) {
+        R hv[NV];
+        op.stage(hl[s0], hv);
+        la[hslot] = ha[s0];
 #pragma unroll
-  for (int j = 0; j < PD; ++j) {
-    const int z = T.z0 + j;
-    if (z < T.z1) {
-      const long long io = col + (long long)z * g.nxy;
+        for (int k = 0; k < NV; ++k) lv[k][hslot] = hv[k];
+      }
+      op.stage(ql[sp], qv[sp]);             // plane z+1: the +z neighbour now, staged next
+      __syncthreads();
+
       if (own) {
+        Pt<R, NV> P;
+        P.a[0] = qa[s0];
+        P.a[1] = la[oslot - 1];
+        P.a[2] = la[oslot + 1];
+        P.a[3] = la[oslot - PW];
+        P.a[4] = la[oslot + PW];
+        P.a[5] = qa[sm];
+        P.a[6] = qa[sp];
 #pragma unroll
-        for (int k = 0; k < NO; ++k) qo[j][k] = op.own(k, io);
-      }
-      if (hin) {
-        const long long ih = hcol + (long long)z * g.nxy;
-        ha[j] = op.alpha[ih];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) hv[j][k] = op.load(k, ih);
-      }
-    }
-  }
-
-  for (int z = T.z0; z < T.z1; ++z) {
-    // issue the loads of plane z+PD (own staged column, own-only operands, halo)
-    {
-      const int zs = z + PD;
-      qa[QS - 1] = 0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) qv[QS - 1][k] = 0;
-      if (ld && zs < g.nz) {
-        const long long i = lcol + (long long)zs * g.nxy;
-        qa[QS - 1] = op.alpha[i];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) qv[QS - 1][k] = op.load(k, i);
-      }
-      const int zh = z + PD;
-      ha[PD] = 0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) hv[PD][k] = 0;
-#pragma unroll
-      for (int k = 0; k < NO; ++k) qo[PD][k] = 0;
-      if (zh < T.z1) {
-        if (own) {
-          const long long i = col + (long long)zh * g.nxy;
-#pragma unroll
-          for (int k = 0; k < NO; ++k) qo[PD][k] = op.own(k, i);
+        for (int k = 0; k < NV; ++k) {
+          P.v[k][0] = qv[s0][k];
+          P.v[k][1] = lv[k][oslot - 1];
+          P.v[k][2] = lv[k][oslot + 1];
+          P.v[k][3] = lv[k][oslot - PW];
+          P.v[k][4] = lv[k][oslot + PW];
+          P.v[k][5] = qv[sm][k];
+          P.v[k][6] = qv[sp][k];
         }
-        if (hin) {
-          const long long i = hcol + (long long)zh * g.nxy;
-          ha[PD] = op.alpha[i];
-#pragma unroll
-          for (int k = 0; k < NV; ++k) hv[PD][k] = op.load(k, i);
-        }
+        op.point(P, ql[s0], qo[s0], col + (long long)z * g.nxy, z);
       }
-    }
-
-    // planes alternate between two LDS buffers, so one barrier per plane
-    // suffices: a buffer is written again two planes later, after the next
-    // plane's barrier, which every wave passes only once it has finished
-    // reading this plane
-    const int bf = (z - T.z0) & 1;
-    R* la = sh.a[bf];
-    R (*lv)[kMaxPlane] = sh.v[bf];
-    la[oslot] = qa[1];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) lv[k][oslot] = qv[1][k];
-    if (hslot >= 0) {
-      la[hslot] = ha[0];
-#pragma unroll
-      for (int k = 0; k < NV; ++k) lv[k][hslot] = hv[0][k];
-    }
-    __syncthreads();
-
-    if (own) {
-      Pt<R, NV> P;
-      P.a[0] = qa[1];
-      P.a[1] = la[oslot - 1];
-      P.a[2] = la[oslot + 1];
-      P.a[3] = la[oslot - PW];
-      P.a[4] = la[oslot + PW];
-      P.a[5] = qa[0];
-      P.a[6] = qa[2];
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        P.v[k][0] = qv[1][k];
-        P.v[k][1] = lv[k][oslot - 1];
-        P.v[k][2] = lv[k][oslot + 1];
-        P.v[k][3] = lv[k][oslot - PW];
-        P.v[k][4] = lv[k][oslot + PW];
-        P.v[k][5] = qv[0][k];
-        P.v[k][6] = qv[2][k];
-      }
-      op.point(P, qo[0], col + (long long)z * g.nxy, z);
-    }
-
-    // advance the queues by one plane
-#pragma unroll
-    for (int j = 0; j < QS - 1; ++j) {
-      qa[j] = qa[j + 1];
-#pragma unroll
-      for (int k = 0; k < NV; ++k) qv[j][k] = qv[j + 1][k];
-    }
-#pragma unroll
-    for (int j = 0; j < PD; ++j) {
-      ha[j] = ha[j + 1];
-#pragma unroll
-      for (int k = 0; k < NV; ++k) hv[j][k] = hv[j + 1][k];
-#pragma unroll
-      for (int k = 0; k < NO; ++k) qo[j][k] = qo[j + 1][k];
     }
   }
   __syncthreads();                          // both plane buffers are free for the next tile
@@ -552,13 +550,14 @@ __device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, const Coef<R>
 template <typename R>
 struct InitOp {
   static constexpr int NV = 1;
-  static constexpr int NO = 1;
+  static constexpr int NL = 3;
+  static constexpr int NO = 0;
   using OT = R;
   const R* alpha;
   const R* src;                             // the previous state h1 (null = zero state)
   const R* h2;                              // with h2 (and h3) the staged x0 extrapolates:
-  const R* h3;                              //   x0 = e1 h1 + e2 h2 + e3 h3; else x0 = h1
-  R e1, e2, e3;
+  const R* h3;                              //   x0 = e1 h1 + (e2 h2 + h3); else x0 = h1
+  R e1, e2;
   R* xw;                                    // x to initialise with x0 (null = already there)
   R* z;
   const R* top;
@@ -566,19 +565,20 @@ struct InitOp {
   Coef<R> cf;
   long long nxy;
   double acc[3];                            // |b|^2, r.z, |r|^2
-  __device__ R load(int, long long i) const {
-    if (!src) return R(0);
-    if (!h2) return src[i];
-    R v = e2 * h2[i];
-    if (h3) v = fma(e3, h3[i], v);
-    return fma(e1, src[i], v);
+  // raw: h1, h2, h3 (each 0 where absent)
+  __device__ const R* raw_ptr(int k) const { return k == 0 ? src : (k == 1 ? h2 : h3); }
+  __device__ void stage(const R (&r)[3], R (&v)[1]) const {
+    if (!src) { v[0] = R(0); return; }
+    if (!h2) { v[0] = r[0]; return; }
+    R t = mul_rn(e2, r[1]);
+    if (h3) t = add_rn(t, r[2]);
+    v[0] = fma(e1, r[0], t);
   }
-  // the right-hand side's previous state, when the staged value is an extrapolation
-  __device__ R own(int, long long i) const { return h2 ? src[i] : R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[1], long long i, int kz) {
+  __device__ const R* own_ptr(int) const { return nullptr; }
+  __device__ void point(const Pt<R, 1>& P, const R (&rc)[3], const R (&)[1], long long i, int kz) {
     R Av, D;
     stencil<R, 1>(P, 0, cf, kz, Av, D);
-    R b = h2 ? o[0] : P.v[0][0];
+    R b = h2 ? rc[0] : P.v[0][0];     // the right-hand side's previous state h1
     if (kz == 0) b += top_scale * top[i];
     const R r = b - Av;
     const R zz = r * rcp<R>(D);
@@ -600,6 +600,7 @@ struct InitOp {
 template <typename R>
 struct ChebOp {
   static constexpr int NV = 1;
+  static constexpr int NL = 1;
   static constexpr int NO = 2;
   using OT = R;
   const R* alpha;
@@ -612,16 +613,15 @@ struct ChebOp {
   int last;
   Coef<R> cf;
   double acc[1];
-  __device__ R load(int, long long i) const { return yk ? yk[i] : s * z[i]; }
-  __device__ R own(int j, long long i) const {
-    if (j == 0) return z[i];
-    return ykm1 ? ykm1[i] : (k == 1 ? R(0) : s * z[i]);
-  }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int kz) {
+  __device__ const R* raw_ptr(int) const { return yk ? yk : z; }
+  __device__ void stage(const R (&r)[1], R (&v)[1]) const { v[0] = yk ? r[0] : s * r[0]; }
+  __device__ const R* own_ptr(int j) const { return j == 0 ? z : ykm1; }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], const R (&o)[2], long long i, int kz) {
     R Ay, D;
     stencil<R, 1>(P, 0, cf, kz, Ay, D);
     const R y = P.v[0][0];
-    const R yn = y + c1 * (y - o[1]) + c2 * (o[0] - Ay * rcp<R>(D));
+    const R ym = ykm1 ? o[1] : (k == 1 ? R(0) : s * o[0]);
+    const R yn = y + c1 * (y - ym) + c2 * (o[0] - Ay * rcp<R>(D));
     st_out(ynext + i, yn);
     if (last) acc[0] += ((double)D * (double)o[0]) * (double)yn;
   }
@@ -631,7 +631,8 @@ struct ChebOp {
 template <typename R>
 struct DirOp {
   static constexpr int NV = 1;
-  static constexpr int NO = 1;
+  static constexpr int NL = 2;
+  static constexpr int NO = 0;
   using OT = R;
   const R* alpha;
   const R* z;
@@ -641,9 +642,10 @@ struct DirOp {
   int first;
   Coef<R> cf;
   double acc[1];
-  __device__ R load(int, long long i) const { return first ? z[i] : z[i] + beta * pold[i]; }
-  __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
+  __device__ const R* raw_ptr(int k) const { return k == 0 ? z : (first ? nullptr : pold); }
+  __device__ void stage(const R (&r)[2], R (&v)[1]) const { v[0] = first ? r[0] : r[0] + beta * r[1]; }
+  __device__ const R* own_ptr(int) const { return nullptr; }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[2], const R (&)[1], long long i, int kz) {
     R Av, D;
     stencil<R, 1>(P, 0, cf, kz, Av, D);
     st_out(pnew + i, P.v[0][0]);
@@ -655,6 +657,7 @@ struct DirOp {
 template <typename R>
 struct UpdOp {
   static constexpr int NV = 1;
+  static constexpr int NL = 1;
   static constexpr int NO = 2;
   using OT = R;
   const R* alpha;
@@ -664,9 +667,10 @@ struct UpdOp {
   R a;
   Coef<R> cf;
   double acc[2];
-  __device__ R load(int, long long i) const { return p[i]; }
-  __device__ R own(int k, long long i) const { return k == 0 ? x[i] : z[i]; }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[2], long long i, int kz) {
+  __device__ const R* raw_ptr(int) const { return p; }
+  __device__ void stage(const R (&r)[1], R (&v)[1]) const { v[0] = r[0]; }
+  __device__ const R* own_ptr(int k) const { return k == 0 ? x : z; }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], const R (&o)[2], long long i, int kz) {
     R Ap, D;
     stencil<R, 1>(P, 0, cf, kz, Ap, D);
     st_out(x + i, o[0] + a * P.v[0][0]);
@@ -683,6 +687,7 @@ struct UpdOp {
 template <typename R>
 struct GradOp {
   static constexpr int NV = 2;
+  static constexpr int NL = 2;
   static constexpr int NO = 1;
   using OT = double;
   const R* alpha;
@@ -690,9 +695,10 @@ struct GradOp {
   const R* T;
   double* G;
   double sx, sy, sz;
-  __device__ R load(int k, long long i) const { return k == 0 ? mu[i] : T[i]; }
-  __device__ double own(int, long long i) const { return G[i]; }
-  __device__ void point(const Pt<R, 2>& P, const double (&o)[1], long long i, int) {
+  __device__ const R* raw_ptr(int k) const { return k == 0 ? mu : T; }
+  __device__ void stage(const R (&r)[2], R (&v)[2]) const { v[0] = r[0]; v[1] = r[1]; }
+  __device__ const double* own_ptr(int) const { return G; }
+  __device__ void point(const Pt<R, 2>& P, const R (&)[2], const double (&o)[1], long long i, int) {
     const double a = P.a[0], m = P.v[0][0], t = P.v[1][0];
     const double s[7] = {0.0, sx, sx, sy, sy, sz, sz};
     double acc = 0.0;
@@ -710,16 +716,18 @@ struct GradOp {
 template <typename R>
 struct WOp {
   static constexpr int NV = 1;
-  static constexpr int NO = 1;
+  static constexpr int NL = 1;
+  static constexpr int NO = 0;
   using OT = R;
   const R* alpha;
   const R* u;
   R* what;
   Coef<R> cf;
   double acc[1];
-  __device__ R load(int, long long i) const { return u[i]; }
-  __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
+  __device__ const R* raw_ptr(int) const { return u; }
+  __device__ void stage(const R (&r)[1], R (&v)[1]) const { v[0] = r[0]; }
+  __device__ const R* own_ptr(int) const { return nullptr; }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], const R (&)[1], long long i, int kz) {
     R w, D;
     stencil<R, 1>(P, 0, cf, kz, w, D);
     st_out(what + i, w * rcp<R>(D));
@@ -737,7 +745,8 @@ struct WOp {
 template <typename R>
 struct FusedOp {
   static constexpr int NV = 1;
-  static constexpr int NO = 5;
+  static constexpr int NL = 3;
+  static constexpr int NO = 2;
   using OT = R;
   const R* alpha;
   const R* u;                               // u_i
@@ -752,22 +761,17 @@ struct FusedOp {
   int first;
   Coef<R> cf;
   double acc[3];
-  __device__ R load(int, long long i) const {
-    const R sv = first ? wh[i] : wh[i] + b * sho[i];
-    return u[i] - a * sv;
+  // raw: u_i, w_i / D, s_{i-1} / D; staged: u_{i+1}
+  __device__ const R* raw_ptr(int k) const { return k == 0 ? u : (k == 1 ? wh : (first ? nullptr : sho)); }
+  __device__ void stage(const R (&r)[3], R (&v)[1]) const {
+    const R sv = first ? r[1] : r[1] + b * r[2];
+    v[0] = r[0] - a * sv;
   }
-  __device__ R own(int k, long long i) const {
-    switch (k) {
-      case 0: return x[i];
-      case 1: return first ? R(0) : p[i];
-      case 2: return u[i];
-      case 3: return wh[i];
-      default: return first ? R(0) : sho[i];
-    }
-  }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[5], long long i, int kz) {
-    const R sv = first ? o[3] : o[3] + b * o[4];
-    const R pv = first ? o[2] : o[2] + b * o[1];
+  // own: x, p_{i-1}
+  __device__ const R* own_ptr(int k) const { return k == 0 ? x : (first ? nullptr : p); }
+  __device__ void point(const Pt<R, 1>& P, const R (&rc)[3], const R (&o)[2], long long i, int kz) {
+    const R sv = first ? rc[1] : rc[1] + b * rc[2];
+    const R pv = first ? rc[0] : rc[0] + b * o[1];
     st_out(x + i, o[0] + a * pv);
     st_out(p + i, pv);
     st_out(shn + i, sv);
@@ -787,15 +791,17 @@ struct FusedOp {
 template <typename R>
 struct ApplyOp {
   static constexpr int NV = 1;
-  static constexpr int NO = 1;
+  static constexpr int NL = 1;
+  static constexpr int NO = 0;
   using OT = R;
   const R* alpha;
   const R* xin;
   R* y;
   Coef<R> cf;
-  __device__ R load(int, long long i) const { return xin[i]; }
-  __device__ R own(int, long long) const { return R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&)[1], long long i, int kz) {
+  __device__ const R* raw_ptr(int) const { return xin; }
+  __device__ void stage(const R (&r)[1], R (&v)[1]) const { v[0] = r[0]; }
+  __device__ const R* own_ptr(int) const { return nullptr; }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], const R (&)[1], long long i, int kz) {
     R Av, D;
     stencil<R, 1>(P, 0, cf, kz, Av, D);
     y[i] = Av;
@@ -808,6 +814,7 @@ struct ApplyOp {
 template <typename R>
 struct JacobiOp {
   static constexpr int NV = 1;
+  static constexpr int NL = 1;
   static constexpr int NO = 1;
   using OT = R;
   const R* alpha;
@@ -818,9 +825,10 @@ struct JacobiOp {
   R top_scale;
   Coef<R> cf;
   double acc[2];
-  __device__ R load(int, long long i) const { return xin ? xin[i] : R(0); }
-  __device__ R own(int, long long i) const { return h1 ? h1[i] : R(0); }
-  __device__ void point(const Pt<R, 1>& P, const R (&o)[1], long long i, int kz) {
+  __device__ const R* raw_ptr(int) const { return xin; }
+  __device__ void stage(const R (&r)[1], R (&v)[1]) const { v[0] = r[0]; }
+  __device__ const R* own_ptr(int) const { return h1; }
+  __device__ void point(const Pt<R, 1>& P, const R (&)[1], const R (&o)[1], long long i, int kz) {
     R Av, D;
     stencil<R, 1>(P, 0, cf, kz, Av, D);
     R b = o[0];
@@ -1061,7 +1069,6 @@ __device__ __forceinline__ StepResult run_step(const StepArgs<R>& S, const StepV
     init.h2 = order >= 1 ? V.xprev2 : nullptr;
     init.h3 = order == 2 ? V.xprev3 : nullptr;
     guess_coef<R>(order, init.e1, init.e2);
-    init.e3 = R(1);
     init.xw = (V.xprev == V.x) ? nullptr : V.x;
     sweep<R>(g, rank, S.team, S.xcd_order, init, sh);
     stamp();

@@ -514,7 +514,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   float (&xr)[TZ] = pr;                     // x0 lives in the p registers during the set-up
 
   // ---------------- set-up: x0, b, r = b - A x0, u = r / D; x = x0 in memory
-  // x0 = h1 (the previous state), or its extrapolation ex1 h1 + ex2 h2 + ex3 h3
+  // x0 = h1 (the previous state), or its extrapolation e1 h1 + (e2 h2 + h3)
   const float* x0src = V.xprev;
   const int order = guess_order(V);
   const float* h2 = order >= 1 ? V.xprev2 : nullptr;
@@ -523,8 +523,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   guess_coef<float>(order, e1, e2);
   auto x0_at = [&](int i) -> float {
     if (!h2) return x0src[i];
-    float v = e2 * h2[i];
-    if (h3) v = fmaf(1.f, h3[i], v);
+    float v = mul_rn(e2, h2[i]);
+    if (h3) v = add_rn(v, h3[i]);
     return fmaf(e1, x0src[i], v);
   };
   if (q.own && x0src) {

@@ -21,6 +21,7 @@
 #include "nh_resident.hpp"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -616,6 +617,10 @@ nh_status nh_server_submit(nh_server* s, int nx, int ny, int nz, double h, doubl
 nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* finished_ids, int finished_cap,
                          int* n_finished) {
   if (!s) return NH_EINVAL;
+  struct TickRange {   // a host-side roctx range per tick, shown by marker tracing
+    TickRange() { roctxRangePushA("nh_server_tick"); }
+    ~TickRange() { roctxRangePop(); }
+  } const tick_range;
   if (finished_cap > 0 && !finished_ids) return sfail(s, NH_EINVAL, "finished_ids is null");
   if (hipSetDevice(s->device) != hipSuccess) return sfail(s, NH_EHIP, "hipSetDevice failed");
   int finished = 0;

@@ -315,7 +315,7 @@ def test_runs_are_bitwise_deterministic():
     assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["G"], b["G"])
 
 
-@pytest.mark.parametrize("guess", ["adaptive", "projection"])
+@pytest.mark.parametrize("guess", ["adaptive", "projection", "extrapolate"])
 def test_resident_and_streaming_kernels_agree_bitwise(guess):
     """Both FP32 kernels of the single-reduction iteration build the operator
     from the same rounded face terms (the resident sweep carries each cell's

@@ -48,3 +48,21 @@ def test_null_context_calls_fail_cleanly():
     assert lib.nh_server_last_error(None) == b"null server"
     assert lib.nh_server_create(None, 0, None, 1e9, 0, 1) == _lib.NH_EINVAL
     lib.nh_server_destroy(None)
+
+
+def test_library_marks_its_passes_with_roctx_ranges():
+    """The forward pass, the adjoint pass, checkpoint segments and serving ticks are
+    host-side roctx ranges: the library links the range library and calls it."""
+    import subprocess
+    path = _lib.load()._name
+    undef = subprocess.run(["nm", "-D", "--undefined-only", path], capture_output=True, text=True,
+                           check=True).stdout
+    assert "roctxRangePushA" in undef and "roctxRangePop" in undef
+    needed = subprocess.run(["readelf", "-d", path], capture_output=True, text=True, check=True).stdout
+    assert "librocprofiler-sdk-roctx" in needed
+    for src, names in (("nh_api.hip", ("nh_forward", "nh_adjoint", "segment recompute", "segment adjoint")),
+                       ("nh_serve.hip", ("nh_server_tick",))):
+        with open(os.path.join(ROOT, "paper_2603_11045_amd", "csrc", src)) as f:
+            text = f.read()
+        for n in names:
+            assert re.search(r'Range\w*\(?[^;]*"%s' % re.escape(n), text) or ('roctxRangePushA("%s")' % n) in text, n
