@@ -157,6 +157,10 @@ __device__ __forceinline__ R add_rn(R a, R b) {
 #pragma clang fp contract(off)
   return a + b;
 }
+// a * b + c with one rounding, in the precision of R
+template <typename R> __device__ __forceinline__ R fma_r(R a, R b, R c);
+template <> __device__ __forceinline__ float fma_r<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_r<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // dt * c_f = s * a*b/(a+b) with s = 2 dt / h^2 (Prop. 1); b = 0 outside the grid gives 0.
 template <typename R>
@@ -356,6 +360,12 @@ struct Pt {
   R a[7];
   R v[NV][7];
 };
+
+// A load through a global (not flat) pointer.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, long long i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
 
 // Buffer loads of one z plane of a vector. The resource covers the plane
 // (base p + zp nxy, nxy elements); a lane whose byte offset is kOffLane, a
@@ -741,7 +751,11 @@ struct WOp {
 //   u_{i+1} = u_i - a s_i   (staged: needed at the halo for the stencil),
 //   w_{i+1} = A u_{i+1};  accumulate u.r = D u^2, u.w and |r|^2 = (D u)^2.
 // The next a, b follow from these three sums alone, so an iteration needs a
-// single team reduction.
+// single team reduction. x moves every second iteration: xmode 1 leaves it
+// (the iteration's a p stays pending), xmode 2 applies the pending term of the
+// previous iteration (ap, and p_{i-1} read here anyway) and then its own, in
+// that order and each rounded as on its own (the same bits as two updates),
+// which saves reading and writing x in every other iteration.
 template <typename R>
 struct FusedOp {
   static constexpr int NV = 1;
@@ -758,7 +772,9 @@ struct FusedOp {
   R* whn;                                   // w_{i+1} / D
   R* shn;                                   // s_i / D
   R a, b;
+  R ap;                                     // a_{i-1} of the pending update (xmode 2)
   int first;
+  int xmode;
   Coef<R> cf;
   double acc[3];
   // raw: u_i, w_i / D, s_{i-1} / D; staged: u_{i+1}
@@ -767,12 +783,12 @@ struct FusedOp {
     const R sv = first ? r[1] : r[1] + b * r[2];
     v[0] = r[0] - a * sv;
   }
-  // own: x, p_{i-1}
-  __device__ const R* own_ptr(int k) const { return k == 0 ? x : (first ? nullptr : p); }
+  // own: x (when it moves), p_{i-1}
+  __device__ const R* own_ptr(int k) const { return k == 0 ? (xmode == 2 ? x : nullptr) : (first ? nullptr : p); }
   __device__ void point(const Pt<R, 1>& P, const R (&rc)[3], const R (&o)[2], long long i, int kz) {
     const R sv = first ? rc[1] : rc[1] + b * rc[2];
     const R pv = first ? rc[0] : rc[0] + b * o[1];
-    st_out(x + i, o[0] + a * pv);
+    if (xmode == 2) st_out(x + i, fma_r(a, pv, fma_r(ap, o[1], o[0])));
     st_out(p + i, pv);
     st_out(shn + i, sv);
     R w, D;
@@ -1169,6 +1185,8 @@ __device__ __forceinline__ StepResult run_step(const StepArgs<R>& S, const StepV
       R* wb[2] = {S.w0, S.w1};
       R* sb[2] = {S.s0, S.s1};
       int cur = 0;
+      int xpend = 0;                        // x += a p of the last iteration still to apply
+      R a_pend = R(0);
       while (ok) {
         if (it >= S.max_iter) { status |= kNoConv; break; }
         FusedOp<R> F;
@@ -1178,9 +1196,13 @@ __device__ __forceinline__ StepResult run_step(const StepArgs<R>& S, const StepV
         F.un = ub[cur ^ 1]; F.whn = wb[cur ^ 1]; F.shn = sb[cur ^ 1];
         F.a = (R)a_cg; F.b = (R)b_cg;
         F.first = (it == 0);
+        F.xmode = xpend ? 2 : 1;
+        F.ap = a_pend;
         F.cf = cf;
         F.acc[0] = F.acc[1] = F.acc[2] = 0.0;
         sweep<R>(g, rank, S.team, S.xcd_order, F, sh);
+        xpend = !xpend;
+        a_pend = F.a;
         stamp();
         double v3n[3] = {F.acc[0], F.acc[1], F.acc[2]};
         ok &= team_sum<R, 3>(S, rank, red, v3n, sh);
@@ -1193,6 +1215,18 @@ __device__ __forceinline__ StepResult run_step(const StepArgs<R>& S, const StepV
         b_cg = gn / gam;
         a_cg = gn / (dn - b_cg * gn / a_cg);
         gam = gn;
+      }
+      if (xpend && ok) {
+        // the last iteration's x += a p (p holds its p), then a team barrier:
+        // the gradient pass and a following step read x at the halo
+        const R ap = a_pend;
+        const R* pp = S.p0;
+        R* xx = V.x;
+        own_cells(g, rank, S.team, S.xcd_order, [&](long long i, long long, int) {
+          st_out(xx + i, fma_r(ap, gld(pp, i), gld((const R*)xx, i)));
+        });
+        double vz[1] = {0.0};
+        ok &= team_sum<R, 1>(S, rank, red, vz, sh);
       }
     }
   }

@@ -7,6 +7,11 @@ module turns one into the short text summaries kept with the benchmark:
     per-kernel dispatch statistics (the ``--stats`` table), and for kernel K
     the average duration over its last N dispatches (the timed region).
 
+``python -m paper_2603_11045_amd.profiling markers DB``
+    the library's roctx ranges (forward, adjoint, checkpoint segments,
+    serving ticks) of a ``--marker-trace`` run: count and host-side duration
+    per range name.
+
 ``python -m paper_2603_11045_amd.profiling traffic --fetch DB1 --write DB2 --kernel K --last N --out F``
     HBM bytes per dispatch of kernel K from a ``--pmc FETCH_SIZE`` run and a
     ``--pmc WRITE_SIZE`` run, each scaled by what the same counter reads for
@@ -78,6 +83,24 @@ def kernel_table(db: str) -> str:
     return "\n".join(out)
 
 
+def marker_table(db: str) -> str:
+    """Count, total and mean duration (ms) of the roctx ranges, by range message."""
+    con = sqlite3.connect(db)
+    rows = con.execute("SELECT extdata, start, end FROM regions WHERE category LIKE 'MARKER%'").fetchall()
+    con.close()
+    agg: Dict[str, list] = {}
+    for ext, s, e in rows:
+        try:
+            name = json.loads(ext).get("message", "?") if ext else "?"
+        except ValueError:
+            name = "?"
+        agg.setdefault(name, []).append((int(e) - int(s)) / 1e6)
+    out = ["| range | count | total ms | mean ms | min ms | max ms |", "|---|---|---|---|---|---|"]
+    for n, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| `{n}` | {len(v)} | {sum(v):.1f} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
+    return "\n".join(out)
+
+
 def last_average_us(db: str, kernel: str, last: int) -> dict:
     d = [(e - s) / 1e3 for n, s, e in dispatches(db) if n == kernel]
     if not d:
@@ -143,6 +166,8 @@ def main(argv=None):
     k.add_argument("db")
     k.add_argument("--kernel", default=None)
     k.add_argument("--last", type=int, default=0)
+    m = sub.add_parser("markers")
+    m.add_argument("db")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -155,6 +180,8 @@ def main(argv=None):
         if a.kernel:
             print()
             print(json.dumps(last_average_us(a.db, a.kernel, a.last)))
+    elif a.cmd == "markers":
+        print(marker_table(a.db))
     else:
         rec = traffic(a.fetch, a.write, a.kernel, a.last)
         txt = json.dumps(rec, indent=1)
