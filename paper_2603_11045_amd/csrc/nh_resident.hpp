@@ -521,16 +521,30 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   const float* h3 = order == 2 ? V.xprev3 : nullptr;
   float e1, e2;
   guess_coef<float>(order, e1, e2);
-  auto x0_at = [&](int i) -> float {
-    if (!h2) return x0src[i];
-    float v = mul_rn(e2, h2[i]);
-    if (h3) v = add_rn(v, h3[i]);
-    return fmaf(e1, x0src[i], v);
+  auto x0_of = [&](float h1v, float h2v, float h3v) -> float {
+    if (!h2) return h1v;
+    float v = mul_rn(e2, h2v);
+    if (h3) v = add_rn(v, h3v);
+    return fmaf(e1, h1v, v);
   };
+  auto x0_at = [&](int i) -> float { return x0_of(x0src[i], h2 ? h2[i] : 0.f, h3 ? h3[i] : 0.f); };
+  // the column's h1, h2, h3 are all loaded before any is used (h1 in the w
+  // registers, h2 in the p registers, h3 in the u registers: all free until
+  // the set-up sweep); h1 stays for the right-hand side, so the set-up sweep
+  // waits for no load
+  float (&br)[TZ] = wr;
   if (q.own && x0src) {
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
-      if (z < q.tzn) xr[z] = x0_at(q.col + (T.z0 + z) * nxy);
+      if (z < q.tzn) {
+        const int i = q.col + (T.z0 + z) * nxy;
+        br[z] = x0src[i];
+        if (h2) xr[z] = h2[i];
+        if (h3) ur[z] = h3[i];
+      }
+#pragma unroll
+    for (int z = 0; z < TZ; ++z)
+      if (z < q.tzn) xr[z] = x0_of(br[z], xr[z], ur[z]);
   }
   if (q.own && x0src != V.x) {
 #pragma unroll
@@ -546,6 +560,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   } else {
     fill_ring<G>(g, q, lring, [&](int) { return 0.f; });
   }
+  // the top source, loaded before the sweep as well
+  const float top_q = q.own && T.z0 == 0 ? V.top_src[q.col] : 0.f;
   __builtin_amdgcn_s_waitcnt(0);            // the alpha tile has reached LDS
   __syncthreads();
   double acc3[3] = {0.0, 0.0, 0.0};
@@ -553,8 +569,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                  [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                    const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                    const float Av = apply_at(n, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
-                   float b = h2 ? x0src[q.col + (T.z0 + z) * nxy] : xr[z];
-                   if (T.z0 + z == 0) b += V.top_scale * V.top_src[q.col];
+                   float b = h2 ? br[z] : xr[z];
+                   if (T.z0 + z == 0) b += V.top_scale * top_q;
                    const float r = b - Av;
                    const float u = r * rcp<float>(n.D);
                    ur[z] = u;
@@ -570,7 +586,14 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     for (int z = 0; z < TZ; ++z)
       if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(S.z + q.col + (T.z0 + z) * nxy, ur[z]);
   }
-  ok &= team_sum_dev<3>(S, rank, red, acc3, rs);
+  // the neighbours' u0 faces start loading into the u ring as soon as their
+  // slots show that they are published (the set-up's x0 values there are used)
+  ok &= team_sum_dev<3>(S, rank, red, acc3, rs, res_neighbours(g, tile, S.team, S.xcd_order, [&]() {
+                          int tid_l = threadIdx.x, nxy_l = nxy;
+                          asm volatile("" : "+v"(tid_l));
+                          asm volatile("" : "+s"(nxy_l));
+                          ring_dma<G>(g, q, lring, S.z, tid_l, nxy_l);
+                        }));
   stamp();
   const double bb = acc3[0];
   double gam = acc3[1], rr = acc3[2];
@@ -579,6 +602,10 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   float* wb[2] = {S.w0, S.w1};
   float* sb[2] = {S.s0, S.s1};
   int it = 0, status = kOk;
+  if (!(ok && bb != 0.0 && rr > S.rtol2 * bb)) {
+    __builtin_amdgcn_s_waitcnt(0);          // no solve: the u ring's loads end before LDS is reused
+    __syncthreads();
+  }
   if (ok && bb == 0.0) {
     if (q.own) {
 #pragma unroll
@@ -591,7 +618,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     // ---------------- w0 = A u0
     if (q.own && q.bot_z) zlo[0] = ld_dev(ub[0] + q.col + (T.z0 - 1) * nxy);
     if (q.own && q.top_z) zhi[0] = ld_dev(ub[0] + q.col + T.z1 * nxy);
-    fill_ring<G>(g, q, lring, [&](int i) { return ld_dev(ub[0] + i); });
+    __builtin_amdgcn_s_waitcnt(0);          // the u ring has landed
     __syncthreads();
     double acc1[1] = {0.0};
     // w0 / D on the tile's faces is published as each plane is done (no
@@ -614,8 +641,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                             int tid_l = threadIdx.x, nxy_l = nxy;
                             asm volatile("" : "+v"(tid_l));
                             asm volatile("" : "+s"(nxy_l));
-                            ring_dma<G>(g, q, ring_u, ub[0], tid_l, nxy_l);
-                            ring_dma<G>(g, q, ring_w, wb[0], tid_l, nxy_l);
+                            ring_dma<G>(g, q, ring_w, wb[0], tid_l, nxy_l);   // u0 is in ring_u already
                           }));
     stamp();
     double a_cg = gam / acc1[0], b_cg = 0.0;
