@@ -85,6 +85,47 @@ def cpu_baseline(w, sample_steps: int, threads: int = 0):
             "cg_iters": int(it_f.sum() + it_a.sum()), "seconds": t}
 
 
+def stream_probe(dev, reps: int = 20) -> dict:
+    """What the streaming sweep's traffic reaches on this chip: nh_stream_probe_f32
+    (6 loads and 5 device-coherent stores per cell, 64x16-column tiles marching
+    512x512x64, one barrier per plane, no arithmetic), timed with events on its
+    stream over `reps` passes after 3 warm-up passes."""
+    import ctypes
+
+    import torch
+
+    from paper_2603_11045_amd import _lib
+
+    nx, ny, nz = 512, 512, 64
+    bufs = [torch.full((nz, ny, nx), float(k), dtype=torch.float32, device=dev) for k in range(11)]
+    vp = ctypes.c_void_p
+    ins = (vp * 6)(*[b.data_ptr() for b in bufs[:6]])
+    outs = (vp * 5)(*[b.data_ptr() for b in bufs[6:]])
+    lib = _lib.load()
+    stream = torch.cuda.current_stream()
+
+    def once():
+        code = lib.nh_stream_probe_f32(ins, outs, nx, ny, nz, vp(stream.cuda_stream))
+        if code != 0:
+            raise RuntimeError(f"nh_stream_probe_f32 returned {code}")
+
+    for _ in range(3):
+        once()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        once()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    ok = bool(torch.all(bufs[6] == 1.0)) and bool(torch.all(bufs[9] == 7.0))
+    del bufs
+    torch.cuda.empty_cache()
+    gbs = 44.0 * nx * ny * nz / us / 1e3
+    return {"grid": [nx, ny, nz], "bytes_per_cell": 44, "passes": reps, "us_per_pass": us, "gbs": gbs,
+            "frac_of_peak": gbs / 8000.0, "outputs_ok": ok}
+
+
 def paper_fixed_k(Solver, dev, reps: int):
     """The paper's own solver set-up (App. D.2, Table 5): the 64x64x16
     specimen with periodic lateral faces, dx = dy = 0.156, dz = 0.0625,
@@ -263,6 +304,8 @@ def main():
                     help="repetitions of the paper-shaped fixed-K timing (0 = skip)")
     ap.add_argument("--invert-iters", type=int, default=20,
                     help="timed iterations of each inversion driver (0 = skip)")
+    ap.add_argument("--no-stream-probe", action="store_true",
+                    help="skip the access-pattern probe (nh_stream_probe_f32) of the streaming sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (nh_copy_f32) three times, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -465,6 +508,8 @@ def main():
             print(f"[bench] section {name} failed: {e!r}", file=sys.stderr, flush=True)
             rec[name] = {"error": repr(e)}
 
+    if not args.no_stream_probe:
+        section("stream_probe", lambda: stream_probe(dev))
     if args.paper_reps > 0:
         section("paper_fixed_k", lambda: paper_fixed_k(Solver, dev, args.paper_reps))
     if args.invert_iters > 0:

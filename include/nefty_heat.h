@@ -306,6 +306,20 @@ void nh_destroy(nh_ctx *ctx);
  * traffic (8 bytes per element) to calibrate hardware byte counters. */
 nh_status nh_copy_f32(const float *src, float *dst, size_t n, void *hip_stream);
 
+/* One pass of the streaming CG sweep's memory access pattern without its
+ * arithmetic, on `hip_stream` (NULL = the null stream), asynchronous. Not
+ * part of the solver: a measurement of what that traffic reaches on the chip.
+ * in6: six device pointers, out5: five device pointers (host arrays of device
+ * addresses, read during the call), each an nz x ny x nx FP32 volume, x
+ * fastest; tiles of 64 x 16 columns march the nz planes, six loads and five
+ * device-coherent stores per cell (44 bytes), one workgroup barrier per plane.
+ * Results: out[k] = in[k] + in[k+1] (k < 4), out[4] = in[4] + in[5] + in[0]
+ * of the -x neighbour within the 64-cell row (0 at its first cell).
+ * NH_EINVAL for null pointers, nx not a multiple of 64, ny not a multiple of
+ * 16, or a non-positive size. */
+nh_status nh_stream_probe_f32(const float *const *in6, float *const *out5, int nx, int ny, int nz,
+                              void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of inversion jobs (the reconstruction loop
  * of Sec. 4.3 run for many independent requests on one GPU).

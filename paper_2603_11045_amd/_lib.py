@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "NH_OK", -1: "NH_EINVAL", -2: "NH_ENOMEM", -3: "NH_ESTATE", -
 EXPORTED = ["nh_create", "nh_set_grid", "nh_set_solver", "nh_forward", "nh_adjoint",
             "nh_forward_f64", "nh_adjoint_f64", "nh_adjoint_vjp", "nh_adjoint_vjp_f64",
             "nh_adjoint_source_grad", "nh_adjoint_source_grad_f64", "nh_get_state", "nh_apply_A", "nh_tv", "nh_tv_f64", "nh_tv_noalloc", "nh_set_launch",
-            "nh_set_boundary", "nh_set_jacobi_sweeps", "nh_set_cg_variant", "nh_set_preconditioner", "nh_set_initial_guess", "nh_set_barrier_timeout", "nh_get_stats", "nh_get_step_iters", "nh_last_error", "nh_destroy", "nh_copy_f32",
+            "nh_set_boundary", "nh_set_jacobi_sweeps", "nh_set_cg_variant", "nh_set_preconditioner", "nh_set_initial_guess", "nh_set_barrier_timeout", "nh_get_stats", "nh_get_step_iters", "nh_last_error", "nh_destroy", "nh_copy_f32", "nh_stream_probe_f32",
             "nh_server_create", "nh_server_submit", "nh_server_tick", "nh_server_job", "nh_server_release",
             "nh_server_get_stats", "nh_server_last_error", "nh_server_destroy", "nh_serve_job_team",
             "nh_serve_job_bytes", "nh_serve_admit_select", "nh_server_set_slice",
@@ -160,6 +160,8 @@ def load():
     lib.nh_destroy.argtypes = [vp]
     lib.nh_destroy.restype = None
     lib.nh_copy_f32.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.nh_stream_probe_f32.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, vp]
     llp = ctypes.POINTER(ctypes.c_longlong)
     lib.nh_server_create.argtypes = [ctypes.POINTER(vp), ip, vp, dp, ip, ip]
     lib.nh_server_submit.argtypes = [vp, ip, ip, ip, dp, dp, ip, dp, ip, vp, vp, vp, vp, llp]

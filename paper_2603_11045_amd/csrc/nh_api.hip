@@ -28,6 +28,42 @@
 #include <string>
 #include <vector>
 
+namespace nh {
+
+// The streaming sweep's memory access pattern without its arithmetic: tiles
+// of 64 x 16 columns (one 1024-thread workgroup each) march the nz planes;
+// per cell six loads and five device-coherent stores, one workgroup barrier
+// per plane. A measurement of what this traffic reaches on the chip, not part
+// of the solver: out_k = in_k + in_{k+1}, and out_4 also adds the -x
+// neighbour's in_0 through LDS.
+struct ProbeArgs {
+  const float* in[6];
+  float* out[5];
+  int nx, ny, nz;
+};
+
+__global__ void __launch_bounds__(1024, 1) stream_probe_kernel(ProbeArgs A) {
+  __shared__ float sh[2][1024];
+  const int ntx = A.nx >> 6;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const long long col = (long long)((blockIdx.x % ntx) * 64 + tx) + (long long)A.nx * ((blockIdx.x / ntx) * 16 + ty);
+  const long long nxy = (long long)A.nx * A.ny;
+  for (int z = 0; z < A.nz; ++z) {
+    const long long i = col + z * nxy;
+    float v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = gld(A.in[k], i);
+    sh[z & 1][threadIdx.x] = v[0];
+    __syncthreads();
+    const float w = tx > 0 ? sh[z & 1][threadIdx.x - 1] : 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st_out(A.out[k] + i, v[k] + v[k + 1]);
+    st_out(A.out[4] + i, v[4] + v[5] + w);
+  }
+}
+
+}  // namespace nh
+
 namespace {
 
 using nh::Geom;
@@ -1486,6 +1522,28 @@ void nh_destroy(nh_ctx* c) {
   for (Buf& b : c->w) release(c, b);
   for (auto e : c->ev) (void)hipEventDestroy(e);
   delete c;
+}
+
+nh_status nh_stream_probe_f32(const float* const* in6, float* const* out5, int nx, int ny, int nz,
+                              void* hip_stream) {
+  if (!in6 || !out5) return NH_EINVAL;
+  if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 64 != 0 || ny % 16 != 0) return NH_EINVAL;
+  const long long tiles = (long long)(nx / 64) * (ny / 16);
+  if (tiles > 1 << 20 || (long long)nx * ny * nz > (1ll << 40)) return NH_EINVAL;
+  nh::ProbeArgs A;
+  for (int k = 0; k < 6; ++k) {
+    if (!in6[k]) return NH_EINVAL;
+    A.in[k] = in6[k];
+  }
+  for (int k = 0; k < 5; ++k) {
+    if (!out5[k]) return NH_EINVAL;
+    A.out[k] = out5[k];
+  }
+  A.nx = nx;
+  A.ny = ny;
+  A.nz = nz;
+  hipLaunchKernelGGL(nh::stream_probe_kernel, dim3((unsigned)tiles), dim3(1024), 0, (hipStream_t)hip_stream, A);
+  return hipGetLastError() == hipSuccess ? NH_OK : NH_EHIP;
 }
 
 nh_status nh_copy_f32(const float* src, float* dst, size_t n, void* hip_stream) {

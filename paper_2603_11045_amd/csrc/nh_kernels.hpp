@@ -395,11 +395,13 @@ __device__ __forceinline__ double plane_ld<double>(__amdgpu_buffer_rsrc_t r, uns
 // (raw_ptr(k); null reads 0), combined into the NV staged vectors by
 // stage(raw, v) when a plane is staged; NO operands of type OT read at the
 // cell itself (own_ptr(k)); alpha; and point(P, rc, o, i, kz), which also
-// receives the cell's raw values rc. Loads are issued kPrefetch planes ahead
+// receives the cell's raw values rc. Loads are issued Op::PD planes ahead
 // of their use; all queues are rings of Q plane slots with compile-time slot
 // numbers (the z loop is unrolled Q times), so no register moves, which would
 // wait for loads in flight, rotate them. Arithmetic on loaded values happens
-// in stage and point, once the data is needed.
+// in stage and point, once the data is needed. The set-up and gradient
+// operators, which run once per step and hold the most values per plane,
+// prefetch one plane less (their rings would not fit the registers).
 constexpr int kPrefetch = 3;
 
 template <typename R, typename Op>
@@ -407,10 +409,13 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
   constexpr int NV = Op::NV;
   constexpr int NL = Op::NL;
   constexpr int NO = Op::NO > 0 ? Op::NO : 1;
-  constexpr int PD = kPrefetch;
+  constexpr int PD = Op::PD;
   constexpr int Q = PD + 2;                 // plane slots: z-1 .. z+PD
   using OT = typename Op::OT;
-  const int tid = threadIdx.x;
+  // the lane's geometry is recomputed in every call (laundered): hoisted out
+  // of a caller's iteration loop it would hold registers through the solve
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int TX = g.TX, TY = g.TY, PW = TX + 2;
   const int tx = tid & (TX - 1), ty = tid >> g.txs;
   const int gx = T.x0 + tx, gy = T.y0 + ty;
@@ -559,6 +564,7 @@ __device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, const Coef<R>
 // Set-up: b = x0 + top source, r = b - A x0, z = r / D.
 template <typename R>
 struct InitOp {
+  static constexpr int PD = kPrefetch - 1;
   static constexpr int NV = 1;
   static constexpr int NL = 3;
   static constexpr int NO = 0;
@@ -609,6 +615,7 @@ struct InitOp {
 // (k = 1) or s z (k = 2). The last step also accumulates r . y_m = (D z) . y_m.
 template <typename R>
 struct ChebOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 1;
   static constexpr int NO = 2;
@@ -640,6 +647,7 @@ struct ChebOp {
 // Phase A: p_new = z + beta p_old, w = A p_new, accumulate p_new . w.
 template <typename R>
 struct DirOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 2;
   static constexpr int NO = 0;
@@ -666,6 +674,7 @@ struct DirOp {
 // Phase B: x += a p, z -= a (A p) / D, accumulate r.z = D z^2 and |r|^2 = (D z)^2.
 template <typename R>
 struct UpdOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 1;
   static constexpr int NO = 2;
@@ -696,6 +705,7 @@ struct UpdOp {
 // s_f = 2 dt / h^2, i.e. G += -dt dc_f/da_p dT dmu (eq. grad_assembly).
 template <typename R>
 struct GradOp {
+  static constexpr int PD = kPrefetch - 1;
   static constexpr int NV = 2;
   static constexpr int NL = 2;
   static constexpr int NO = 1;
@@ -725,6 +735,7 @@ struct GradOp {
 // Single-reduction set-up, second part: w = A u, store w / D, accumulate u.w.
 template <typename R>
 struct WOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 1;
   static constexpr int NO = 0;
@@ -758,6 +769,7 @@ struct WOp {
 // which saves reading and writing x in every other iteration.
 template <typename R>
 struct FusedOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 3;
   static constexpr int NO = 2;
@@ -806,6 +818,7 @@ struct FusedOp {
 // y = A x on its own (operator tests).
 template <typename R>
 struct ApplyOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 1;
   static constexpr int NO = 0;
@@ -829,6 +842,7 @@ struct ApplyOp {
 // accumulates |b|^2 and |b - A x|^2 (the residual of the sweep's input).
 template <typename R>
 struct JacobiOp {
+  static constexpr int PD = kPrefetch;
   static constexpr int NV = 1;
   static constexpr int NL = 1;
   static constexpr int NO = 1;

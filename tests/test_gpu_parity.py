@@ -464,3 +464,31 @@ def test_error_paths():
     s2.set_barrier_timeout(20.0)
     T2 = s2.forward(a2, q2, [1.0, 0.0], 1.0, 2)
     assert torch.isfinite(T2).all()
+
+
+# ------------------------------------------------------------------ measurement probe
+def test_stream_probe_outputs():
+    """nh_stream_probe_f32 (the streaming sweep's access pattern, used to measure
+    what that traffic reaches): every output element against numpy, on a grid of
+    several 64x16-column tiles and five planes."""
+    import ctypes
+
+    from paper_2603_11045_amd import _lib
+    nx, ny, nz = 128, 48, 5
+    rng = np.random.default_rng(41)
+    host = [rng.standard_normal((nz, ny, nx)).astype(np.float32) for _ in range(6)]
+    ins_t = [torch.from_numpy(h).cuda() for h in host]
+    outs_t = [torch.zeros((nz, ny, nx), dtype=torch.float32, device="cuda") for _ in range(5)]
+    vp = ctypes.c_void_p
+    ins = (vp * 6)(*[t.data_ptr() for t in ins_t])
+    outs = (vp * 5)(*[t.data_ptr() for t in outs_t])
+    lib = _lib.load()
+    assert lib.nh_stream_probe_f32(ins, outs, nx, ny, nz, vp(torch.cuda.current_stream().cuda_stream)) == 0
+    torch.cuda.synchronize()
+    got = [t.cpu().numpy() for t in outs_t]
+    for k in range(4):
+        assert np.array_equal(got[k], host[k] + host[k + 1]), k
+    left = np.zeros_like(host[0])
+    left[:, :, 1:] = host[0][:, :, :-1]
+    left[:, :, 64::64] = 0.0                 # the neighbour lies within the 64-cell row of a tile
+    assert np.array_equal(got[4], (host[4] + host[5]) + left)

@@ -30,10 +30,13 @@ HOT = {
 }
 
 
-# multi-step kernels: the most VGPR spills allowed
+# multi-step kernels: the most VGPR spills allowed. Their values live across
+# the steps of a launch; the reloads sit outside the plane loops (checked in
+# the assembly when a budget was set: the serving streaming kernel reloads per
+# step, per iteration and per tile, never per plane).
 BATCHED = {
-    "_ZN2nh21batch_resident_kernelEPKNS_6JobRunEPK15HIP_vector_typeIiLj2EEPNS_7JobProgE": ("batch_resident_kernel", 6),
-    "_ZN2nh16batch_run_kernelEPKNS_6JobRunEPK15HIP_vector_typeIiLj2EEPNS_7JobProgE": ("batch_run_kernel", 25),
+    "_ZN2nh21batch_resident_kernelEPKNS_6JobRunEPK15HIP_vector_typeIiLj2EEPNS_7JobProgE": ("batch_resident_kernel", 8),
+    "_ZN2nh16batch_run_kernelEPKNS_6JobRunEPK15HIP_vector_typeIiLj2EEPNS_7JobProgE": ("batch_run_kernel", 96),
     "_ZN2nh19jacobi_steps_kernelILi8EEEvNS_8StepArgsIfEENS_8JacStepsE": ("jacobi_steps_kernel<8>", 6),
     "_ZN2nh18jacobi_step_kernelILi8EEEvNS_8StepArgsIfEE": ("jacobi_step_kernel<8>", 0),
 }

@@ -66,3 +66,17 @@ def test_library_marks_its_passes_with_roctx_ranges():
             text = f.read()
         for n in names:
             assert re.search(r'Range\w*\(?[^;]*"%s' % re.escape(n), text) or ('roctxRangePushA("%s")' % n) in text, n
+
+
+def test_stream_probe_rejects_bad_arguments():
+    """The access-pattern probe checks its arguments before touching the GPU."""
+    lib = _lib.load()
+    vp = ctypes.c_void_p
+    fake_in = (vp * 6)(*[vp(64 * (k + 1)) for k in range(6)])
+    fake_out = (vp * 5)(*[vp(64 * (k + 8)) for k in range(5)])
+    einval = -1
+    assert lib.nh_stream_probe_f32(None, fake_out, 64, 16, 1, None) == einval
+    assert lib.nh_stream_probe_f32(fake_in, None, 64, 16, 1, None) == einval
+    assert lib.nh_stream_probe_f32(fake_in, fake_out, 65, 16, 1, None) == einval   # nx not a multiple of 64
+    assert lib.nh_stream_probe_f32(fake_in, fake_out, 64, 17, 1, None) == einval   # ny not a multiple of 16
+    assert lib.nh_stream_probe_f32(fake_in, fake_out, 64, 16, 0, None) == einval
