@@ -324,6 +324,9 @@ struct nh_server {
   int slice_iters = 512;
   int backfill = 1;        // 1: EASY backfilling, 0: strict arrival order
   std::map<long long, std::pair<double, long long>> shape_time;   // grid -> (seconds, steps) measured
+  // grid -> (seconds, iterations + steps) measured: the slice budget's cost of an iteration
+  std::map<long long, std::pair<double, long long>> shape_iter;
+  double unit_ns = 0.0, unit_cost = 0.0;   // measured ns against the cost model's units, summed
   size_t used_bytes = 0;
   int used_blocks = 0;
   long long next_id = 1;
@@ -422,6 +425,12 @@ void retire(nh_server* s, SJob* j) {
 }
 
 // Job j's slice of the next launch.
+long long shape_key(const SJob* j) { return ((long long)j->nx << 42) | ((long long)j->ny << 21) | j->nz; }
+
+// iterations (plus steps) a grid must have run before its measured time per
+// iteration prices its slices
+constexpr long long kShapeIterMin = 64;
+
 void job_run(const nh_server* s, const SJob* j, unsigned long long epoch_base, nh::JobRun& J) {
   std::memset(&J, 0, sizeof(J));
   nh::StepArgs<float>& S = J.S;
@@ -464,11 +473,29 @@ void job_run(const nh_server* s, const SJob* j, unsigned long long epoch_base, n
   J.mode = S.mode;
   J.n0 = j->step;
   J.nsteps = j->nsteps;
-  J.cost = j->cost;
-  J.budget = (long long)s->slice_iters * (s->resident ? kResCells + kResFixedCost : kVoxelsPerBlock + kReductionCost);
+  // The slice ends once the job's iterations (and steps, each priced as one
+  // iteration) times its cost would pass the budget. Until anything has been
+  // measured, cost and budget are in the cost model's units (the cells of a
+  // workgroup's tile plus a fixed part per reduction); afterwards in
+  // nanoseconds: the budget is the model's budget at the measured ns per model
+  // unit, and a job's cost its grid's measured time per iteration, so that
+  // every team's slice takes about the same time and few wait for the slowest.
+  const long long model_budget =
+      (long long)s->slice_iters * (s->resident ? kResCells + kResFixedCost : kVoxelsPerBlock + kReductionCost);
+  if (s->unit_cost > 0.0) {
+    const double ns_per_unit = s->unit_ns / s->unit_cost;
+    J.budget = std::llround((double)model_budget * ns_per_unit);
+    auto it = s->shape_iter.find(shape_key(j));
+    const double ns = it != s->shape_iter.end() && it->second.second >= kShapeIterMin
+                          ? 1e9 * it->second.first / (double)it->second.second
+                          : (double)j->cost * ns_per_unit;
+    J.cost = std::max<long long>(1, std::llround(ns));
+  } else {
+    J.cost = j->cost;
+    J.budget = model_budget;
+  }
 }
 
-long long shape_key(const SJob* j) { return ((long long)j->nx << 42) | ((long long)j->ny << 21) | j->nz; }
 
 // Estimated seconds per step of job j: its own measured mean once it has run
 // a few steps, else the mean of its grid shape, else of all measured jobs.
@@ -745,6 +772,14 @@ nh_status nh_server_tick(nh_server* s, int* n_active, int* n_queued, long long* 
         auto& st = s->shape_time[shape_key(j)];
         st.first += sec;
         st.second += pr.steps;
+        const long long work = pr.iters + pr.steps;
+        if (work > 0) {
+          auto& si = s->shape_iter[shape_key(j)];
+          si.first += sec;
+          si.second += work;
+          s->unit_ns += 1e9 * sec;
+          s->unit_cost += (double)work * (double)j->cost;
+        }
       }
       const bool failed = (pr.status & (nh::kNonFinite | nh::kTimeout)) != 0;
       if (j->state == NH_JOB_FORWARD) {
