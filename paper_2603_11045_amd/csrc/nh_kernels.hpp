@@ -19,7 +19,9 @@
 //   phase B   a = rz / pw,  x += a p,  z -= a (A p) / D,  rz = D z.z, rr = |D z|^2
 // until rr <= rtol^2 bb. Only z is stored (r = D z); A p is recomputed in
 // phase B instead of being stored, and D comes from alpha in-kernel, so an
-// iteration moves 40 bytes per voxel in FP32.
+// iteration moves 40 bytes per voxel in FP32. That is variant 0; the default
+// is the single-reduction form of the same iteration (FusedOp below: one
+// sweep and one team reduction per iteration).
 //
 // The stencil is evaluated by marching a 2-D tile of (x, y) columns along z:
 // each z plane of the staged vectors and of alpha, with its one-cell halo in

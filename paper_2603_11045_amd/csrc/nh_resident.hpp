@@ -5,16 +5,19 @@
 // A u / D and A p / D, the vectors of the single-reduction iteration of
 // nh_kernels.hpp -- stays in the registers of the workgroup that owns the tile
 // for the whole time step, and alpha stays in LDS. Only x, which no neighbour
-// reads during the solve, is updated in place in memory (8 bytes per cell and
-// iteration, coalesced, no halo). The elementwise updates run in registers, the stencil
-// exchanges in-tile neighbours through LDS one z-plane at a time, and only the
-// values on the tile's faces are published (write-through, device-scope
-// stores) for the neighbouring tiles, which read them with device-scope loads
-// after the next team reduction. Because every inter-workgroup exchange uses
-// device-coherent accesses, the team reduction needs no L2 write-back or
-// invalidation. The arithmetic is the same as the streaming kernel's
-// single-reduction form; halo values are recomputed with the same fused
-// multiply-adds as the owner uses, so both sides see identical bits.
+// reads during the solve, is updated in place in memory inside each
+// iteration's sweep (8 bytes per cell and iteration, coalesced, no halo). The
+// elementwise updates run in registers, the stencil exchanges in-tile
+// neighbours through LDS one z-plane at a time, and only the values on the
+// tile's faces are published (write-through, device-scope stores) for the
+// neighbouring tiles. A neighbour loads them straight into its LDS halo rings
+// (device-coherent direct loads) as soon as the team reduction that follows
+// shows their slots tagged, while it still gathers the other slots. Because
+// every inter-workgroup exchange uses device-coherent accesses, the team
+// reduction needs no L2 write-back or invalidation. The arithmetic is the same
+// as the streaming kernel's single-reduction form; halo values are recomputed
+// with the same fused multiply-adds as the owner uses, so both sides see
+// identical bits.
 #pragma once
 
 #include "nh_kernels.hpp"
