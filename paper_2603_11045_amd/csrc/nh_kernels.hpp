@@ -168,9 +168,36 @@ template <> __device__ __forceinline__ double fma_r<double>(double a, double b, 
 template <typename R>
 __device__ __forceinline__ R face(R s, R a, R b) { return s * (a * b) * rcp<R>(a + b); }
 
+// The step kernels stage 1/alpha instead of alpha (a cell outside the grid,
+// read as 0, becomes +inf) and write the face term as s times the face
+// weight 1/(1/a + 1/b) = a*b/(a+b): one addition and one reciprocal per face,
+// and a face towards an absent cell weighs 1/inf = 0.
+template <typename R>
+__device__ __forceinline__ R inv_alpha(R a) { return rcp<R>(a); }
+template <typename R>
+__device__ __forceinline__ R face_w(R ia, R ib) { return rcp<R>(ia + ib); }
+
+// D = 1 + sx (w0 + w1) + sy (w2 + w3) + sz (w4 + w5) and
+// A v = v + sum over the axes of s_d (w_- (v - v_-) + w_+ (v - v_+)), from
+// the face weights w (-x +x -y +y -z +z) and the neighbour values n, every
+// rounding written out: kernels that stage the same values obtain the same
+// bits however each compiles.
+template <typename R>
+__device__ __forceinline__ R diag_w(R sx, R sy, R sz, const R (&w)[6]) {
+  R d = fma_r(sx, add_rn(w[0], w[1]), R(1));
+  d = fma_r(sy, add_rn(w[2], w[3]), d);
+  return fma_r(sz, add_rn(w[4], w[5]), d);
+}
+template <typename R>
+__device__ __forceinline__ R apply_w(R sx, R sy, R sz, const R (&w)[6], R v, const R (&n)[6]) {
+  const R gx = fma_r(w[1], v - n[1], mul_rn(w[0], v - n[0]));
+  const R gy = fma_r(w[3], v - n[3], mul_rn(w[2], v - n[2]));
+  const R gz = fma_r(w[5], v - n[5], mul_rn(w[4], v - n[4]));
+  return fma_r(sz, gz, fma_r(sy, gy, fma_r(sx, gx, v)));
+}
+
 // The diagonal of A: 1 + the six face terms (+ the sink term), summed in this
-// order by every kernel, so that kernels computing the same faces obtain the
-// same bits.
+// order (kernels that take the face terms one by one).
 template <typename R>
 __device__ __forceinline__ R diag_of(R c0, R c1, R c2, R c3, R c4, R c5) {
   return R(1) + (((c0 + c1) + (c2 + c3)) + (c4 + c5));
@@ -356,7 +383,8 @@ __device__ __forceinline__ Coef<R> coef_of(const StepArgs<R>& S) {
   return Coef<R>{S.sx, S.sy, S.sz, S.sb, S.g.nz - 1};
 }
 
-// Stencil values of one cell: index 0 centre, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z.
+// Stencil values of one cell: index 0 centre, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z,
+// 6 +z; a holds 1/alpha (+inf outside the grid).
 template <typename R, int NV>
 struct Pt {
   R a[7];
@@ -482,6 +510,8 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
   for (int j = 0; j < PD; ++j) load_cell(j + 1, T.z0 + j);
   op.stage(ql[0], qv[0]);
   op.stage(ql[1], qv[1]);
+  qa[0] = inv_alpha<R>(qa[0]);
+  qa[1] = inv_alpha<R>(qa[1]);
 
   for (int zb = T.z0; zb < T.z1; zb += Q) {
 #pragma unroll
@@ -506,11 +536,12 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
       if (hslot >= 0) {
         R hv[NV];
         op.stage(hl[s0], hv);
-        la[hslot] = ha[s0];
+        la[hslot] = inv_alpha<R>(ha[s0]);
 #pragma unroll
         for (int k = 0; k < NV; ++k) lv[k][hslot] = hv[k];
       }
       op.stage(ql[sp], qv[sp]);             // plane z+1: the +z neighbour now, staged next
+      qa[sp] = inv_alpha<R>(qa[sp]);
       __syncthreads();
 
       if (own) {
@@ -539,25 +570,22 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
   __syncthreads();                          // both plane buffers are free for the next tile
 }
 
-// A v and the diagonal D of A at one cell, from staged alpha and v (row k of P).
-// A cell of the plane kz carries the Robin sink if kz is the back plane.
+// A v and the diagonal D of A at one cell, from staged 1/alpha and v (row k
+// of P). A cell of the plane kz carries the Robin sink if kz is the back plane.
 template <typename R, int NV>
 __device__ __forceinline__ void stencil(const Pt<R, NV>& P, int k, const Coef<R>& cf, int kz, R& Av, R& D) {
-  const R a = P.a[0];
-  const R c1 = face<R>(cf.sx, a, P.a[1]), c2 = face<R>(cf.sx, a, P.a[2]);
-  const R c3 = face<R>(cf.sy, a, P.a[3]), c4 = face<R>(cf.sy, a, P.a[4]);
-  const R c5 = face<R>(cf.sz, a, P.a[5]), c6 = face<R>(cf.sz, a, P.a[6]);
-  const R sk = kz == cf.zb ? cf.sb : R(0);
-  const R v = P.v[k][0];
-  R s = c1 * (v - P.v[k][1]);
-  s += c2 * (v - P.v[k][2]);
-  s += c3 * (v - P.v[k][3]);
-  s += c4 * (v - P.v[k][4]);
-  s += c5 * (v - P.v[k][5]);
-  s += c6 * (v - P.v[k][6]);
-  s += sk * v;
-  Av = v + s;
-  D = diag_of<R>(c1, c2, c3, c4, c5, c6, sk);
+  R w[6], n[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    w[f] = face_w<R>(P.a[0], P.a[f + 1]);
+    n[f] = P.v[k][f + 1];
+  }
+  Av = apply_w<R>(cf.sx, cf.sy, cf.sz, w, P.v[k][0], n);
+  D = diag_w<R>(cf.sx, cf.sy, cf.sz, w);
+  if (kz == cf.zb && cf.sb != R(0)) {
+    Av = fma_r(cf.sb, P.v[k][0], Av);
+    D = add_rn(D, cf.sb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -704,7 +732,8 @@ struct UpdOp {
 };
 
 // Adjoint epilogue: G_p -= sum_f s_f (a_q/(a_p+a_q))^2 (T_p-T_q)(mu_p-mu_q),
-// s_f = 2 dt / h^2, i.e. G += -dt dc_f/da_p dT dmu (eq. grad_assembly).
+// s_f = 2 dt / h^2, i.e. G += -dt dc_f/da_p dT dmu (eq. grad_assembly); from
+// the staged reciprocals, a_q/(a_p+a_q) = (1/a_p)/(1/a_p + 1/a_q).
 template <typename R>
 struct GradOp {
   static constexpr int PD = kPrefetch - 1;
@@ -721,13 +750,12 @@ struct GradOp {
   __device__ void stage(const R (&r)[2], R (&v)[2]) const { v[0] = r[0]; v[1] = r[1]; }
   __device__ const double* own_ptr(int) const { return G; }
   __device__ void point(const Pt<R, 2>& P, const R (&)[2], const double (&o)[1], long long i, int) {
-    const double a = P.a[0], m = P.v[0][0], t = P.v[1][0];
+    const double ia = P.a[0], m = P.v[0][0], t = P.v[1][0];
     const double s[7] = {0.0, sx, sx, sy, sy, sz, sz};
     double acc = 0.0;
 #pragma unroll
     for (int f = 1; f < 7; ++f) {
-      const double q = P.a[f];
-      const double w = q / (a + q);
+      const double w = ia / (ia + (double)P.a[f]);
       acc += s[f] * (w * w) * ((t - (double)P.v[1][f]) * (m - (double)P.v[0][f]));
     }
     st_out(G + i, o[0] - acc);

@@ -267,38 +267,33 @@ __device__ __forceinline__ void fill_ring(const Geom& g, const ResPos& q, float*
     if (slot[k] >= 0) ring[slot[k]] = v[k];
 }
 
-// Face conductance times dt and the neighbour values of one cell, from the
-// alpha tile in LDS (lz = z + 1 is the cell's plane) and the staged plane.
+// Face weights and the diagonal of one cell, from the 1/alpha tile in LDS
+// (lz = z + 1 is the cell's plane).
 struct Nb {
-  float c[6];                               // -x +x -y +y -z +z
+  float w[6];                               // -x +x -y +y -z +z
   float D;
 };
 
 template <class G>
 __device__ __forceinline__ Nb faces_at(const float* la, const ResPos& q, int z, float sx, float sy, float sz) {
   const float* pl = la + (z + 1) * G::PL + q.oslot;
-  const float a = pl[0];
+  const float ia = pl[0];
   Nb n;
-  n.c[0] = face<float>(sx, a, pl[-1]);
-  n.c[1] = face<float>(sx, a, pl[1]);
-  n.c[2] = face<float>(sy, a, pl[-G::PW]);
-  n.c[3] = face<float>(sy, a, pl[G::PW]);
-  n.c[4] = face<float>(sz, a, pl[-G::PL]);
-  n.c[5] = face<float>(sz, a, pl[G::PL]);
-  n.D = diag_of<float>(n.c[0], n.c[1], n.c[2], n.c[3], n.c[4], n.c[5]);
+  n.w[0] = face_w<float>(ia, pl[-1]);
+  n.w[1] = face_w<float>(ia, pl[1]);
+  n.w[2] = face_w<float>(ia, pl[-G::PW]);
+  n.w[3] = face_w<float>(ia, pl[G::PW]);
+  n.w[4] = face_w<float>(ia, pl[-G::PL]);
+  n.w[5] = face_w<float>(ia, pl[G::PL]);
+  n.D = diag_w<float>(sx, sy, sz, n.w);
   return n;
 }
 
 // A v at one cell given the four in-plane neighbours from LDS and the two z neighbours.
-__device__ __forceinline__ float apply_at(const Nb& n, float v, const float* pl, int oslot, int PW, float vzm,
-                                          float vzp) {
-  float s = n.c[0] * (v - pl[oslot - 1]);
-  s += n.c[1] * (v - pl[oslot + 1]);
-  s += n.c[2] * (v - pl[oslot - PW]);
-  s += n.c[3] * (v - pl[oslot + PW]);
-  s += n.c[4] * (v - vzm);
-  s += n.c[5] * (v - vzp);
-  return v + s;
+__device__ __forceinline__ float apply_at(const Nb& n, float sx, float sy, float sz, float v, const float* pl,
+                                          int oslot, int PW, float vzm, float vzp) {
+  const float nb[6] = {pl[oslot - 1], pl[oslot + 1], pl[oslot - PW], pl[oslot + PW], vzm, vzp};
+  return apply_w<float>(sx, sy, sz, n.w, v, nb);
 }
 
 // Plane-by-plane sweep over the tile for NV staged vectors. own(k, z) gives
@@ -490,20 +485,19 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
 
   // alpha tile with halos: planes z0-1 .. z0+tzn, each (TX+2) x (TY+2),
   // streamed straight into LDS (slot e of the tile <- lane e % 64 of a wave's
-  // load); cells outside the grid are stored as zero
-  {
-    const int n = (q.tzn + 2) * G::PL;
-    for (int e0 = 0; e0 < n; e0 += kResBlock) {
-      const int e = e0 + tid0;
-      if (e < n) {
-        const int lz = e / G::PL, rem = e - lz * G::PL;
-        const int ly = rem / G::PW, lx = rem - ly * G::PW;
-        const int gz = T.z0 - 1 + lz, gxx = T.x0 - 1 + lx, gyy = T.y0 - 1 + ly;
-        if (gz >= 0 && gz < g.nz && gxx >= 0 && gxx < g.nx && gyy >= 0 && gyy < g.ny)
-          __builtin_amdgcn_global_load_lds(S.alpha + gxx + g.nx * gyy + gz * nxy, la + e0 + (tid0 & ~63), 4, 0, 0);
-        else
-          la[e] = 0.f;
-      }
+  // load); cells outside the grid are stored as zero. Once loaded, each
+  // thread replaces its slots by 1/alpha (+inf outside the grid).
+  const int na = (q.tzn + 2) * G::PL;
+  for (int e0 = 0; e0 < na; e0 += kResBlock) {
+    const int e = e0 + tid0;
+    if (e < na) {
+      const int lz = e / G::PL, rem = e - lz * G::PL;
+      const int ly = rem / G::PW, lx = rem - ly * G::PW;
+      const int gz = T.z0 - 1 + lz, gxx = T.x0 - 1 + lx, gyy = T.y0 - 1 + ly;
+      if (gz >= 0 && gz < g.nz && gxx >= 0 && gxx < g.nx && gyy >= 0 && gyy < g.ny)
+        __builtin_amdgcn_global_load_lds(S.alpha + gxx + g.nx * gyy + gz * nxy, la + e0 + (tid0 & ~63), 4, 0, 0);
+      else
+        la[e] = 0.f;
     }
   }
 
@@ -566,12 +560,14 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   // the top source, loaded before the sweep as well
   const float top_q = q.own && T.z0 == 0 ? V.top_src[q.col] : 0.f;
   __builtin_amdgcn_s_waitcnt(0);            // the alpha tile has reached LDS
+  // (a wave's direct loads fill the slots of its own threads)
+  for (int e = tid0; e < na; e += kResBlock) la[e] = inv_alpha<float>(la[e]);
   __syncthreads();
   double acc3[3] = {0.0, 0.0, 0.0};
   plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return xr[z]; }, zlo, zhi,
                  [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                    const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
-                   const float Av = apply_at(n, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
+                   const float Av = apply_at(n, sx, sy, sz, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                    float b = h2 ? br[z] : xr[z];
                    if (T.z0 + z == 0) b += V.top_scale * top_q;
                    const float r = b - Av;
@@ -629,7 +625,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
                    [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                      const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
-                     const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
+                     const float w = apply_at(n, sx, sy, sz, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                      wr[z] = w * rcp<float>(n.D);
                      acc1[0] += (double)ur[z] * (double)w;
                      if (q.edge || z == 0 || z + 1 == q.tzn) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
@@ -657,6 +653,13 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       int col_l = q.col;
       asm volatile("" : "+s"(nxy_l));
       asm volatile("" : "+v"(col_l));
+      // the tile's depth and first plane too: held constant, every plane's
+      // comparisons and offsets would be computed once before the loop and
+      // kept in scalar registers spilled to vector lanes, reloaded per plane
+      ResPos ql = q;
+      int z0_l = T.z0;
+      asm volatile("" : "+s"(ql.tzn));
+      asm volatile("" : "+s"(z0_l));
       const float a = (float)a_cg, b = (float)b_cg;
       const bool first = it == 0;
       // the neighbours' published u, w/D, s/D on the tile's ring are on their
@@ -728,20 +731,20 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       const int pbytes = 4 * nxy_l;
       float xq[kXAhead + 1];
 #pragma unroll
-      for (int z = 0; z < kXAhead; ++z) xq[z] = z < q.tzn ? buf_ld(rx, vown, (T.z0 + z) * pbytes) : 0.f;
-      plane_sweep<G, 1>(g, q, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
+      for (int z = 0; z < kXAhead; ++z) xq[z] = z < ql.tzn ? buf_ld(rx, vown, (z0_l + z) * pbytes) : 0.f;
+      plane_sweep<G, 1>(g, ql, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
                      [&](int z, float* const* pl, const float* vzm, const float* vzp) {
-                       if (z + kXAhead < q.tzn)
-                         xq[(z + kXAhead) % (kXAhead + 1)] = buf_ld(rx, vown, (T.z0 + z + kXAhead) * pbytes);
+                       if (z + kXAhead < ql.tzn)
+                         xq[(z + kXAhead) % (kXAhead + 1)] = buf_ld(rx, vown, (z0_l + z + kXAhead) * pbytes);
                        const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
-                       const float w = apply_at(n, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
+                       const float w = apply_at(n, sx, sy, sz, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                        wr[z] = w * rcp<float>(n.D);
                        const double ud = ur[z], Dd = n.D, rd = Dd * ud;
                        acc[0] += rd * ud;
                        acc[1] += (double)w * ud;
                        acc[2] += rd * rd;
-                       const unsigned vf = (z == 0 || z + 1 == q.tzn) ? vown : vedge;
-                       const int so = (T.z0 + z) * pbytes;
+                       const unsigned vf = (z == 0 || z + 1 == ql.tzn) ? vown : vedge;
+                       const int so = (z0_l + z) * pbytes;
                        buf_st<kCpolSc1>(ru, vf, so, ur[z]);
                        buf_st<kCpolSc1>(rw, vf, so, wr[z]);
                        buf_st<kCpolSc1>(rs_, vf, so, sr[z]);
@@ -790,7 +793,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     }
   }
   if (S.mode == kAdjoint && V.T_grad && ok) {
-    // gradient: G_p -= sum_f s_f (a_q/(a_p+a_q))^2 (T_p-T_q)(mu_p-mu_q)
+    // gradient: G_p -= sum_f s_f (a_q/(a_p+a_q))^2 (T_p-T_q)(mu_p-mu_q),
+    // a_q/(a_p+a_q) = (1/a_p)/(1/a_p + 1/a_q) from the reciprocals in LDS
     float (&mcol)[TZ] = ur;                 // the solve is over: mu and T columns reuse u and p
     float (&tcol)[TZ] = pr;
 #pragma unroll
@@ -820,7 +824,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     plane_sweep<G, 2>(g, q, lp, lring, [&](int k, int z) { return k == 0 ? mcol[z] : tcol[z]; }, glo, ghi,
                    [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                      const float* plz = la + (z + 1) * G::PL + q.oslot;
-                     const double a = plz[0];
+                     const double ia = plz[0];
                      const double m = mcol[z], t = tcol[z];
                      double qa[6], dm[6], dT[6];
                      qa[0] = plz[-1]; qa[1] = plz[1];
@@ -836,7 +840,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                      double gsum = 0.0;
 #pragma unroll
                      for (int f = 0; f < 6; ++f) {
-                       const double w = qa[f] / (a + qa[f]);
+                       const double w = ia / (ia + qa[f]);
                        gsum += sf[f] * (w * w) * (dT[f] * dm[f]);
                      }
                      const int i = q.col + (T.z0 + z) * nxy;

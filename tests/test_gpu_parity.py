@@ -318,11 +318,10 @@ def test_runs_are_bitwise_deterministic():
 @pytest.mark.parametrize("guess", ["adaptive", "projection", "extrapolate"])
 def test_resident_and_streaming_kernels_agree_bitwise(guess):
     """Both FP32 kernels of the single-reduction iteration build the operator
-    from the same rounded face terms (the resident sweep carries each cell's
-    -z face from the plane below rather than recomputing it, and D is summed
-    without fused multiply-adds) and cast the FP64 scalars to FP32: on the same
-    problem, tiled differently, they give identical surface frames, gradient
-    and iteration counts."""
+    from the same staged 1/alpha with every rounding of the face weights, the
+    diagonal and A v written out (no contraction left to the compiler), and
+    cast the FP64 scalars to FP32: on the same problem, tiled differently, they
+    give identical surface frames, gradient and iteration counts."""
     w = wl.small_problem(96, 24, 40, 6, seed=23, dt=4.0, precision="f32", rtol=1e-6)
     gs = wl.random_surface_weights(6, 24, 96, seed=24).astype(np.float32)
     res = run_gpu(w, gs=gs, guess=guess)
