@@ -62,7 +62,8 @@ struct ResRed {
 
 // LDS layout of the resident kernel (bytes).
 constexpr size_t kResAlphaFloats = (size_t)(kResTZ + 2) * kResPlane;   // alpha tile + halos
-constexpr size_t kResPlaneFloats = 4 * (size_t)kResPlane;              // [2 vectors][2 buffers]
+constexpr int kResPZ = 3;                   // planes per barrier in one-vector sweeps
+constexpr size_t kResPlaneFloats = 2 * (size_t)kResPZ * kResPlane;     // [2 sets][kResPZ] or [2 vectors][2]
 constexpr size_t kResRingFloats = 3 * (size_t)kResTZ * kRing;          // [3 vectors][TZ][ring]
 constexpr size_t kResLdsBytes =
     (kResAlphaFloats + kResPlaneFloats + kResRingFloats) * sizeof(float) + sizeof(ResRed) + 64;
@@ -299,9 +300,15 @@ __device__ __forceinline__ float apply_at(const Nb& n, float sx, float sy, float
 // Plane-by-plane sweep over the tile for NV staged vectors. own(k, z) gives
 // the thread's own value of vector k at plane z, ring[k] the LDS ring buffers,
 // zlo/zhi the values below and above the tile; cell(z, plane pointers) does the work.
-template <class G, int NV, typename OwnF, typename RingF, typename CellF>
+// A one-vector sweep stages PZ1 (<= kResPZ) planes per barrier (groups
+// alternate between two sets of plane buffers, so one barrier per group
+// suffices: a set is written again two groups later, after the next group's
+// barrier).
+template <class G, int NV, int PZ1, typename OwnF, typename RingF, typename CellF>
 __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, float* lp, RingF ringv,
                                               OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
+  static_assert(PZ1 >= 1 && PZ1 <= kResPZ, "plane buffers");
+  constexpr int PZ = NV == 1 ? PZ1 : 1;     // planes per barrier
   // ring cells handled by this thread for the plane copy
   // the ring cell this thread copies into the plane: its LDS plane slot, ring
   // slot base and the log2 of the ring slot stride per plane, packed in one
@@ -316,29 +323,44 @@ __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, fl
     hpack = hslot | (rbase << 10) | ((rstride == 64 ? 6 : 3) << 23);
   }
 #pragma unroll
-  for (int z = 0; z < kResTZ; ++z) {
-    if (z < q.tzn) {
-      float* pl[NV];
+  for (int zg = 0; zg < kResTZ; zg += PZ) {
+    if (zg < q.tzn) {
+      float* pl[PZ][NV];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) pl[k] = lp + (size_t)(2 * k + (z & 1)) * kResPlane;
+      for (int j = 0; j < PZ; ++j)
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        pl[k][q.oslot] = q.own ? own(k, z) : 0.f;
-        // (laundered per plane, so that the 32 planes' ring slots are not all
-        // precomputed into registers)
-        int hp = hpack;
-        asm volatile("" : "+v"(hp));
-        if (hp >= 0) pl[k][hp & 1023] = ringv(k, ((hp >> 10) & 8191) + (z << (hp >> 23)));
+        for (int k = 0; k < NV; ++k)
+          pl[j][k] = lp + (size_t)(PZ > 1 ? PZ * ((zg / PZ) & 1) + j : 2 * k + (zg & 1)) * kResPlane;
+#pragma unroll
+      for (int j = 0; j < PZ; ++j) {
+        const int z = zg + j;
+        if (z < kResTZ && (j == 0 || z < q.tzn)) {
+#pragma unroll
+          for (int k = 0; k < NV; ++k) {
+            pl[j][k][q.oslot] = q.own ? own(k, z) : 0.f;
+            // (laundered per plane, so that the 32 planes' ring slots are not all
+            // precomputed into registers)
+            int hp = hpack;
+            asm volatile("" : "+v"(hp));
+            if (hp >= 0) pl[j][k][hp & 1023] = ringv(k, ((hp >> 10) & 8191) + (z << (hp >> 23)));
+          }
+        }
       }
       __syncthreads();
       if (q.own) {
-        float vzm[NV], vzp[NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-          vzm[k] = z == 0 ? zlo[k] : own(k, z > 0 ? z - 1 : 0);
-          vzp[k] = z + 1 == q.tzn ? zhi[k] : own(k, z + 1 < kResTZ ? z + 1 : kResTZ - 1);
+        for (int j = 0; j < PZ; ++j) {
+          const int z = zg + j;
+          if (z < kResTZ && (j == 0 || z < q.tzn)) {
+            float vzm[NV], vzp[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+              vzm[k] = z == 0 ? zlo[k] : own(k, z > 0 ? z - 1 : 0);
+              vzp[k] = z + 1 == q.tzn ? zhi[k] : own(k, z + 1 < kResTZ ? z + 1 : kResTZ - 1);
+            }
+            cell(z, pl[j], vzm, vzp);
+          }
         }
-        cell(z, pl, vzm, vzp);
       }
     }
   }
@@ -346,11 +368,11 @@ __device__ __forceinline__ void plane_sweep_r(const Geom& g, const ResPos& q, fl
 }
 
 // Plane sweep whose halo ring values are stored in LDS (NV ring buffers).
-template <class G, int NV, typename OwnF, typename CellF>
+template <class G, int NV, int PZ1, typename OwnF, typename CellF>
 __device__ __forceinline__ void plane_sweep(const Geom& g, const ResPos& q, float* lp, const float* ring,
                                             OwnF own, const float (&zlo)[2], const float (&zhi)[2], CellF cell) {
-  plane_sweep_r<G, NV>(g, q, lp, [&](int k, int o) { return ring[(size_t)k * kResTZ * kRing + o]; }, own, zlo,
-                       zhi, cell);
+  plane_sweep_r<G, NV, PZ1>(g, q, lp, [&](int k, int o) { return ring[(size_t)k * kResTZ * kRing + o]; }, own,
+                            zlo, zhi, cell);
 }
 
 // Rank of the workgroup owning face neighbour k (-x, +x, -y, +y, -z, +z) of
@@ -435,7 +457,7 @@ __device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* 
 // (dsm: the dynamic LDS of kResLdsBytes). Per-step fields come from V.
 // publish: end with a fenced team barrier, for callers that run further steps
 // in the same launch.
-template <int TXC>
+template <int TXC, int PZ = kResPZ>
 __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, const StepVar<float>& V, int rank,
                                                     unsigned char* dsm, bool publish) {
   using G = RG<TXC>;
@@ -564,7 +586,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   for (int e = tid0; e < na; e += kResBlock) la[e] = inv_alpha<float>(la[e]);
   __syncthreads();
   double acc3[3] = {0.0, 0.0, 0.0};
-  plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return xr[z]; }, zlo, zhi,
+  plane_sweep<G, 1, PZ>(g, q, lp, lring, [&](int, int z) { return xr[z]; }, zlo, zhi,
                  [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                    const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                    const float Av = apply_at(n, sx, sy, sz, xr[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
@@ -622,7 +644,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
     double acc1[1] = {0.0};
     // w0 / D on the tile's faces is published as each plane is done (no
     // global loads in the sweep, so the stores never hold up a wait)
-    plane_sweep<G, 1>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
+    plane_sweep<G, 1, PZ>(g, q, lp, lring, [&](int, int z) { return ur[z]; }, zlo, zhi,
                    [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                      const Nb n = faces_at<G>(la, q, z, sx, sy, sz);
                      const float w = apply_at(n, sx, sy, sz, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
@@ -732,7 +754,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       float xq[kXAhead + 1];
 #pragma unroll
       for (int z = 0; z < kXAhead; ++z) xq[z] = z < ql.tzn ? buf_ld(rx, vown, (z0_l + z) * pbytes) : 0.f;
-      plane_sweep<G, 1>(g, ql, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
+      plane_sweep<G, 1, PZ>(g, ql, lp, ring_u, [&](int, int z) { return ur[z]; }, zlo, zhi,
                      [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                        if (z + kXAhead < ql.tzn)
                          xq[(z + kXAhead) % (kXAhead + 1)] = buf_ld(rx, vown, (z0_l + z + kXAhead) * pbytes);
@@ -821,7 +843,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       ghi[1] = V.T_grad[q.col + T.z1 * nxy];
     }
     __syncthreads();
-    plane_sweep<G, 2>(g, q, lp, lring, [&](int k, int z) { return k == 0 ? mcol[z] : tcol[z]; }, glo, ghi,
+    plane_sweep<G, 2, 1>(g, q, lp, lring, [&](int k, int z) { return k == 0 ? mcol[z] : tcol[z]; }, glo, ghi,
                    [&](int z, float* const* pl, const float* vzm, const float* vzp) {
                      const float* plz = la + (z + 1) * G::PL + q.oslot;
                      const double ia = plz[0];

@@ -222,7 +222,8 @@ __global__ void __launch_bounds__(kResBlock, 1) batch_resident_kernel(const JobR
   if (m.x < 0) return;
   const CJobRun& J = *(const CJobRun*)(jobs + m.x);
   run_slice(J, m, prog, &ss, [&](const StepArgs<float>& S, const StepVar<float>& V) {
-    return resident_step<64>(S, V, m.y, dsm, true);
+    // one plane per barrier: staging more would spill the slice's state
+    return resident_step<64, 1>(S, V, m.y, dsm, true);
   });
 }
 
