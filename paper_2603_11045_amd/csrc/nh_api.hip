@@ -145,6 +145,7 @@ struct nh_ctx {
   // workspaces
   Buf alpha, qxy, z, p0, p1, u1, vw0, vw1, vs0, vs1, traj, seg, slots, steps, flag;
   Buf tvpart;                                // per-workgroup partial sums of the TV regulariser
+  Buf xface;                                 // resident kernel: compact x-edge columns of u, w/D, s/D
   Buf srcq, srcqt;                           // source gradients: dL/dq^n series, q_t on the device
   double* scratch = nullptr;                 // this device's scratch array (nh_tv_noalloc)
   Buf jt[2];                                 // tagged iterates of the blocked fixed-K kernel
@@ -543,6 +544,7 @@ void base_args(nh_ctx* c, StepArgs<R>& S, double dt) {
   S.w1 = (R*)c->vw1.p;
   S.s0 = (R*)c->vs0.p;
   S.s1 = (R*)c->vs1.p;
+  S.xface = (R*)c->xface.p;
   S.variant = c->variant == 0 ? 0 : 1;
   S.jacobi_k = c->jacobi_k;
   S.jtx = c->jac_tb ? c->jtx : 0;
@@ -712,6 +714,10 @@ nh_status ensure_common(nh_ctx* c, int nsteps) {
     NH_TRY(ensure(c, c->vs0, vb));
     NH_TRY(ensure(c, c->vs1, vb));
   }
+  if (sizeof(R) == 4 && c->resident)   // three vectors, two banks
+    NH_TRY(ensure(c, c->xface, sizeof(float) * 2 * (size_t)c->team * nh::kXfTile));
+  else
+    NH_TRY(release(c, c->xface));
   const size_t slot_bytes = sizeof(nh::Slot) * (2 * (size_t)c->team + 2);   // streaming: team + 1; resident: 2 banks
   if (c->slots.bytes < slot_bytes || !c->slots.p) {
     NH_TRY(ensure(c, c->slots, slot_bytes));
@@ -1516,7 +1522,7 @@ void nh_destroy(nh_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   Buf* bufs[] = {&c->trace, &c->alpha, &c->qxy, &c->z, &c->p0, &c->p1, &c->u1, &c->vw0, &c->vw1,
                  &c->vs0, &c->vs1, &c->traj, &c->seg, &c->slots, &c->steps, &c->flag, &c->tvpart, &c->srcq, &c->srcqt,
-                 &c->jt[0], &c->jt[1], &c->pguess, &c->ppart, &c->pstate, &c->dmaxb};
+                 &c->jt[0], &c->jt[1], &c->pguess, &c->ppart, &c->pstate, &c->dmaxb, &c->xface};
   for (Buf* b : bufs) release(c, *b);
   for (Buf& b : c->mu) release(c, b);
   for (Buf& b : c->w) release(c, b);

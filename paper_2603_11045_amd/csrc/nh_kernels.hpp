@@ -90,6 +90,7 @@ struct StepArgs {
   R* w1;
   R* s0;
   R* s1;
+  R* xface;                                 // resident kernel: compact x-edge columns (nh_resident.hpp)
   int variant;                              // 0: two reductions per iteration, 1: one
   int jacobi_k;                             // > 0: K Jacobi sweeps from h1 instead of CG
   int jtx, jty;                             // temporally blocked fixed-K kernel: interior tiles per axis,

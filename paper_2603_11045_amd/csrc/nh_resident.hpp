@@ -10,9 +10,10 @@
 // elementwise updates run in registers, the stencil exchanges in-tile
 // neighbours through LDS one z-plane at a time, and only the values on the
 // tile's faces are published (write-through, device-scope stores) for the
-// neighbouring tiles. A neighbour loads them straight into its LDS halo rings
-// (device-coherent direct loads) as soon as the team reduction that follows
-// shows their slots tagged, while it still gathers the other slots. Because
+// neighbouring tiles, the x-edge columns as compact copies. A neighbour loads
+// them straight into its LDS halo rings (device-coherent direct loads) as soon
+// as the team reduction that follows shows their slots tagged, while it still
+// gathers the other slots. Because
 // every inter-workgroup exchange uses device-coherent accesses, the team
 // reduction needs no L2 write-back or invalidation. The arithmetic is the same
 // as the streaming kernel's single-reduction form; halo values are recomputed
@@ -222,6 +223,8 @@ struct ResPos {
   int oslot;
   bool top_z, bot_z;                        // a tile exists below (z0-1) / above (z1)
   bool edge;                                // column on the tile's x/y boundary
+  bool yedge;                               // column on the tile's y boundary
+  int xside;                                // 0 first, 1 last column of the tile in x, else -1
 };
 
 // Geometry of ring cell h (0 <= h < RING): grid column and LDS plane slot.
@@ -413,6 +416,19 @@ __device__ __forceinline__ ResNeighbours<F> res_neighbours(const Geom& g, int ti
   return ResNeighbours<F>{g, tile, team, xcd, f};
 }
 
+// Compact copies of the tiles' x-edge columns, which the x neighbours load
+// into their halo rings: [bank][tile][side][vector][kResTZ][8] floats, side 0
+// the tile's first column in x, 1 its last, vectors u, w/D, s/D. Eight planes
+// of one column are 64 consecutive floats, one load of a wave (in the vectors
+// themselves consecutive values of a column lie nx floats apart, a cache line
+// each); the offsets of a tile's vectors and planes are constants.
+constexpr int kXfCol = kResTZ * 8;          // floats of one column
+constexpr int kXfTile = 2 * 3 * kXfCol;     // floats per tile and bank
+// column (tile 0, side 0) of vector vec in bank `bank`
+__device__ __forceinline__ float* xface_of(float* xf, int team, int vec, int bank) {
+  return xf + (size_t)bank * team * kXfTile + (size_t)vec * kXfCol;
+}
+
 // Start copying src's values at the tile's ring cells into an LDS ring buffer
 // with direct global-to-LDS loads (device-coherent), without waiting. Each
 // wave issues nine loads of 64 lanes: the -y and +y halo rows of planes w,
@@ -421,10 +437,11 @@ __device__ __forceinline__ ResNeighbours<F> res_neighbours(const Geom& g, int ti
 // landing in 64 consecutive slots of the side-by-side layout. Lanes on cells
 // outside the grid or below the tile's last plane load nothing: their slots
 // must hold zeros already. (Loading the rows 16 bytes per lane, four planes
-// per load, measured slower.)
+// per load, measured slower.) With xsrc the column blocks come from the
+// compact copies of the x neighbours' edge columns.
 template <class G>
 __device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* ring, const float* src, int tid,
-                                         int nxy) {
+                                         int nxy, const float* xsrc = nullptr, int tile = 0) {
   static_assert(G::TX == 64 && G::TY == 8 && kResBlock == 512, "ring loads assume 64 x 8 tiles, 8 waves");
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -448,16 +465,23 @@ __device__ __forceinline__ void ring_dma(const Geom& g, const ResPos& q, float* 
   const bool xp = wave >= 4;
   const int cx = xp ? q.x0 + G::TX : q.x0 - 1;
   const int cz = 8 * b + (lane >> 3), cy = q.y0 + (lane & 7);
-  if (cz < q.tzn && cx >= 0 && cx < g.nx && cy < g.ny)
-    __builtin_amdgcn_global_load_lds(bz + ((long long)cz * nxy + cx + (long long)g.nx * cy),
-                                     ring + (xp ? kRingXp : kRingXm) + 64 * b, 4, 0, kCpolSc1);
+  if (cz < q.tzn && cx >= 0 && cx < g.nx && cy < g.ny) {
+    // from the compact copy: the neighbour's facing column (its first for +x,
+    // its last for -x), planes 8 b .. 8 b + 7, 64 consecutive floats
+    const float* s = xsrc ? xsrc + (size_t)(2 * (xp ? tile + g.ntz : tile - g.ntz) + (xp ? 0 : 1)) * (3 * kXfCol) +
+                                64 * b + lane
+                          : bz + ((long long)cz * nxy + cx + (long long)g.nx * cy);
+    __builtin_amdgcn_global_load_lds(s, ring + (xp ? kRingXp : kRingXm) + 64 * b, 4, 0, kCpolSc1);
+  }
 }
 
 // One implicit-Euler step of one team with the tile's CG state in registers
 // (dsm: the dynamic LDS of kResLdsBytes). Per-step fields come from V.
 // publish: end with a fenced team barrier, for callers that run further steps
-// in the same launch.
-template <int TXC, int PZ = kResPZ>
+// in the same launch. PZ: planes per barrier of the one-vector sweeps; XF: the
+// x-edge columns also go to the compact copies in S.xface (2 * team * kXfTile
+// floats), from which the x neighbours load them (and not from the vectors).
+template <int TXC, int PZ = kResPZ, bool XF = false>
 __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, const StepVar<float>& V, int rank,
                                                     unsigned char* dsm, bool publish) {
   using G = RG<TXC>;
@@ -490,6 +514,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
   q.bot_z = T.z0 > 0;
   q.top_z = T.z1 < g.nz;
   q.edge = q.tx == 0 || q.tx == G::TX - 1 || q.ty == 0 || q.ty == G::TY - 1;
+  q.yedge = XF && (q.ty == 0 || q.ty == G::TY - 1);
+  q.xside = !XF ? -1 : (q.tx == 0 ? 0 : (q.tx == G::TX - 1 ? 1 : -1));
   const float sx = S.sx, sy = S.sy, sz = S.sz;
   const int nxy = (int)g.nxy;
 
@@ -601,11 +627,17 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                    acc3[2] += rd * rd;
                  });
   stamp();
-  // publish u0 on the tile's faces
+  // publish u0 on the tile's faces (x-edge columns: the compact copy)
+  float* const xf = XF ? S.xface : nullptr;
+  const bool fedge = XF ? q.yedge : q.edge;   // face cells stored in the vectors
+  const int xfo = (2 * tile + q.xside) * (3 * kXfCol) + q.ty;   // the column's row, bank 0 vector 0
   if (q.own) {
 #pragma unroll
     for (int z = 0; z < TZ; ++z)
-      if (z < q.tzn && (q.edge || z == 0 || z + 1 == q.tzn)) st_dev(S.z + q.col + (T.z0 + z) * nxy, ur[z]);
+      if (z < q.tzn) {
+        if (fedge || z == 0 || z + 1 == q.tzn) st_dev(S.z + q.col + (T.z0 + z) * nxy, ur[z]);
+        if (XF && q.xside >= 0) st_dev(xface_of(xf, S.team, 0, 0) + xfo + 8 * z, ur[z]);
+      }
   }
   // the neighbours' u0 faces start loading into the u ring as soon as their
   // slots show that they are published (the set-up's x0 values there are used)
@@ -613,7 +645,10 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                           int tid_l = threadIdx.x, nxy_l = nxy;
                           asm volatile("" : "+v"(tid_l));
                           asm volatile("" : "+s"(nxy_l));
-                          ring_dma<G>(g, q, lring, S.z, tid_l, nxy_l);
+                          if constexpr (XF)
+                            ring_dma<G>(g, q, lring, S.z, tid_l, nxy_l, xface_of(xf, S.team, 0, 0), tile);
+                          else
+                            ring_dma<G>(g, q, lring, S.z, tid_l, nxy_l);
                         }));
   stamp();
   const double bb = acc3[0];
@@ -650,7 +685,8 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                      const float w = apply_at(n, sx, sy, sz, ur[z], pl[0], q.oslot, G::PW, vzm[0], vzp[0]);
                      wr[z] = w * rcp<float>(n.D);
                      acc1[0] += (double)ur[z] * (double)w;
-                     if (q.edge || z == 0 || z + 1 == q.tzn) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
+                     if (fedge || z == 0 || z + 1 == q.tzn) st_dev(wb[0] + q.col + (T.z0 + z) * nxy, wr[z]);
+                     if (XF && q.xside >= 0) st_dev(xface_of(xf, S.team, 1, 0) + xfo + 8 * z, wr[z]);
                    });
     stamp();
     // the first iteration's halo rings (u0, w0/D; no s yet) start loading as
@@ -662,7 +698,11 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                             int tid_l = threadIdx.x, nxy_l = nxy;
                             asm volatile("" : "+v"(tid_l));
                             asm volatile("" : "+s"(nxy_l));
-                            ring_dma<G>(g, q, ring_w, wb[0], tid_l, nxy_l);   // u0 is in ring_u already
+                            // (u0 is in ring_u already)
+                            if constexpr (XF)
+                              ring_dma<G>(g, q, ring_w, wb[0], tid_l, nxy_l, xface_of(xf, S.team, 1, 0), tile);
+                            else
+                              ring_dma<G>(g, q, ring_w, wb[0], tid_l, nxy_l);
                           }));
     stamp();
     double a_cg = gam / acc1[0], b_cg = 0.0;
@@ -749,7 +789,12 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
       const __amdgpu_buffer_rsrc_t rx = vec_rsrc(V.x, g.ng);
       const __amdgpu_buffer_rsrc_t ru = vec_rsrc(uo_n, g.ng), rw = vec_rsrc(wo_n, g.ng), rs_ = vec_rsrc(so_n, g.ng);
       const unsigned vown = q.own ? 4u * (unsigned)col_l : kNoLane;
-      const unsigned vedge = q.own && q.edge ? 4u * (unsigned)col_l : kNoLane;
+      const unsigned vedge = q.own && fedge ? 4u * (unsigned)col_l : kNoLane;
+      // the compact x-edge columns of this iteration's bank: a lane offset on
+      // the x-edge columns, constant offsets per vector and plane
+      const __amdgpu_buffer_rsrc_t rxf = vec_rsrc(xf, XF ? 2LL * S.team * kXfTile : 0);
+      const unsigned vxf =
+          XF && q.own && q.xside >= 0 ? 4u * (unsigned)(xfo + (cur ^ 1) * S.team * kXfTile) : kNoLane;
       const int pbytes = 4 * nxy_l;
       float xq[kXAhead + 1];
 #pragma unroll
@@ -770,6 +815,11 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                        buf_st<kCpolSc1>(ru, vf, so, ur[z]);
                        buf_st<kCpolSc1>(rw, vf, so, wr[z]);
                        buf_st<kCpolSc1>(rs_, vf, so, sr[z]);
+                       if (XF) {
+                         buf_st<kCpolSc1>(rxf, vxf, 32 * z, ur[z]);
+                         buf_st<kCpolSc1>(rxf, vxf, 4 * kXfCol + 32 * z, wr[z]);
+                         buf_st<kCpolSc1>(rxf, vxf, 8 * kXfCol + 32 * z, sr[z]);
+                       }
                        const float xn = fmaf(a, pr[z], xq[z % (kXAhead + 1)]);
                        buf_st(rx, vown, so, xn);
                        if (z == 0) xtop = xn;
@@ -782,9 +832,15 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
                               int tid_r = threadIdx.x, nxy_r = nxy;
                               asm volatile("" : "+v"(tid_r));
                               asm volatile("" : "+s"(nxy_r));
-                              ring_dma<G>(g, q, ring_u, uo_n, tid_r, nxy_r);
-                              ring_dma<G>(g, q, ring_w, wo_n, tid_r, nxy_r);
-                              ring_dma<G>(g, q, ring_s, so_n, tid_r, nxy_r);
+                              if constexpr (XF) {
+                                ring_dma<G>(g, q, ring_u, uo_n, tid_r, nxy_r, xface_of(xf, S.team, 0, cur ^ 1), tile);
+                                ring_dma<G>(g, q, ring_w, wo_n, tid_r, nxy_r, xface_of(xf, S.team, 1, cur ^ 1), tile);
+                                ring_dma<G>(g, q, ring_s, so_n, tid_r, nxy_r, xface_of(xf, S.team, 2, cur ^ 1), tile);
+                              } else {
+                                ring_dma<G>(g, q, ring_u, uo_n, tid_r, nxy_r);
+                                ring_dma<G>(g, q, ring_w, wo_n, tid_r, nxy_r);
+                                ring_dma<G>(g, q, ring_s, so_n, tid_r, nxy_r);
+                              }
                             }));
       stamp();
       ++it;
@@ -895,7 +951,7 @@ __device__ __forceinline__ StepResult resident_step(const StepArgs<float>& S, co
 template <int TXC>
 __global__ void __launch_bounds__(kResBlock, 1) resident_step_kernel(StepArgs<float> S) {
   extern __shared__ __align__(16) unsigned char dsm[];
-  resident_step<TXC>(S, step_var(S), blockIdx.x, dsm, false);
+  resident_step<TXC, kResPZ, true>(S, step_var(S), blockIdx.x, dsm, false);
 }
 
 }  // namespace nh
