@@ -113,7 +113,9 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
   __syncthreads();
   const StepArgs<float>& S = (const StepArgs<float>&)J.S;
   while (true) {
-    const int n = ss->n;
+    // (wave-uniform: the step's pointers below then live in scalar registers,
+    // which leaves the step the vector registers of three planes per barrier)
+    const int n = __builtin_amdgcn_readfirstlane(ss->n);
     const int k = pos(n) % kGuessPeriod;
     const long long ng = J.S.g.ng, nxy = J.S.g.nxy;
     StepVar<float> V;
@@ -147,7 +149,8 @@ __device__ __forceinline__ void run_slice(const CJobRun& J, int2 m, JobProg* pro
     if (k < 3) {
       order = k;
     } else {
-      const int p0 = ss->pc[0], p1 = ss->pc[1], p2 = ss->pc[2];
+      const int p0 = __builtin_amdgcn_readfirstlane(ss->pc[0]), p1 = __builtin_amdgcn_readfirstlane(ss->pc[1]),
+                p2 = __builtin_amdgcn_readfirstlane(ss->pc[2]);
       if (p0 >= 0 && p1 >= 0 && p2 >= 0) {
         int best = p2;
         if (p1 < best) { order = 1; best = p1; }
@@ -222,8 +225,9 @@ __global__ void __launch_bounds__(kResBlock, 1) batch_resident_kernel(const JobR
   if (m.x < 0) return;
   const CJobRun& J = *(const CJobRun*)(jobs + m.x);
   run_slice(J, m, prog, &ss, [&](const StepArgs<float>& S, const StepVar<float>& V) {
-    // one plane per barrier: staging more would spill the slice's state
-    return resident_step<64, 1>(S, V, m.y, dsm, true);
+    // three planes per barrier; the x-edge columns from the vectors (the
+    // compact copies would spill the slice's state)
+    return resident_step<64, 3>(S, V, m.y, dsm, true);
   });
 }
 
