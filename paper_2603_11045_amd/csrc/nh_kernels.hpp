@@ -24,11 +24,11 @@
 // sweep and one team reduction per iteration).
 //
 // The stencil is evaluated by marching a 2-D tile of (x, y) columns along z:
-// each z plane of the staged vectors and of alpha, with its one-cell halo in
+// each z plane of the staged vectors and of 1/alpha, with its one-cell halo in
 // x and y, goes through LDS with x-contiguous (coalesced) loads, while the
 // +-z neighbours of a column stay in registers. Cells outside the grid read
-// alpha = 0, which makes their harmonic-mean conductance 0: the zero-flux
-// boundary needs no special case.
+// alpha = 0, staged as 1/alpha = +inf, which makes their harmonic-mean
+// conductance 0: the zero-flux boundary needs no special case.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -230,7 +230,7 @@ __device__ __forceinline__ double ld_val(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Shared state of one workgroup: two buffers of a staged plane (alpha and up
+// Shared state of one workgroup: two buffers of a staged plane (1/alpha and up
 // to two vectors; march_tile alternates them), and red, two buffers of
 // per-wave partial sums, which the two block sums of a team reduction use in
 // turn.
@@ -482,9 +482,9 @@ __device__ __forceinline__ void march_tile(const Geom& g, const Tile& T, Op& op,
   const unsigned vown = own ? (unsigned)col * (unsigned)sizeof(OT) : kOffLane;
 
   // rings; plane zp sits in slot (zp - (z0 - 1)) mod Q
-  R qa[Q], ql[Q][NL];                       // staged column: alpha, raw values
+  R qa[Q], ql[Q][NL];                       // staged column: alpha (1/alpha once staged), raw values
   R qv[Q][NV];                              // staged column: staged vectors
-  R ha[Q], hl[Q][NL];                       // halo cell: alpha, raw values
+  R ha[Q], hl[Q][NL];                       // halo cell: alpha, raw values (staged as 1/alpha)
   OT qo[Q][NO];                             // own operands
   // staged column of plane zp (inside the grid)
   auto load_col = [&](int s, int zp) {

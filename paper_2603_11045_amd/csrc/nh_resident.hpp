@@ -4,21 +4,21 @@
 // columns of at most kResTZ cells), the CG state of a tile -- p, u = r/D,
 // A u / D and A p / D, the vectors of the single-reduction iteration of
 // nh_kernels.hpp -- stays in the registers of the workgroup that owns the tile
-// for the whole time step, and alpha stays in LDS. Only x, which no neighbour
+// for the whole time step, and 1/alpha stays in LDS. Only x, which no neighbour
 // reads during the solve, is updated in place in memory inside each
 // iteration's sweep (8 bytes per cell and iteration, coalesced, no halo). The
 // elementwise updates run in registers, the stencil exchanges in-tile
-// neighbours through LDS one z-plane at a time, and only the values on the
-// tile's faces are published (write-through, device-scope stores) for the
-// neighbouring tiles, the x-edge columns as compact copies. A neighbour loads
-// them straight into its LDS halo rings (device-coherent direct loads) as soon
-// as the team reduction that follows shows their slots tagged, while it still
-// gathers the other slots. Because
-// every inter-workgroup exchange uses device-coherent accesses, the team
-// reduction needs no L2 write-back or invalidation. The arithmetic is the same
-// as the streaming kernel's single-reduction form; halo values are recomputed
-// with the same fused multiply-adds as the owner uses, so both sides see
-// identical bits.
+// neighbours through LDS a few z-planes per workgroup barrier, and only the
+// values on the tile's faces are published (write-through, device-scope
+// stores) for the neighbouring tiles, in the single-problem kernel the x-edge
+// columns as compact copies. A neighbour loads them straight into its LDS halo
+// rings (device-coherent direct loads) as soon as the team reduction that
+// follows shows their slots tagged, while it still gathers the other slots.
+// Because every inter-workgroup exchange uses device-coherent accesses, the
+// team reduction needs no L2 write-back or invalidation. The arithmetic is the
+// same as the streaming kernel's single-reduction form; halo values are
+// recomputed with the same fused multiply-adds as the owner uses, so both
+// sides see identical bits.
 #pragma once
 
 #include "nh_kernels.hpp"
@@ -223,8 +223,8 @@ struct ResPos {
   int oslot;
   bool top_z, bot_z;                        // a tile exists below (z0-1) / above (z1)
   bool edge;                                // column on the tile's x/y boundary
-  bool yedge;                               // column on the tile's y boundary
-  int xside;                                // 0 first, 1 last column of the tile in x, else -1
+  bool yedge;                               // with compact x-edge columns: column on the y boundary
+  int xside;                                //   and 0 first, 1 last column in x, else -1
 };
 
 // Geometry of ring cell h (0 <= h < RING): grid column and LDS plane slot.
